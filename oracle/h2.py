@@ -1,0 +1,149 @@
+"""The H2 matrix and its matvec, by their plain definitions (oracle).
+
+Paper: Section 3.1.  A = D + F with D the close blocks and
+F = U_1 S_1 V_1 (eq. h20), and the coupling matrix of each level split again
+as S_{k-1} = D_k + U_k S_k V_k (eq. s1) down to the last level (eq. h2).  The
+matvec recursion that follows eq. h2 (x_i = V_i x_{i-1} upward,
+y_{i-1} = D_i x_{i-1} + U_i y_i downward, y = D x + U_1 y_1) computes, up to
+rounding, exactly the product with the matrix
+
+    A_H2 = sum over close leaf pairs (s, t) of   K[I_s, I_t]
+         + sum over far pairs (s, t), any depth,  U_s S_st U_t^T
+
+where U_s is the cluster basis of s evaluated directly at its points (the
+nested bases reproduce it exactly, see cheb.py).  So the oracle multiplies by
+that sum, block by block, with direct (non-nested, non-orthogonalised) bases.
+
+Readings: the symmetric case V_i = U_i^T (one tree for rows and columns);
+the garbled "S_i x_i" term of the recursion is read as the level's
+interaction-list couplings D_{i+1} x_i (the recursion's own definition
+y_{i-1} = D_i x_{i-1} + U_i y_i is taken as authoritative).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import cheb
+from .kernels import kernel_matrix, make_kernel
+from .partition import build_partition
+from .tree import build_tree
+
+
+class H2:
+    """Direct-basis H2 approximation of a kernel matrix.
+
+    `kern` is a callable k(X, Y) (see kernels.py) or a kind name.  Vectors
+    passed to the public methods are in user order.
+    """
+
+    def __init__(self, points, kern, shift, leaf, eta, m, length_scale=None):
+        if isinstance(kern, str):
+            kern = make_kernel(kern, length_scale)
+        self.kern = kern
+        self.shift = float(shift)
+        self.points = np.asarray(points, dtype=np.float64)
+        self.n, self.dim = self.points.shape
+        self.m = int(m)
+        self.r = self.m ** self.dim
+        self.tree = build_tree(self.points, leaf)
+        self.part = build_partition(self.tree, eta)
+        self.L = self.tree.L
+        self.P = self.points[self.tree.perm]          # tree-ordered points
+        floor = cheb.width_floor(self.tree)
+        self.c, self.h = [], []
+        for d in range(self.L + 1):
+            c, h = cheb.box_frame(self.tree.lo[d], self.tree.hi[d], floor)
+            self.c.append(c)
+            self.h.append(h)
+        self._U = {}
+
+    # ---- pieces -------------------------------------------------------
+    @property
+    def d_top(self):
+        return self.part.d_top
+
+    def rows(self, d, j):
+        return self.tree.rows(d, j)
+
+    def basis(self, d, j) -> np.ndarray:
+        """Direct cluster basis U_s (n_s x r) of cluster j at depth d."""
+        key = (d, j)
+        if key not in self._U:
+            X = self.P[self.rows(d, j)]
+            self._U[key] = cheb.tensor_eval(X, self.c[d][j], self.h[d][j], self.m)
+        return self._U[key]
+
+    def nodes(self, d, j) -> np.ndarray:
+        return cheb.cluster_nodes(self.c[d][j], self.h[d][j], self.m)
+
+    def coupling(self, d, s, t) -> np.ndarray:
+        return cheb.coupling(self.kern, self.nodes(d, s), self.nodes(d, t))
+
+    def transfer(self, d, j) -> np.ndarray:
+        """E_c for child j at depth d (d >= 1) to its parent j // 2."""
+        p = j // 2
+        return cheb.transfer(self.c[d][j], self.h[d][j],
+                             self.c[d - 1][p], self.h[d - 1][p], self.m)
+
+    def near_block(self, s, t) -> np.ndarray:
+        """Close leaf block K[I_s, I_t] (shift on the diagonal when s == t)."""
+        Xs = self.P[self.rows(self.L, s)]
+        if s == t:
+            return kernel_matrix(self.kern, Xs, self.shift)
+        Xt = self.P[self.rows(self.L, t)]
+        return kernel_matrix(self.kern, Xs, self.shift, Xt)
+
+    # ---- products -----------------------------------------------------
+    def matvec_tree(self, xt: np.ndarray) -> np.ndarray:
+        """y = A_H2 x with x, y in tree order (blockwise definition)."""
+        xt = np.asarray(xt, dtype=np.float64)
+        y = np.zeros_like(xt)
+        L = self.L
+        for s, t in self.part.near[L]:
+            y[self.rows(L, s)] += self.near_block(s, t) @ xt[self.rows(L, t)]
+        for d in range(L + 1):
+            far = self.part.far[d]
+            if far.shape[0] == 0:
+                continue
+            xhat = {}
+            yhat = {}
+            for s, t in far:
+                if t not in xhat:
+                    xhat[t] = self.basis(d, t).T @ xt[self.rows(d, t)]
+                yhat[s] = yhat.get(s, 0.0) + self.coupling(d, s, t) @ xhat[t]
+            for s, v in yhat.items():
+                y[self.rows(d, s)] += self.basis(d, s) @ v
+        return y
+
+    def matvec(self, x: np.ndarray) -> np.ndarray:
+        """y = A_H2 x in user order."""
+        x = np.asarray(x, dtype=np.float64)
+        perm = self.tree.perm
+        yt = self.matvec_tree(x[perm])
+        y = np.empty_like(yt)
+        y[perm] = yt
+        return y
+
+    def dense_tree(self) -> np.ndarray:
+        """A_H2 as a dense matrix in tree order (small N only)."""
+        A = np.zeros((self.n, self.n))
+        L = self.L
+        for s, t in self.part.near[L]:
+            A[self.rows(L, s), self.rows(L, t)] = self.near_block(s, t)
+        for d in range(L + 1):
+            for s, t in self.part.far[d]:
+                A[self.rows(d, s), self.rows(d, t)] = (
+                    self.basis(d, s) @ self.coupling(d, s, t) @ self.basis(d, t).T)
+        return A
+
+    def dense(self) -> np.ndarray:
+        """A_H2 as a dense matrix in user order."""
+        At = self.dense_tree()
+        perm = self.tree.perm
+        A = np.empty_like(At)
+        A[np.ix_(perm, perm)] = At
+        return A
+
+    def kernel_dense(self) -> np.ndarray:
+        """The exact kernel matrix K in user order (small N only)."""
+        return kernel_matrix(self.kern, self.points, self.shift)

@@ -1,0 +1,94 @@
+"""The H2-MG V-cycle (Algorithm 1) and repeated cycles (oracle).
+
+Paper: Section 3.3, Algorithm 1:
+    r_1 = b - A_1 x_0
+    for i = 1 .. l-1:  e~_i = Iter(A_i, r_i, 0);  r_{i+1} = U_i^T (r_i - A_i e~_i)
+    e_l = dir_sol(A_l, r_l)                      (Cholesky)
+    for i = l-1 .. 1:  e~_i = e~_i + V_i^T e_{i+1};  e_i = Iter(A_i, r_i, e~_i)
+    x* = x_0 + e_1
+and successive V-cycles restart from x*.  Iter uses n_f CG steps on the
+finest level and n_c on the others (Remark on fine and coarse iterations).
+
+Readings:
+* restriction U_i^T and prolongation V_i^T = U_i (symmetric case), i.e. the
+  transposed and plain level transfers P_i of galerkin.py;
+* the residual r_i - A_i e~_i is formed explicitly (one product);
+* both pre- and post-smoothing use n_f steps on level 1 and n_c elsewhere;
+* outer loop: x_0 = 0; before each cycle the FP64 residual b - A_H2 x is
+  measured and the loop stops when ||b - A_H2 x|| / ||b|| < rtol
+  (rtol = 1e-8) or after max_cycles cycles.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import scipy.linalg
+
+from .cg import cg
+
+
+@dataclasses.dataclass
+class SolveResult:
+    x: np.ndarray
+    cycles: int
+    converged: bool
+    history: list          # relative residual before each cycle, and at exit
+
+
+def coarsest_factor(A: np.ndarray):
+    return scipy.linalg.cho_factor(A, lower=True)
+
+
+def vcycle(H, x0: np.ndarray, b: np.ndarray, n_f: int = 1, n_c: int = 40,
+           factor=None, r1=None) -> np.ndarray:
+    """One V-cycle of Algorithm 1 on the dense hierarchy H (tree order)."""
+    ops, P = H.ops, H.prolong
+    l = len(ops)
+    if factor is None:
+        factor = coarsest_factor(ops[-1])
+    r = [None] * l
+    et = [None] * l
+    r[0] = b - ops[0] @ x0 if r1 is None else r1
+    for i in range(l - 1):
+        n = n_f if i == 0 else n_c
+        apply = ops[i].__matmul__
+        et[i] = cg(apply, r[i], None, n)
+        r[i + 1] = P[i].T @ (r[i] - apply(et[i]))
+    e = scipy.linalg.cho_solve(factor, r[l - 1])
+    for i in range(l - 2, -1, -1):
+        n = n_f if i == 0 else n_c
+        et[i] = et[i] + P[i] @ e
+        e = cg(ops[i].__matmul__, r[i], et[i], n)
+    return x0 + e
+
+
+def solve(H, b: np.ndarray, rtol: float = 1e-8, max_cycles: int = 500,
+          n_f: int = 1, n_c: int = 40, x0=None) -> SolveResult:
+    """Repeated V-cycles on A_H2 x = b (b and x in tree order)."""
+    A = H.ops[0]
+    factor = coarsest_factor(H.ops[-1])
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    nb = float(np.linalg.norm(b))
+    hist = []
+    if nb == 0.0:
+        return SolveResult(np.zeros_like(b), 0, True, [0.0])
+    for cyc in range(max_cycles + 1):
+        res = b - A @ x
+        rel = float(np.linalg.norm(res)) / nb
+        hist.append(rel)
+        if rel < rtol:
+            return SolveResult(x, cyc, True, hist)
+        if cyc == max_cycles:
+            break
+        x = vcycle(H, x, b, n_f, n_c, factor, r1=res)
+    return SolveResult(x, max_cycles, False, hist)
+
+
+def solve_user(h2, H, b_user: np.ndarray, **kw) -> SolveResult:
+    """solve() with b and x in user order."""
+    perm = h2.tree.perm
+    res = solve(H, np.asarray(b_user, dtype=np.float64)[perm], **kw)
+    x = np.empty_like(res.x)
+    x[perm] = res.x
+    return dataclasses.replace(res, x=x)

@@ -1,0 +1,18 @@
+"""Shared pytest configuration.
+
+Tests marked `gpu` need an MI355X and the built HIP library; everything else
+runs on the CPU (oracle pins, host structure logic, library loading).
+"""
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: CPU test that takes more than ~20 s")

@@ -1,0 +1,186 @@
+"""Pins of the oracle's restricted operators, CG smoother, V-cycle and
+iterative refinement.
+
+Independent references: plain dense Galerkin products, Cauchy interlacing,
+the blockwise form of eq. a2_str, scipy's CG, dense Cholesky solves, Galerkin
+orthogonality of an exact two-grid correction, monotone A-norm error, and
+torch's float32 -> bfloat16 conversion.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg
+import torch
+
+import synth
+from oracle.cg import NotSPD, cg
+from oracle.galerkin import Hierarchy, galerkin
+from oracle.h2 import H2
+from oracle.ir import ir_solve, round_bf16, round_fp32
+from oracle.ortho import coarse_basis, qr_pos
+from oracle.vcycle import coarsest_factor, solve, vcycle
+
+
+@pytest.fixture(scope="module")
+def small():
+    P = synth.uniform_points(777, 2, 5)
+    h = H2(P, "exp", 1e-2, 24, 0.7, 3, 0.1)
+    return h, Hierarchy(h)
+
+
+# ---------------------------------------------------------------- Galerkin
+def test_blockwise_galerkin_equals_dense_product(small):
+    h, H = small
+    A = H.ops[0]
+    for d in (h.L, h.d_top):
+        W = coarse_basis(h, d)
+        np.testing.assert_allclose(galerkin(A, W, h.tree.offsets[d], h.r), W.T @ A @ W,
+                                   rtol=1e-12, atol=1e-12 * np.abs(A).max())
+
+
+def test_coarse_operators_interlace_and_nest(small):
+    h, H = small
+    ev = np.linalg.eigvalsh(H.ops[0])
+    for k in range(1, H.levels):
+        Ak = H.ops[k]
+        assert np.abs(Ak - Ak.T).max() <= 1e-12 * np.abs(Ak).max()
+        evk = np.linalg.eigvalsh(0.5 * (Ak + Ak.T))
+        assert evk[0] >= ev[0] * (1 - 1e-10) and evk[-1] <= ev[-1] * (1 + 1e-10)
+        if k + 1 < H.levels:
+            Pk = H.prolong[k]
+            np.testing.assert_allclose(Pk.T @ Ak @ Pk, H.ops[k + 1],
+                                       atol=1e-11 * np.abs(Ak).max())
+
+
+def test_first_restricted_operator_blocks_follow_eq_a2_str(small):
+    """A_2 = U_1^T D U_1 + D_2 + ...: its close-pair blocks are Q_s^T K_st Q_t
+    and its depth-L interaction-list blocks are R_s S_st R_t^T."""
+    h, H = small
+    A2 = H.ops[1]
+    r, L = h.r, h.L
+    for s, t in h.part.near[L][::37].tolist():
+        Qs = qr_pos(h.basis(L, s))[0]
+        Qt = qr_pos(h.basis(L, t))[0]
+        np.testing.assert_allclose(A2[s * r:(s + 1) * r, t * r:(t + 1) * r],
+                                   Qs.T @ h.near_block(s, t) @ Qt, atol=1e-12)
+    for s, t in h.part.far[L][::29].tolist():
+        Rs = qr_pos(h.basis(L, s))[1]
+        Rt = qr_pos(h.basis(L, t))[1]
+        np.testing.assert_allclose(A2[s * r:(s + 1) * r, t * r:(t + 1) * r],
+                                   Rs @ h.coupling(L, s, t) @ Rt.T, atol=1e-12)
+
+
+# ---------------------------------------------------------------- CG
+def _spd(n, seed, cond=1e3):
+    rng = np.random.default_rng(seed)
+    Q = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    return (Q * np.geomspace(1, cond, n)) @ Q.T
+
+
+def test_cg_exact_in_n_steps_and_first_step():
+    A = _spd(8, 0, cond=10.0)
+    r = synth.normal_vector(8, 1)
+    e = cg(A.__matmul__, r, None, 8)
+    np.testing.assert_allclose(e, np.linalg.solve(A, r), rtol=1e-9)
+    e1 = cg(A.__matmul__, r, None, 1)
+    np.testing.assert_allclose(e1, (r @ r) / (r @ A @ r) * r, rtol=1e-14)
+
+
+def test_cg_matches_scipy_and_is_monotone_in_a_norm():
+    A = _spd(60, 2, 1e4)
+    b = synth.normal_vector(60, 3)
+    e0 = synth.normal_vector(60, 4)
+    xs = np.linalg.solve(A, b)
+    prev = np.inf
+    for n in (1, 3, 8, 20):
+        e = cg(A.__matmul__, b, e0, n)
+        ref, _ = scipy.sparse.linalg.cg(A, b, x0=e0, rtol=0.0, atol=0.0, maxiter=n)
+        np.testing.assert_allclose(e, ref, rtol=1e-9, atol=1e-12)
+        err = np.sqrt((e - xs) @ A @ (e - xs))
+        assert err <= prev
+        prev = err
+
+
+def test_cg_zero_rhs_and_breakdown():
+    A = _spd(5, 0)
+    np.testing.assert_array_equal(cg(A.__matmul__, np.zeros(5), None, 3), 0.0)
+    with pytest.raises(NotSPD):
+        cg(np.diag([1.0, -1.0, 2.0]).__matmul__, np.array([0.0, 1.0, 0.0]), None, 2)
+
+
+# ---------------------------------------------------------------- V-cycle
+def test_single_level_is_a_direct_solve():
+    P = synth.uniform_points(400, 2, 1)
+    h = H2(P, "exp", 1e-2, 16, 1e-9, 3, 0.1)
+    H = Hierarchy(h)
+    assert H.levels == 1
+    b = synth.normal_vector(400, 2)
+    res = solve(H, b)
+    assert res.cycles == 1 and res.history[-1] < 1e-13
+
+
+def test_two_grid_correction_is_galerkin_orthogonal(small):
+    """Exact coarse solve, no smoothing: U_1^T (b - A x*) = 0."""
+    h, H = small
+    H2lvl = Hierarchy.__new__(Hierarchy)
+    H2lvl.h2, H2lvl.ops, H2lvl.prolong = h, H.ops[:2], H.prolong[:1]
+    b = synth.normal_vector(h.n, 6)
+    x = vcycle(H2lvl, np.zeros(h.n), b, n_f=0, n_c=0)
+    res = H.prolong[0].T @ (b - H.ops[0] @ x)
+    assert np.linalg.norm(res) <= 1e-12 * np.linalg.norm(b) * np.linalg.cond(H.ops[1])
+
+
+def test_vcycle_error_monotone_and_converges_to_cholesky(small):
+    h, H = small
+    A = H.ops[0]
+    b = synth.normal_vector(h.n, 8)
+    xs = np.linalg.solve(A, b)
+    fac = coarsest_factor(H.ops[-1])
+    x = np.zeros(h.n)
+    prev = np.inf
+    for _ in range(6):
+        x = vcycle(H, x, b, 1, 40, fac)
+        err = np.sqrt((x - xs) @ A @ (x - xs))
+        assert err <= prev * (1 + 1e-12)
+        prev = err
+    res = solve(H, b, rtol=1e-8)
+    assert res.converged and res.history[-1] < 1e-8
+    kappa = np.linalg.cond(A)
+    assert np.linalg.norm(res.x - xs) <= kappa * 1e-8 * np.linalg.norm(xs)
+
+
+def test_vcycle_is_affine_in_initial_guess(small):
+    """x* = x0 + (V-cycle correction of the residual b - A x0)."""
+    h, H = small
+    b = synth.normal_vector(h.n, 9)
+    x0 = synth.normal_vector(h.n, 10)
+    a = vcycle(H, x0, b)
+    c = x0 + vcycle(H, np.zeros(h.n), b - H.ops[0] @ x0)
+    np.testing.assert_allclose(a, c, rtol=1e-9, atol=1e-9 * np.linalg.norm(a))
+
+
+# ---------------------------------------------------------------- refinement
+def test_bf16_and_fp32_rounding_match_torch():
+    x = synth.normal_vector(4096, 12) * np.geomspace(1e-6, 1e6, 4096)
+    x32 = x.astype(np.float32).astype(np.float64)                # exact in fp32
+    ref = torch.from_numpy(x32).to(torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(round_bf16(x32), ref)
+    np.testing.assert_array_equal(round_fp32(x), x.astype(np.float32))
+
+
+def test_fp64_refinement_is_the_plain_iteration(small):
+    h, H = small
+    b = synth.normal_vector(h.n, 13)
+    a = solve(H, b, rtol=1e-10)
+    c = ir_solve(H, b, "fp64", rtol=1e-10)
+    assert a.cycles == c.cycles
+    np.testing.assert_allclose(a.history, c.history, rtol=1e-6)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_refinement_fixed_point_is_the_fp64_solution(small, prec):
+    h, H = small
+    b = synth.normal_vector(h.n, 14)
+    res = ir_solve(H, b, prec, rtol=1e-8)
+    A = H.ops[0]
+    assert res.converged
+    assert np.linalg.norm(b - A @ res.x) < 1e-8 * np.linalg.norm(b)
