@@ -1,0 +1,224 @@
+/*
+ * h2mg.h -- C ABI of the MI355X H2 matrix and H2-MG solver library.
+ *
+ * The library builds an H2 approximation A_H2 of a dense SPD kernel matrix
+ * A_ij = k(|p_i - p_j|) (+ shift on the diagonal) from points and a kernel,
+ * multiplies by it, and solves A_H2 x = b by the H2-MG V-cycle.
+ *
+ * Paper: Sushnikova, Turkiyyah, Chow, Keyes, "H2-MG: A multigrid method for
+ * hierarchical rank structured matrices".
+ *   - H2 representation and matvec: Section 3.1 (eq. f, eq. h20, eq. s1,
+ *     eq. h2, and the matvec recursion that follows eq. h2).
+ *   - Restricted operators: Section 3.3 (eq. a2_str).
+ *   - V-cycle: Section 3.3, Algorithm 1; smoother Iter = CG.
+ *   - Kernels: Section 4 (eq. a_gau, eq. a_exp).
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns an h2mg_status; no exception crosses the ABI.  On
+ *     failure h2mg_last_error() returns a thread-local message that stays
+ *     valid until the next call on the same thread.
+ *   - "device" pointers are HIP device allocations on the current device;
+ *     "host" pointers are ordinary host memory.  The caller owns every
+ *     pointer it passes; the library copies what it keeps.
+ *   - Points are n x dim row-major FP64 in user order.  Vectors passed to
+ *     h2mg_matvec / h2mg_solve are length-n FP64 in user order (the library
+ *     permutes to tree order internally).
+ *   - Coefficient vectors of coarse level k >= 2 (tree depth d = L - k + 2)
+ *     are cluster-major: 2^d clusters of r coefficients each, clusters in
+ *     tree order.
+ *   - Device work is enqueued on the given stream (0 = null stream).
+ *     h2mg_matvec, h2mg_level_apply, h2mg_restrict and h2mg_prolong do not
+ *     block the host.  h2mg_build, h2mg_setup_mg, h2mg_vcycle and
+ *     h2mg_solve synchronise the stream before returning.
+ *   - A handle is not thread-safe: calls on one handle must not overlap.
+ */
+#ifndef H2MG_H_
+#define H2MG_H_
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum h2mg_status {
+  H2MG_OK = 0,
+  H2MG_ERR_INVALID_ARG = 1,   /* bad size, parameter, null or non-finite input */
+  H2MG_ERR_OOM = 2,           /* device or host allocation failed */
+  H2MG_ERR_HIP = 3,           /* a HIP runtime call failed */
+  H2MG_ERR_NOT_SPD = 4,       /* p^T A p <= 0 in CG or a Cholesky pivot <= 0 */
+  H2MG_ERR_NOT_CONVERGED = 5, /* cycle cap reached; x holds the last iterate */
+  H2MG_ERR_NUMERIC = 6,       /* NaN/Inf met during a solve */
+  H2MG_ERR_STATE = 7          /* calls in the wrong order */
+} h2mg_status;
+
+/* Kernel families (Section 4: exponential eq. a_exp, Gaussian eq. a_gau;
+ * Matern-3/2 in addition).  k(0) = 1 for all, and the diagonal of A is
+ * k(0) + shift (the paper's 1 + c).
+ *   H2MG_KERNEL_EXP:      k(r) = exp(-r / l)
+ *   H2MG_KERNEL_GAUSS:    k(r) = exp(-r^2 / (2 l^2))   (paper's sigma = 2 l^2)
+ *   H2MG_KERNEL_MATERN32: k(r) = (1 + sqrt(3) r / l) exp(-sqrt(3) r / l) */
+typedef enum h2mg_kernel_kind {
+  H2MG_KERNEL_EXP = 0,
+  H2MG_KERNEL_GAUSS = 1,
+  H2MG_KERNEL_MATERN32 = 2
+} h2mg_kernel_kind;
+
+typedef struct h2mg_kernel {
+  int32_t kind;          /* h2mg_kernel_kind */
+  double length_scale;   /* l > 0 */
+  double shift;          /* >= 0, added to the diagonal */
+} h2mg_kernel;
+
+/* Cluster tree and bases (Section 3.1).  Binary tree of uniform depth
+ * L = min{L : leaf_size * 2^L >= n}, median split along the longest side of
+ * each cluster's tight box; a pair of clusters is far (admissible) when its
+ * boxes are apart and max(diam) <= eta * dist; bases are tensor Chebyshev
+ * interpolants with cheb_m nodes per axis, rank r = cheb_m^dim.
+ * Requires r <= 64 and every leaf to hold at least r points. */
+typedef struct h2mg_build_opts {
+  int32_t leaf_size;     /* >= 1 */
+  double eta;            /* > 0 */
+  int32_t cheb_m;        /* >= 1 */
+} h2mg_build_opts;
+
+typedef enum h2mg_precision {
+  H2MG_FP64 = 0,         /* every step in FP64 */
+  H2MG_FP32_IR = 1,      /* V-cycle on FP32 operators inside FP64 refinement */
+  H2MG_BF16_IR = 2       /* V-cycle on BF16 operators inside FP64 refinement */
+} h2mg_precision;
+
+/* Solver options (Section 3.3, Algorithm 1 and the remark on fine and
+ * coarse iterations).  n_fine / n_coarse CG steps pre- and post-smoothing on
+ * the finest / coarser levels; the solve stops when
+ * ||b - A_H2 x||_2 / ||b||_2 < rtol, measured in FP64, or after max_cycles
+ * V-cycles (FP64) or refinement steps (mixed forms, one V-cycle each). */
+typedef struct h2mg_solve_opts {
+  int32_t n_fine;        /* >= 0, paper default 1 */
+  int32_t n_coarse;      /* >= 0, paper default 40 */
+  double rtol;           /* > 0, e.g. 1e-8 */
+  int32_t max_cycles;    /* >= 0 */
+  int32_t precision;     /* h2mg_precision */
+  int32_t use_x0;        /* 1: x holds the initial guess; 0: start from 0 */
+} h2mg_solve_opts;
+
+typedef struct h2mg_solve_info {
+  int32_t cycles;        /* V-cycles (or refinement steps) performed */
+  int32_t converged;     /* 1 if the residual test passed */
+  double rel_residual;   /* final ||b - A_H2 x|| / ||b|| in FP64 */
+  double solve_seconds;  /* wall time of the solve on the host clock */
+  int32_t history_len;   /* entries available from h2mg_solve_history */
+} h2mg_solve_info;
+
+/* ------------------------------------------------------------------ plan
+ * Host-side cluster tree and block partition (no device work).  Exposed so
+ * the structure can be inspected and tested without a GPU. */
+typedef struct h2mg_plan_s* h2mg_plan_t;
+
+typedef struct h2mg_plan_info {
+  int64_t n;             /* number of points */
+  int32_t dim;
+  int32_t depth;         /* leaf depth L */
+  int32_t d_top;         /* shallowest depth with a far pair, -1 if none */
+  int32_t rank;          /* r = cheb_m^dim */
+  int32_t leaf_min;      /* smallest and largest leaf size */
+  int32_t leaf_max;
+} h2mg_plan_info;
+
+/* Build the tree and partition of `points_host` (n x dim, host, user order).
+ * Errors: INVALID_ARG for n < 1, dim not in {1,2,3}, leaf_size < 1,
+ * eta <= 0 or non-finite, cheb_m < 1, r > 64, non-finite coordinates, or a
+ * leaf with fewer than r points; OOM.  *out must be freed with
+ * h2mg_plan_destroy. */
+h2mg_status h2mg_plan_create(const double* points_host, int64_t n, int32_t dim,
+                             const h2mg_build_opts* opts, h2mg_plan_t* out);
+h2mg_status h2mg_plan_query(h2mg_plan_t plan, h2mg_plan_info* info);
+/* perm_host[k] = user index at tree position k (n entries). */
+h2mg_status h2mg_plan_perm(h2mg_plan_t plan, int64_t* perm_host);
+/* offsets_host[j] = first tree position of cluster j at `depth`
+ * (2^depth + 1 entries). */
+h2mg_status h2mg_plan_offsets(h2mg_plan_t plan, int32_t depth, int64_t* offsets_host);
+/* Number of near (which = 0) or far (which = 1) cluster pairs at `depth`,
+ * counting both (s, t) and (t, s). */
+h2mg_status h2mg_plan_pair_count(h2mg_plan_t plan, int32_t depth, int32_t which,
+                                 int64_t* count);
+/* The pairs themselves, sorted by (s, t): pairs_host[2i] = s, [2i+1] = t. */
+h2mg_status h2mg_plan_pairs(h2mg_plan_t plan, int32_t depth, int32_t which,
+                            int64_t* pairs_host);
+void h2mg_plan_destroy(h2mg_plan_t plan);
+
+/* ------------------------------------------------------------------ H2 */
+typedef struct h2mg_h2_s* h2mg_h2_t;
+
+/* Build A_H2 from `points_dev` (device, n x dim FP64, user order) and the
+ * kernel (Section 3.1): tree and partition on the host, then on the device
+ * the orthonormal nested bases (leaf bases Q, transfers E), and the
+ * orthogonalised far couplings S of every depth.  Near leaf blocks are
+ * evaluated on the fly in every product.  Errors as h2mg_plan_create, plus
+ * INVALID_ARG for a null pointer or a bad kernel, OOM, HIP.  Blocks until
+ * the build is complete. */
+h2mg_status h2mg_build(const double* points_dev, int64_t n, int32_t dim,
+                       const h2mg_kernel* kernel, const h2mg_build_opts* opts,
+                       hipStream_t stream, h2mg_h2_t* out);
+
+/* y = A_H2 x (Section 3.1 matvec: upsweep x_i = V_i x_{i-1}, couplings,
+ * downsweep y_{i-1} = D_i x_{i-1} + U_i y_i, near field y = D x + U_1 y_1).
+ * x_dev, y_dev: device, length n, user order; they must not overlap. */
+h2mg_status h2mg_matvec(h2mg_h2_t h, const double* x_dev, double* y_dev,
+                        hipStream_t stream);
+
+/* Build the H2-MG hierarchy (Section 3.3): restricted operators
+ * A_k = U_{k-1}^T A_{k-1} V_{k-1}^T for every level, i.e. the projected close
+ * blocks of eq. a2_str at every depth, the dense coarsest operator A_l and
+ * its FP64 Cholesky factor.  precision_mask bit 1 (value 2) also prepares
+ * FP32 copies of the operators, bit 2 (value 4) BF16 copies; FP64 is always
+ * built.  Errors: NOT_SPD if a Cholesky pivot of A_l is <= 0; OOM; HIP.
+ * Calling it again only adds missing precisions. */
+h2mg_status h2mg_setup_mg(h2mg_h2_t h, int32_t precision_mask, hipStream_t stream);
+
+/* Number of MG levels l (1 when there is no far block: then A_1 is solved
+ * directly) and the size N_k of level k (1-based; N_1 = n). */
+h2mg_status h2mg_level_count(h2mg_h2_t h, int32_t* levels);
+h2mg_status h2mg_level_size(h2mg_h2_t h, int32_t level, int64_t* size);
+
+/* y = A_k x on level k (level 1: x, y in user order, same as h2mg_matvec;
+ * level >= 2: coefficient order).  Requires h2mg_setup_mg for level >= 2. */
+h2mg_status h2mg_level_apply(h2mg_h2_t h, int32_t level, const double* x_dev,
+                             double* y_dev, hipStream_t stream);
+/* Restriction r_{k+1} = U_k^T r_k and prolongation e_k = V_k^T e_{k+1} = U_k e_{k+1}
+ * between levels k and k+1 (Algorithm 1).  Level 1 vectors in user order. */
+h2mg_status h2mg_restrict(h2mg_h2_t h, int32_t level, const double* r_dev,
+                          double* r_next_dev, hipStream_t stream);
+h2mg_status h2mg_prolong(h2mg_h2_t h, int32_t level, const double* e_next_dev,
+                         double* e_dev, hipStream_t stream);
+
+/* One V-cycle of Algorithm 1 in FP64: x_out = x0 + e_1 for A_H2 x = b.
+ * All vectors device, length n, user order; x_out may alias x0. */
+h2mg_status h2mg_vcycle(h2mg_h2_t h, const double* x0_dev, const double* b_dev,
+                        double* x_out_dev, const h2mg_solve_opts* opts,
+                        hipStream_t stream);
+
+/* Solve A_H2 x = b by repeated V-cycles (FP64) or FP64 iterative refinement
+ * around a low-precision V-cycle (opts->precision).  b_dev, x_dev: device,
+ * length n, user order.  Runs h2mg_setup_mg itself when needed.  Errors:
+ * NOT_CONVERGED (x holds the last iterate, info filled), NOT_SPD, NUMERIC,
+ * INVALID_ARG (null, bad options, non-finite b).  info may be null. */
+h2mg_status h2mg_solve(h2mg_h2_t h, const double* b_dev, double* x_dev,
+                       const h2mg_solve_opts* opts, h2mg_solve_info* info,
+                       hipStream_t stream);
+/* Relative residual before each cycle of the last solve, then at exit
+ * (host array of at least `capacity` doubles; copies min(capacity, len)). */
+h2mg_status h2mg_solve_history(h2mg_h2_t h, double* history_host, int32_t capacity);
+
+/* Device memory held by the handle, in bytes. */
+h2mg_status h2mg_memory_bytes(h2mg_h2_t h, int64_t* bytes);
+
+h2mg_status h2mg_destroy(h2mg_h2_t h);
+
+const char* h2mg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* H2MG_H_ */

@@ -124,6 +124,38 @@ class H2:
         y[perm] = yt
         return y
 
+    def matvec_rows(self, x: np.ndarray, leaf: int) -> np.ndarray:
+        """Rows of one leaf (tree order) of y = A_H2 x, x in user order.
+
+        The same blockwise sum as matvec_tree restricted to the block rows
+        that contain the leaf: its close leaf pairs, and at every depth the
+        far pairs of the leaf's ancestor (parent basis restricted to the
+        leaf's rows).  Cost O(n_leaf * n) at most, so it can sample any size.
+        """
+        xt = np.asarray(x, dtype=np.float64)[self.tree.perm]
+        L = self.L
+        lr = self.rows(L, leaf)
+        y = np.zeros(lr.stop - lr.start)
+        near = self.part.near[L]
+        lo, hi = np.searchsorted(near[:, 0], [leaf, leaf + 1])
+        for s, t in near[lo:hi]:
+            y += self.near_block(s, t) @ xt[self.rows(L, t)]
+        for d in range(L + 1):
+            far = self.part.far[d]
+            anc = leaf >> (L - d)
+            lo, hi = np.searchsorted(far[:, 0], [anc, anc + 1])
+            if hi == lo:
+                continue
+            Xa = self.P[lr]
+            Ua = cheb.tensor_eval(Xa, self.c[d][anc], self.h[d][anc], self.m)
+            acc = np.zeros(self.r)
+            for s, t in far[lo:hi]:
+                tr = self.rows(d, t)
+                Ut = cheb.tensor_eval(self.P[tr], self.c[d][t], self.h[d][t], self.m)
+                acc += self.coupling(d, s, t) @ (Ut.T @ xt[tr])
+            y += Ua @ acc
+        return y
+
     def dense_tree(self) -> np.ndarray:
         """A_H2 as a dense matrix in tree order (small N only)."""
         A = np.zeros((self.n, self.n))

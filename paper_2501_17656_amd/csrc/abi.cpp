@@ -1,0 +1,295 @@
+// extern "C" entry points declared in include/h2mg.h.  Every call returns a
+// status; exceptions never cross this boundary.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+
+#include "h2_build.h"
+
+using namespace h2mg;
+
+struct h2mg_plan_s {
+  Plan plan;
+};
+
+struct h2mg_h2_s {
+  H2* h;
+};
+
+namespace {
+
+template <typename F>
+h2mg_status guarded(F&& f) {
+  clear_error();
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return fail(H2MG_ERR_OOM, "allocation failed");
+  } catch (const std::exception& e) {
+    return fail(H2MG_ERR_HIP, "%s", e.what());
+  } catch (...) {
+    return fail(H2MG_ERR_HIP, "unknown error");
+  }
+}
+
+h2mg_status check_stream_err(hipStream_t s) {
+  (void)s;
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(H2MG_ERR_HIP, "%s", hipGetErrorString(e));
+  return H2MG_OK;
+}
+
+bool valid_solve_opts(const h2mg_solve_opts* o) {
+  return o && o->n_fine >= 0 && o->n_coarse >= 0 && o->rtol > 0.0 && std::isfinite(o->rtol) &&
+         o->max_cycles >= 0 && o->precision >= 0 && o->precision <= 2;
+}
+
+SolveParams to_params(const h2mg_solve_opts* o) {
+  SolveParams sp;
+  sp.n_fine = o->n_fine;
+  sp.n_coarse = o->n_coarse;
+  sp.rtol = o->rtol;
+  sp.max_cycles = o->max_cycles;
+  sp.precision = o->precision;
+  sp.use_x0 = o->use_x0 != 0;
+  return sp;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* h2mg_last_error(void) { return last_error_cstr(); }
+
+h2mg_status h2mg_plan_create(const double* points_host, int64_t n, int32_t dim,
+                             const h2mg_build_opts* opts, h2mg_plan_t* out) {
+  return guarded([&] {
+    if (!out) return fail(H2MG_ERR_INVALID_ARG, "null output handle");
+    *out = nullptr;
+    auto* p = new h2mg_plan_s();
+    h2mg_status st = build_plan(points_host, n, dim, opts, &p->plan);
+    if (st != H2MG_OK) {
+      delete p;
+      return st;
+    }
+    *out = p;
+    return H2MG_OK;
+  });
+}
+
+h2mg_status h2mg_plan_query(h2mg_plan_t plan, h2mg_plan_info* info) {
+  return guarded([&] {
+    if (!plan || !info) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    const Plan& P = plan->plan;
+    info->n = P.n;
+    info->dim = P.dim;
+    info->depth = P.L;
+    info->d_top = P.d_top;
+    info->rank = P.r;
+    info->leaf_min = P.leaf_min;
+    info->leaf_max = P.leaf_max;
+    return H2MG_OK;
+  });
+}
+
+h2mg_status h2mg_plan_perm(h2mg_plan_t plan, int64_t* perm_host) {
+  return guarded([&] {
+    if (!plan || !perm_host) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    std::memcpy(perm_host, plan->plan.perm.data(), plan->plan.perm.size() * sizeof(int64_t));
+    return H2MG_OK;
+  });
+}
+
+h2mg_status h2mg_plan_offsets(h2mg_plan_t plan, int32_t depth, int64_t* off) {
+  return guarded([&] {
+    if (!plan || !off) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    if (depth < 0 || depth > plan->plan.L) return fail(H2MG_ERR_INVALID_ARG, "depth out of range");
+    const auto& o = plan->plan.offsets[depth];
+    std::memcpy(off, o.data(), o.size() * sizeof(int64_t));
+    return H2MG_OK;
+  });
+}
+
+h2mg_status h2mg_plan_pair_count(h2mg_plan_t plan, int32_t depth, int32_t which, int64_t* count) {
+  return guarded([&] {
+    if (!plan || !count) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    if (depth < 0 || depth > plan->plan.L || which < 0 || which > 1)
+      return fail(H2MG_ERR_INVALID_ARG, "depth or kind out of range");
+    const auto& v = which == 0 ? plan->plan.near[depth] : plan->plan.far[depth];
+    *count = int64_t(v.size() / 2);
+    return H2MG_OK;
+  });
+}
+
+h2mg_status h2mg_plan_pairs(h2mg_plan_t plan, int32_t depth, int32_t which, int64_t* pairs) {
+  return guarded([&] {
+    if (!plan || !pairs) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    if (depth < 0 || depth > plan->plan.L || which < 0 || which > 1)
+      return fail(H2MG_ERR_INVALID_ARG, "depth or kind out of range");
+    const auto& v = which == 0 ? plan->plan.near[depth] : plan->plan.far[depth];
+    for (size_t i = 0; i < v.size(); ++i) pairs[i] = v[i];
+    return H2MG_OK;
+  });
+}
+
+void h2mg_plan_destroy(h2mg_plan_t plan) { delete plan; }
+
+h2mg_status h2mg_build(const double* points_dev, int64_t n, int32_t dim, const h2mg_kernel* kernel,
+                       const h2mg_build_opts* opts, hipStream_t stream, h2mg_h2_t* out) {
+  return guarded([&] {
+    if (!out) return fail(H2MG_ERR_INVALID_ARG, "null output handle");
+    *out = nullptr;
+    H2* h = nullptr;
+    h2mg_status st = build_h2(points_dev, n, dim, kernel, opts, stream, &h);
+    if (st != H2MG_OK) return st;
+    *out = new h2mg_h2_s{h};
+    return H2MG_OK;
+  });
+}
+
+h2mg_status h2mg_matvec(h2mg_h2_t hh, const double* x, double* y, hipStream_t stream) {
+  return guarded([&] {
+    if (!hh || !x || !y) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    H2& h = *hh->h;
+    h.stream = stream;
+    launch_gather(h, x, h.vtree);
+    apply_fine(h, P64, h.vtree, h.vtree2, 1.0, nullptr, 0.0);
+    launch_scatter(h, h.vtree2, y);
+    return check_stream_err(stream);
+  });
+}
+
+h2mg_status h2mg_setup_mg(h2mg_h2_t hh, int32_t mask, hipStream_t stream) {
+  return guarded([&] {
+    if (!hh) return fail(H2MG_ERR_INVALID_ARG, "null handle");
+    hh->h->stream = stream;
+    return setup_mg(*hh->h, mask);
+  });
+}
+
+h2mg_status h2mg_level_count(h2mg_h2_t hh, int32_t* levels) {
+  return guarded([&] {
+    if (!hh || !levels) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    const H2& h = *hh->h;
+    *levels = h.d_top < 0 ? 1 : h.L - h.d_top + 2;
+    return H2MG_OK;
+  });
+}
+
+h2mg_status h2mg_level_size(h2mg_h2_t hh, int32_t level, int64_t* size) {
+  return guarded([&] {
+    if (!hh || !size) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    const H2& h = *hh->h;
+    const int l = h.d_top < 0 ? 1 : h.L - h.d_top + 2;
+    if (level < 1 || level > l) return fail(H2MG_ERR_INVALID_ARG, "level out of range");
+    *size = h.level_size(level);
+    return H2MG_OK;
+  });
+}
+
+h2mg_status h2mg_level_apply(h2mg_h2_t hh, int32_t level, const double* x, double* y,
+                             hipStream_t stream) {
+  return guarded([&] {
+    if (!hh || !x || !y) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    H2& h = *hh->h;
+    h.stream = stream;
+    if (level == 1) {
+      launch_gather(h, x, h.vtree);
+      apply_fine(h, P64, h.vtree, h.vtree2, 1.0, nullptr, 0.0);
+      launch_scatter(h, h.vtree2, y);
+      return check_stream_err(stream);
+    }
+    if (!h.mg_built) return fail(H2MG_ERR_STATE, "call h2mg_setup_mg before applying level %d", level);
+    if (level < 2 || level > h.levels) return fail(H2MG_ERR_INVALID_ARG, "level out of range");
+    apply_coarse(h, P64, level, x, y);
+    return check_stream_err(stream);
+  });
+}
+
+h2mg_status h2mg_restrict(h2mg_h2_t hh, int32_t level, const double* r, double* r_next,
+                          hipStream_t stream) {
+  return guarded([&] {
+    if (!hh || !r || !r_next) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    H2& h = *hh->h;
+    h.stream = stream;
+    const int l = h.d_top < 0 ? 1 : h.L - h.d_top + 2;
+    if (level < 1 || level >= l) return fail(H2MG_ERR_INVALID_ARG, "level out of range");
+    if (level == 1) {
+      launch_gather(h, r, h.vtree);
+      restrict_level(h, P64, 1, h.vtree, r_next);
+    } else {
+      restrict_level(h, P64, level, r, r_next);
+    }
+    return check_stream_err(stream);
+  });
+}
+
+h2mg_status h2mg_prolong(h2mg_h2_t hh, int32_t level, const double* e_next, double* e,
+                         hipStream_t stream) {
+  return guarded([&] {
+    if (!hh || !e_next || !e) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    H2& h = *hh->h;
+    h.stream = stream;
+    const int l = h.d_top < 0 ? 1 : h.L - h.d_top + 2;
+    if (level < 1 || level >= l) return fail(H2MG_ERR_INVALID_ARG, "level out of range");
+    if (level == 1) {
+      prolong_level(h, P64, 1, e_next, h.vtree, nullptr, 0.0);
+      launch_scatter(h, h.vtree, e);
+    } else {
+      prolong_level(h, P64, level, e_next, e, nullptr, 0.0);
+    }
+    return check_stream_err(stream);
+  });
+}
+
+h2mg_status h2mg_vcycle(h2mg_h2_t hh, const double* x0, const double* b, double* x_out,
+                        const h2mg_solve_opts* opts, hipStream_t stream) {
+  return guarded([&] {
+    if (!hh || !x0 || !b || !x_out) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    if (!valid_solve_opts(opts)) return fail(H2MG_ERR_INVALID_ARG, "invalid solve options");
+    hh->h->stream = stream;
+    return vcycle_once(*hh->h, x0, b, x_out, to_params(opts));
+  });
+}
+
+h2mg_status h2mg_solve(h2mg_h2_t hh, const double* b, double* x, const h2mg_solve_opts* opts,
+                       h2mg_solve_info* info, hipStream_t stream) {
+  return guarded([&] {
+    if (!hh || !b || !x) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    if (!valid_solve_opts(opts)) return fail(H2MG_ERR_INVALID_ARG, "invalid solve options");
+    hh->h->stream = stream;
+    return solve(*hh->h, b, x, to_params(opts), info);
+  });
+}
+
+h2mg_status h2mg_solve_history(h2mg_h2_t hh, double* hist, int32_t cap) {
+  return guarded([&] {
+    if (!hh || (!hist && cap > 0)) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    const auto& v = hh->h->history;
+    for (int i = 0; i < cap && i < int(v.size()); ++i) hist[i] = v[i];
+    return H2MG_OK;
+  });
+}
+
+h2mg_status h2mg_memory_bytes(h2mg_h2_t hh, int64_t* bytes) {
+  return guarded([&] {
+    if (!hh || !bytes) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    *bytes = int64_t(hh->h->arena.bytes);
+    return H2MG_OK;
+  });
+}
+
+h2mg_status h2mg_destroy(h2mg_h2_t hh) {
+  return guarded([&] {
+    if (!hh) return H2MG_OK;
+    (void)hipStreamSynchronize(hh->h->stream);
+    delete hh->h;
+    delete hh;
+    return H2MG_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,133 @@
+// Device-side helpers shared by the setup and apply kernels.
+//
+// Tiled block layout.  Every r x r block (couplings S, projected close
+// blocks, transfers E) is stored for a 64-lane wave laid out as an 8 x 8
+// lane grid: lane l = 8a + b owns rows a*T .. a*T+T-1 and columns
+// b*T .. b*T+T-1 of the block, where T is the smallest power of two with
+// 8T >= r (entries beyond r are zero).  The T*T elements of a lane are cut
+// into chunks of K consecutive elements (K = min(16 bytes / element size,
+// T*T)), and chunk c of lane l lives at element offset (c*64 + l)*K, so a
+// wave reads each chunk row as one contiguous 64*K-element segment.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace h2mg {
+
+// ---------------------------------------------------------------- bf16
+struct bf16 {
+  uint16_t bits;
+};
+
+__host__ __device__ inline float bf16_to_float(bf16 v) {
+  union { uint32_t u; float f; } c;
+  c.u = uint32_t(v.bits) << 16;
+  return c.f;
+}
+
+// Round-to-nearest-even of an FP32 value to BF16 (finite inputs).
+__host__ __device__ inline bf16 float_to_bf16(float f) {
+  union { uint32_t u; float f; } c;
+  c.f = f;
+  uint32_t lsb = (c.u >> 16) & 1u;
+  bf16 r;
+  r.bits = uint16_t((c.u + 0x7fffu + lsb) >> 16);
+  return r;
+}
+
+template <typename T> struct Conv;
+template <> struct Conv<double> {
+  __device__ static double to_f64(double v) { return v; }
+  __device__ static double from_f64(double v) { return v; }
+};
+template <> struct Conv<float> {
+  __device__ static double to_f64(float v) { return v; }
+  __device__ static float from_f64(double v) { return float(v); }
+};
+template <> struct Conv<bf16> {
+  __device__ static double to_f64(bf16 v) { return bf16_to_float(v); }
+  __device__ static bf16 from_f64(double v) { return float_to_bf16(float(v)); }
+};
+
+// Load one stored element as the accumulation type.
+template <typename Tacc, typename Tb> __device__ inline Tacc ld_as(Tb v);
+template <> __device__ inline double ld_as<double, double>(double v) { return v; }
+template <> __device__ inline float ld_as<float, float>(float v) { return v; }
+template <> __device__ inline float ld_as<float, bf16>(bf16 v) { return bf16_to_float(v); }
+template <> __device__ inline double ld_as<double, float>(float v) { return v; }
+
+// ---------------------------------------------------------------- tiles
+__host__ __device__ constexpr int tile_T(int r) {
+  return r <= 8 ? 1 : r <= 16 ? 2 : r <= 32 ? 4 : 8;
+}
+template <typename Tb>
+__host__ __device__ constexpr int tile_K(int T) {
+  return (16 / int(sizeof(Tb))) < T * T ? (16 / int(sizeof(Tb))) : T * T;
+}
+// Elements per stored tile.
+__host__ __device__ constexpr int64_t tile_elems(int T) { return 64LL * T * T; }
+
+// Element offset of block entry (i, j) inside a tile.
+template <typename Tb>
+__host__ __device__ inline int tile_offset(int i, int j, int T) {
+  const int K = tile_K<Tb>(T);
+  const int a = i / T, u = i % T, b = j / T, v = j % T;
+  const int lane = 8 * a + b;
+  const int e = u * T + v;
+  return ((e / K) * 64 + lane) * K + (e % K);
+}
+
+// Load the T*T elements of this lane's sub-tile (row-major u*T + v) from
+// the tile starting at `tile`.
+template <int T, typename Tb, typename Tacc>
+__device__ inline void load_subtile(const Tb* __restrict__ tile, int lane, Tacc (&B)[T * T]) {
+  constexpr int K = tile_K<Tb>(T);
+  constexpr int NC = T * T / K;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const Tb* p = tile + (c * 64 + lane) * K;
+    if constexpr (K * sizeof(Tb) == 16) {
+      // one 16-byte load per chunk
+      union { uint4 q; Tb e[K]; } u;
+      u.q = *reinterpret_cast<const uint4*>(p);
+#pragma unroll
+      for (int k = 0; k < K; ++k) B[c * K + k] = ld_as<Tacc, Tb>(u.e[k]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) B[c * K + k] = ld_as<Tacc, Tb>(p[k]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- kernels
+enum { KER_EXP = 0, KER_GAUSS = 1, KER_MATERN32 = 2 };
+
+struct KernelParams {
+  int kind;
+  double inv_l;        // 1 / l
+  double inv_2l2;      // 1 / (2 l^2)
+  double shift;
+};
+
+// k as a function of the squared distance (no shift).
+__device__ inline double kernel_r2(const KernelParams& kp, double r2) {
+  if (kp.kind == KER_GAUSS) return exp(-r2 * kp.inv_2l2);
+  const double rr = sqrt(r2);
+  if (kp.kind == KER_EXP) return exp(-rr * kp.inv_l);
+  const double z = 1.7320508075688772 * rr * kp.inv_l;
+  return (1.0 + z) * exp(-z);
+}
+
+__device__ inline float kernel_r2(const KernelParams& kp, float r2) {
+  if (kp.kind == KER_GAUSS) return expf(-r2 * float(kp.inv_2l2));
+  const float rr = sqrtf(r2);
+  if (kp.kind == KER_EXP) return expf(-rr * float(kp.inv_l));
+  const float z = 1.7320508f * rr * float(kp.inv_l);
+  return (1.0f + z) * expf(-z);
+}
+
+// ---------------------------------------------------------------- shuffles
+__device__ inline double shfl_xor(double v, int m) { return __shfl_xor(v, m, 64); }
+__device__ inline float shfl_xor(float v, int m) { return __shfl_xor(v, m, 64); }
+
+}  // namespace h2mg

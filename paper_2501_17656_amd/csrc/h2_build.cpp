@@ -1,0 +1,399 @@
+// Building an H2 handle: host index structures, device allocations, and the
+// order of the setup kernels (Section 3.1 for the H2 pieces, Section 3.3 for
+// the restricted operators and the coarsest Cholesky factor).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <stdexcept>
+#include <unordered_map>
+
+#include "h2_build.h"
+
+namespace h2mg {
+
+void* Arena::alloc(size_t nbytes) {
+  if (nbytes == 0) nbytes = 8;
+  void* p = nullptr;
+  if (hipMalloc(&p, nbytes) != hipSuccess || p == nullptr) {
+    (void)hipGetLastError();
+    throw std::bad_alloc();
+  }
+  ptrs.emplace_back(p, nbytes);
+  bytes += nbytes;
+  return p;
+}
+
+void Arena::release(void* p) {
+  for (size_t i = 0; i < ptrs.size(); ++i)
+    if (ptrs[i].first == p) {
+      (void)hipFree(p);
+      bytes -= ptrs[i].second;
+      ptrs.erase(ptrs.begin() + i);
+      return;
+    }
+}
+
+Arena::~Arena() {
+  for (auto& pr : ptrs) (void)hipFree(pr.first);
+}
+
+namespace {
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename T>
+T* upload(H2& h, const std::vector<T>& v) {
+  T* d = h.arena.make<T>(std::max<size_t>(v.size(), 1));
+  if (!v.empty())
+    hip_check(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, h.stream),
+              "upload");
+  return d;
+}
+
+constexpr int CHUNK = 16;      // stored blocks per GEMV task
+constexpr int NEAR_CHUNK = 4;  // close leaf pairs per near-field task
+
+// Tasks and column lists of the stored blocks [first, first + count) of one
+// depth (sorted by row gid, then column gid).
+View make_view(H2& h, int d, int first, int count) {
+  View v;
+  v.depth = d;
+  const int nrows = 1 << d;
+  const int gid0 = nrows - 1;
+  std::vector<int> rtp(nrows + 1, 0);
+  for (int b = first; b < first + count;) {
+    const int row = h.blk_row_h[b];
+    int e = b;
+    while (e < first + count && h.blk_row_h[e] == row) ++e;
+    for (int c = b; c < e; c += CHUNK) {
+      v.task.push_back(row);
+      v.task.push_back(c);
+      v.task.push_back(std::min(e, c + CHUNK));
+      rtp[row - gid0 + 1]++;
+    }
+    b = e;
+  }
+  for (int i = 0; i < nrows; ++i) rtp[i + 1] += rtp[i];
+  v.ntasks = int(v.task.size() / 3);
+  std::vector<int> cptr(nrows + 1, 0), cblk;
+  for (int b = first; b < first + count; ++b)
+    if (h.blk_col_h[b] != h.blk_row_h[b]) cptr[h.blk_col_h[b] - gid0 + 1]++;
+  for (int i = 0; i < nrows; ++i) cptr[i + 1] += cptr[i];
+  cblk.resize(cptr[nrows]);
+  std::vector<int> fill(cptr.begin(), cptr.end() - 1);
+  for (int b = first; b < first + count; ++b)
+    if (h.blk_col_h[b] != h.blk_row_h[b]) cblk[fill[h.blk_col_h[b] - gid0]++] = b;
+  v.row_task_ptr = upload(h, rtp);
+  v.col_ptr = upload(h, cptr);
+  v.col_blk = upload(h, cblk);
+  return v;
+}
+
+Launch make_launch(H2& h, const std::vector<const View*>& views) {
+  Launch l;
+  std::vector<int> all;
+  for (const View* v : views) {
+    l.base.push_back(int(all.size() / 3));
+    all.insert(all.end(), v->task.begin(), v->task.end());
+  }
+  l.ntasks = int(all.size() / 3);
+  l.task = upload(h, all);
+  h.max_tasks = std::max(h.max_tasks, l.ntasks);
+  return l;
+}
+
+}  // namespace
+
+h2mg_status build_h2(const double* points_dev, int64_t n, int dim, const h2mg_kernel* kernel,
+                     const h2mg_build_opts* opts, hipStream_t stream, H2** out) {
+  if (!points_dev || !kernel || !opts || !out) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+  if (kernel->kind < 0 || kernel->kind > 2) return fail(H2MG_ERR_INVALID_ARG, "unknown kernel kind %d", kernel->kind);
+  if (!(kernel->length_scale > 0.0) || !std::isfinite(kernel->length_scale))
+    return fail(H2MG_ERR_INVALID_ARG, "length_scale must be finite and > 0");
+  if (!(kernel->shift >= 0.0) || !std::isfinite(kernel->shift))
+    return fail(H2MG_ERR_INVALID_ARG, "shift must be finite and >= 0");
+  if (n < 1 || dim < 1 || dim > 3) return fail(H2MG_ERR_INVALID_ARG, "bad n or dim");
+  if (opts->leaf_size > 256)
+    return fail(H2MG_ERR_INVALID_ARG, "leaf_size must be <= 256 (got %d)", opts->leaf_size);
+
+  std::vector<double> pts_h(size_t(n) * dim);
+  hipError_t e = hipMemcpyAsync(pts_h.data(), points_dev, pts_h.size() * sizeof(double),
+                                hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return fail(H2MG_ERR_HIP, "copying points to the host: %s", hipGetErrorString(e));
+
+  H2* hp = new (std::nothrow) H2();
+  if (!hp) return fail(H2MG_ERR_OOM, "host allocation failed");
+  H2& h = *hp;
+  h2mg_status st = build_plan(pts_h.data(), n, dim, opts, &h.plan);
+  if (st != H2MG_OK) {
+    delete hp;
+    return st;
+  }
+  try {
+    const Plan& P = h.plan;
+    h.stream = stream;
+    h.n = int(n);
+    h.dim = dim;
+    h.r = P.r;
+    h.m = P.m;
+    h.L = P.L;
+    h.d_top = P.d_top;
+    h.T = tile_T(h.r);
+    h.nleaf = 1 << h.L;
+    h.leaf_max = P.leaf_max;
+    h.ngid = (1 << (h.L + 1)) - 1;
+    h.kp.kind = kernel->kind;
+    h.kp.inv_l = 1.0 / kernel->length_scale;
+    h.kp.inv_2l2 = 1.0 / (2.0 * kernel->length_scale * kernel->length_scale);
+    h.kp.shift = kernel->shift;
+
+    // ---- geometry
+    std::vector<double> ptree(size_t(n) * dim);
+    for (int64_t i = 0; i < n; ++i)
+      for (int a = 0; a < dim; ++a) ptree[i * dim + a] = pts_h[P.perm[i] * dim + a];
+    h.pts = upload(h, ptree);
+    h.perm = upload(h, P.perm);
+    std::vector<int> loff(h.nleaf + 1);
+    for (int j = 0; j <= h.nleaf; ++j) loff[j] = int(P.offsets[h.L][j]);
+    h.leaf_off = upload(h, loff);
+    double Hmax = 0.0;
+    for (int a = 0; a < dim; ++a) Hmax = std::max(Hmax, 0.5 * (P.hi[0][a] - P.lo[0][a]));
+    const double floor_h = 1e-9 * Hmax;
+    std::vector<double> cb(size_t(h.ngid) * dim), hb(size_t(h.ngid) * dim);
+    for (int d = 0; d <= h.L; ++d)
+      for (int j = 0; j < (1 << d); ++j) {
+        const int g = (1 << d) - 1 + j;
+        for (int a = 0; a < dim; ++a) {
+          const double lo = P.lo[d][j * dim + a], hi = P.hi[d][j * dim + a];
+          cb[size_t(g) * dim + a] = 0.5 * (lo + hi);
+          hb[size_t(g) * dim + a] = std::max(0.5 * (hi - lo), floor_h);
+        }
+      }
+    h.cbox = upload(h, cb);
+    h.hbox = upload(h, hb);
+    std::vector<double> t(h.m);
+    for (int k = 0; k < h.m; ++k) t[k] = std::cos((2.0 * k + 1.0) * M_PI / (2.0 * h.m));
+    h.nodes1d = upload(h, t);
+
+    // ---- stored blocks (upper triangle): S of depths d_top..L, then Pi
+    h.s_first.assign(h.L + 1, 0);
+    h.s_count.assign(h.L + 1, 0);
+    h.p_first.assign(h.L + 1, 0);
+    h.p_count.assign(h.L + 1, 0);
+    const int dlo = h.d_top < 0 ? h.L + 1 : h.d_top;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int d = dlo; d <= h.L; ++d) {
+        const auto& lst = pass == 0 ? P.far[d] : P.near[d];
+        const int gid0 = (1 << d) - 1;
+        (pass == 0 ? h.s_first : h.p_first)[d] = int(h.blk_row_h.size());
+        for (size_t i = 0; i < lst.size(); i += 2)
+          if (lst[i] <= lst[i + 1]) {
+            h.blk_row_h.push_back(gid0 + lst[i]);
+            h.blk_col_h.push_back(gid0 + lst[i + 1]);
+          }
+        (pass == 0 ? h.s_count : h.p_count)[d] =
+            int(h.blk_row_h.size()) - (pass == 0 ? h.s_first : h.p_first)[d];
+      }
+    h.nblk = int(h.blk_row_h.size());
+    h.blk_row = upload(h, h.blk_row_h);
+    h.blk_col = upload(h, h.blk_col_h);
+    h.sview.resize(h.L + 1);
+    h.pview.resize(h.L + 1);
+    h.coarse_launch.resize(h.L + 1);
+    if (h.d_top >= 0) {
+      for (int d = h.d_top; d <= h.L; ++d) {
+        h.sview[d] = make_view(h, d, h.s_first[d], h.s_count[d]);
+        h.pview[d] = make_view(h, d, h.p_first[d], h.p_count[d]);
+      }
+      std::vector<const View*> vs;
+      for (int d = h.d_top; d <= h.L; ++d) vs.push_back(&h.sview[d]);
+      h.fine_launch = make_launch(h, vs);
+      for (int d = h.d_top; d <= h.L; ++d) {
+        std::vector<const View*> cv;
+        for (int q = h.d_top; q < d; ++q) cv.push_back(&h.sview[q]);
+        cv.push_back(&h.pview[d]);
+        cv.push_back(&h.sview[d]);
+        h.coarse_launch[d] = make_launch(h, cv);
+      }
+    }
+
+    // ---- close leaf pairs for the near field
+    {
+      const auto& lst = P.near[h.L];
+      std::vector<int> prow, pcol;
+      for (size_t i = 0; i < lst.size(); i += 2)
+        if (lst[i] <= lst[i + 1]) {
+          prow.push_back(lst[i]);
+          pcol.push_back(lst[i + 1]);
+        }
+      NearField& nf = h.near;
+      nf.npairs = int(prow.size());
+      std::vector<int> task, rtp(h.nleaf + 1, 0), cptr(h.nleaf + 1, 0), cpair;
+      for (int p = 0; p < nf.npairs;) {
+        int e2 = p;
+        while (e2 < nf.npairs && prow[e2] == prow[p]) ++e2;
+        for (int c = p; c < e2; c += NEAR_CHUNK) {
+          task.push_back(prow[p]);
+          task.push_back(c);
+          task.push_back(std::min(e2, c + NEAR_CHUNK));
+          rtp[prow[p] + 1]++;
+        }
+        p = e2;
+      }
+      for (int i = 0; i < h.nleaf; ++i) rtp[i + 1] += rtp[i];
+      for (int p = 0; p < nf.npairs; ++p)
+        if (pcol[p] != prow[p]) cptr[pcol[p] + 1]++;
+      for (int i = 0; i < h.nleaf; ++i) cptr[i + 1] += cptr[i];
+      cpair.resize(cptr[h.nleaf]);
+      std::vector<int> fill(cptr.begin(), cptr.end() - 1);
+      for (int p = 0; p < nf.npairs; ++p)
+        if (pcol[p] != prow[p]) cpair[fill[pcol[p]]++] = p;
+      nf.ntasks = int(task.size() / 3);
+      nf.task = upload(h, task);
+      nf.pair_col = upload(h, pcol);
+      nf.row_task_ptr = upload(h, rtp);
+      nf.col_ptr = upload(h, cptr);
+      nf.col_pair = upload(h, cpair);
+      nf.ld = (h.leaf_max + 7) / 8 * 8;
+    }
+
+    // ---- workspace
+    const size_t rr = size_t(h.r);
+    h.xall = h.arena.make<double>(size_t(h.ngid) * rr);
+    h.yall = h.arena.make<double>(size_t(h.ngid) * rr);
+    h.partial = h.arena.make<double>(size_t(std::max(h.max_tasks, 1)) * rr);
+    h.colpart = h.arena.make<double>(size_t(std::max(h.nblk, 1)) * rr);
+    h.near_partial = h.arena.make<double>(size_t(std::max(h.near.ntasks, 1)) * h.near.ld);
+    h.near_colpart = h.arena.make<double>(size_t(std::max(h.near.npairs, 1)) * h.near.ld);
+    h.vtree = h.arena.make<double>(h.n);
+    h.vtree2 = h.arena.make<double>(h.n);
+    h.flags = h.arena.make<int>(4);
+    h.dot_part = h.arena.make<double>(8 * 512);
+    hip_check(hipMemsetAsync(h.flags, 0, 4 * sizeof(int), h.stream), "memset");
+    hip_check(hipMemsetAsync(h.yall, 0, size_t(h.ngid) * rr * sizeof(double), h.stream), "memset");
+
+    // ---- FP64 operator storage
+    const int64_t te = tile_elems(h.T);
+    PrecData& p64 = h.prec[P64];
+    p64.Qr = h.arena.make<double>(size_t(h.n) * rr);
+    p64.Qc = h.arena.make<double>(size_t(h.n) * rr);
+    p64.E = h.arena.make<double>(size_t(h.ngid) * te);
+    p64.blk = h.arena.make<double>(size_t(std::max(h.nblk, 1)) * te);
+    hip_check(hipMemsetAsync(p64.E, 0, size_t(h.ngid) * te * sizeof(double), h.stream), "memset");
+    hip_check(hipMemsetAsync(p64.blk, 0, size_t(std::max(h.nblk, 1)) * te * sizeof(double), h.stream),
+              "memset");
+    h.R = h.arena.make<double>(size_t(h.ngid) * rr * rr);
+
+    // ---- setup kernels
+    launch_leaf_basis_qr(h);
+    if (h.d_top >= 0) {
+      for (int d = h.L - 1; d >= h.d_top; --d) launch_transfer_qr(h, d);
+      for (int d = h.d_top; d <= h.L; ++d) launch_couplings(h, d);
+    }
+    hip_check(hipStreamSynchronize(h.stream), "build");
+    h.arena.release(h.R);
+    h.R = nullptr;
+    p64.ready = true;
+  } catch (const std::bad_alloc&) {
+    delete hp;
+    return fail(H2MG_ERR_OOM, "device allocation failed while building the H2 matrix");
+  } catch (const std::exception& ex) {
+    delete hp;
+    return fail(H2MG_ERR_HIP, "%s", ex.what());
+  }
+  *out = hp;
+  return H2MG_OK;
+}
+
+h2mg_status setup_mg(H2& h, int precision_mask) {
+  try {
+    if (!h.mg_built) {
+      if (h.d_top >= 0) {
+        launch_pi_leaf(h);
+        // child block lookup: (row gid, col gid) -> block id, per depth
+        for (int d = h.L - 1; d >= h.d_top; --d) {
+          std::unordered_map<int64_t, int> idx;
+          auto key = [](int a, int b) { return (int64_t(a) << 32) | uint32_t(b); };
+          for (int pass = 0; pass < 2; ++pass) {
+            const int f = pass == 0 ? h.s_first[d + 1] : h.p_first[d + 1];
+            const int c = pass == 0 ? h.s_count[d + 1] : h.p_count[d + 1];
+            for (int b = f; b < f + c; ++b) idx[key(h.blk_row_h[b], h.blk_col_h[b])] = b;
+          }
+          std::vector<int> cmap;
+          cmap.reserve(size_t(h.p_count[d]) * 4);
+          for (int b = h.p_first[d]; b < h.p_first[d] + h.p_count[d]; ++b) {
+            const int gs = h.blk_row_h[b], gt = h.blk_col_h[b];
+            for (int a = 0; a < 2; ++a)
+              for (int bb = 0; bb < 2; ++bb) {
+                const int cs = 2 * gs + 1 + a, ct = 2 * gt + 1 + bb;
+                if (cs <= ct) {
+                  auto it = idx.find(key(cs, ct));
+                  if (it == idx.end()) throw std::runtime_error("child block not found");
+                  cmap.push_back(it->second);
+                } else {
+                  auto it = idx.find(key(ct, cs));
+                  if (it == idx.end()) throw std::runtime_error("child block not found");
+                  cmap.push_back(-it->second - 1);
+                }
+              }
+          }
+          int* dmap = upload(h, cmap);
+          launch_pi_upper(h, d, dmap);
+          hip_check(hipStreamSynchronize(h.stream), "pi_upper");
+          h.arena.release(dmap);
+        }
+        h.Nl = int64_t(1 << h.d_top) * h.r;
+        h.levels = h.L - h.d_top + 2;
+      } else {
+        if (h.n > 32768)
+          return fail(H2MG_ERR_INVALID_ARG,
+                      "no far blocks: the dense direct solve is limited to n <= 32768");
+        h.Nl = h.n;
+        h.levels = 1;
+      }
+      h.chol = h.arena.make<double>(size_t(h.Nl) * h.Nl);
+      hip_check(hipMemsetAsync(h.chol, 0, size_t(h.Nl) * h.Nl * sizeof(double), h.stream), "memset");
+      if (h.d_top >= 0) launch_assemble_dense(h, h.chol, h.Nl);
+      else launch_assemble_kernel_dense(h, h.chol, h.Nl);
+      hip_check(hipMemsetAsync(h.flags, 0, 4 * sizeof(int), h.stream), "memset");
+      launch_potrf(h, h.chol, h.Nl);
+      int flags[4];
+      hip_check(hipMemcpyAsync(flags, h.flags, sizeof(flags), hipMemcpyDeviceToHost, h.stream), "flags");
+      hip_check(hipStreamSynchronize(h.stream), "setup_mg");
+      if (flags[0]) {
+        h.arena.release(h.chol);
+        h.chol = nullptr;
+        return fail(H2MG_ERR_NOT_SPD, "the coarsest operator (order %lld) is not positive definite",
+                    (long long)h.Nl);
+      }
+      h.mg_built = true;
+    }
+    for (int p = P32; p <= P16; ++p) {
+      if (!(precision_mask & (1 << p)) || h.prec[p].ready) continue;
+      const size_t eb = elem_bytes(p);
+      const int64_t te = tile_elems(h.T);
+      PrecData& pd = h.prec[p];
+      pd.Qr = h.arena.alloc(size_t(h.n) * h.r * eb);
+      pd.Qc = h.arena.alloc(size_t(h.n) * h.r * eb);
+      pd.E = h.arena.alloc(size_t(h.ngid) * te * eb);
+      pd.blk = h.arena.alloc(size_t(std::max(h.nblk, 1)) * te * eb);
+      hip_check(hipMemsetAsync(pd.E, 0, size_t(h.ngid) * te * eb, h.stream), "memset");
+      hip_check(hipMemsetAsync(pd.blk, 0, size_t(std::max(h.nblk, 1)) * te * eb, h.stream), "memset");
+      launch_cast_precision(h, p);
+      hip_check(hipStreamSynchronize(h.stream), "cast");
+      pd.ready = true;
+    }
+  } catch (const std::bad_alloc&) {
+    return fail(H2MG_ERR_OOM, "device allocation failed while building the hierarchy");
+  } catch (const std::exception& ex) {
+    return fail(H2MG_ERR_HIP, "%s", ex.what());
+  }
+  return H2MG_OK;
+}
+
+}  // namespace h2mg

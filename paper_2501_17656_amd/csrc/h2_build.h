@@ -1,0 +1,35 @@
+// Construction, hierarchy setup, products and the solver of an H2 handle.
+#pragma once
+#include "h2_impl.h"
+
+namespace h2mg {
+
+h2mg_status build_h2(const double* points_dev, int64_t n, int dim, const h2mg_kernel* kernel,
+                     const h2mg_build_opts* opts, hipStream_t stream, H2** out);
+h2mg_status setup_mg(H2& h, int precision_mask);
+
+// Products in precision p (vectors double for P64, float otherwise).
+// Fine level, tree order: out = alpha * A_H2 x + beta * add (add may be null).
+void apply_fine(H2& h, int p, const void* xt, void* out, double alpha, const void* add,
+                double beta);
+// Level k >= 2 (depth L - k + 2), coefficient order: y = A_k x.
+void apply_coarse(H2& h, int p, int k, const void* x, void* y);
+void apply_level(H2& h, int p, int k, const void* x, void* y);
+// r_next = U_k^T r (level k to k+1); level-1 vectors in tree order.
+void restrict_level(H2& h, int p, int k, const void* r, void* r_next);
+// e = alpha * U_k e_next + beta * add.
+void prolong_level(H2& h, int p, int k, const void* e_next, void* e, const void* add, double beta);
+
+struct SolveParams {
+  int n_fine = 1, n_coarse = 40;
+  double rtol = 1e-8;
+  int max_cycles = 500;
+  int precision = 0;
+  bool use_x0 = false;
+};
+// Solve A_H2 x = b; b, x device, user order.  Fills info.
+h2mg_status solve(H2& h, const double* b, double* x, const SolveParams& sp, h2mg_solve_info* info);
+// One FP64 V-cycle from x0 (user order).
+h2mg_status vcycle_once(H2& h, const double* x0, const double* b, double* x_out, const SolveParams& sp);
+
+}  // namespace h2mg

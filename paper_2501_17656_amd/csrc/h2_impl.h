@@ -1,0 +1,186 @@
+// Internal definition of the H2 handle and the launchers of every kernel.
+//
+// Numbering.  Cluster j at depth d has the global id gid = 2^d - 1 + j.
+// Coefficient vectors of all depths share one buffer indexed gid * r.
+// Stored r x r blocks (far couplings S and projected close blocks Pi of
+// every depth) live in one array of tiles (device_common.h), upper triangle
+// only (row cluster <= column cluster): the operators are symmetric, so a
+// stored off-diagonal block B contributes B x_t to row s and B^T x_s to row t.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "device_common.h"
+#include "h2mg.h"
+#include "plan.h"
+
+namespace h2mg {
+
+const char* last_error_cstr();
+void clear_error();
+
+enum Prec { P64 = 0, P32 = 1, P16 = 2 };   // FP64, FP32, BF16 operator storage
+inline size_t elem_bytes(int p) { return p == P64 ? 8 : p == P32 ? 4 : 2; }
+
+// Device allocation owned by a handle.
+struct Arena {
+  std::vector<std::pair<void*, size_t>> ptrs;
+  size_t bytes = 0;
+  void* alloc(size_t nbytes);          // throws std::bad_alloc on failure
+  template <typename T> T* make(size_t n) { return static_cast<T*>(alloc(n * sizeof(T))); }
+  void release(void* p);
+  ~Arena();
+};
+
+// A symmetric block operator over one depth: tasks are runs of at most C
+// stored blocks of one block row, processed by one wave each.
+struct View {
+  int depth = 0;
+  int ntasks = 0;
+  std::vector<int> task;               // host: 3 ints per task (row gid, b0, b1)
+  int* row_task_ptr = nullptr;         // device: 2^depth + 1, offsets into this view's tasks
+  int* col_ptr = nullptr;              // device: 2^depth + 1
+  int* col_blk = nullptr;              // device: stored off-diagonal blocks by column
+};
+
+// One GEMV launch over the concatenated tasks of several views.
+struct Launch {
+  int ntasks = 0;
+  int* task = nullptr;                 // device
+  std::vector<int> base;               // task base of each view in the list
+};
+
+// Close leaf pairs (s <= t) for the on-the-fly near field.
+struct NearField {
+  int npairs = 0;
+  int ntasks = 0;
+  int* task = nullptr;                 // device: (row leaf, p0, p1)
+  int* pair_col = nullptr;             // device: column leaf of each pair
+  int* row_task_ptr = nullptr;         // device: nleaf + 1
+  int* col_ptr = nullptr;              // device: nleaf + 1
+  int* col_pair = nullptr;             // device: off-diagonal pairs by column leaf
+  int ld = 0;                          // padded leaf length of partial buffers
+};
+
+struct PrecData {                      // operator storage in one precision
+  bool ready = false;
+  void* Qr = nullptr;                  // N x r row-major, tree order
+  void* Qc = nullptr;                  // per leaf: r x n_leaf (column j contiguous)
+  void* E = nullptr;                   // transfer tiles by child gid
+  void* blk = nullptr;                 // S and Pi tiles by block id
+};
+
+struct H2 {
+  Plan plan;
+  KernelParams kp{};
+  int n = 0, dim = 0, r = 0, m = 0, L = 0, d_top = -1, T = 1;
+  int nleaf = 0, leaf_max = 0;
+  int ngid = 0;                        // 2^(L+1) - 1
+  hipStream_t stream = nullptr;
+  Arena arena;
+
+  // geometry
+  double* pts = nullptr;               // tree-ordered points, N x dim
+  int64_t* perm = nullptr;             // tree position -> user index
+  int* leaf_off = nullptr;             // nleaf + 1
+  double* cbox = nullptr;              // per gid: dim centres
+  double* hbox = nullptr;              // per gid: dim floored half-widths
+  double* nodes1d = nullptr;           // m Chebyshev nodes
+  double* R = nullptr;                 // per gid r x r (setup only, freed after)
+
+  // stored blocks: S of depth d in [s_first[d], s_first[d] + s_count[d]),
+  // Pi of depth d in [p_first[d], p_first[d] + p_count[d])
+  int nblk = 0;
+  std::vector<int> blk_row_h, blk_col_h;   // gids
+  int* blk_row = nullptr;
+  int* blk_col = nullptr;
+  std::vector<int> s_first, s_count, p_first, p_count;
+  std::vector<View> sview, pview;
+  NearField near;
+  PrecData prec[3];
+
+  // launches: fine apply (S of all depths), coarse apply at depth d
+  Launch fine_launch;
+  std::vector<Launch> coarse_launch;   // indexed by depth
+  int max_tasks = 0;
+
+  // workspace (sized for FP64; reused by FP32 kernels)
+  double* xall = nullptr;              // ngid * r
+  double* yall = nullptr;
+  double* partial = nullptr;           // max_tasks * r
+  double* colpart = nullptr;           // nblk * r
+  double* near_partial = nullptr;      // near.ntasks * ld
+  double* near_colpart = nullptr;      // near.npairs * ld
+  double* vtree = nullptr;             // N scratch (tree order)
+  double* vtree2 = nullptr;
+
+  // multigrid
+  bool mg_built = false;
+  int levels = 1;
+  int64_t Nl = 0;                      // coarsest size
+  double* chol = nullptr;              // Nl x Nl column-major, lower factor
+  int* flags = nullptr;                // device flags (0: not SPD, 1: non-finite)
+  double* dot_part = nullptr;          // reduction partials (several slots)
+  std::vector<double> history;
+
+  int64_t level_size(int k) const {    // k = 1..levels
+    if (k == 1) return n;
+    const int d = L - k + 2;
+    return (int64_t(1) << d) * r;
+  }
+  int level_depth(int k) const { return L - k + 2; }
+};
+
+// ------------------------------------------------------------ setup kernels
+void launch_leaf_basis_qr(H2& h);                 // Q (FP64), R of leaves
+void launch_transfer_qr(H2& h, int d);            // E of depth d+1, R of depth d
+void launch_couplings(H2& h, int d);              // S tiles of depth d
+void launch_pi_leaf(H2& h);                       // Pi tiles of depth L
+void launch_pi_upper(H2& h, int d, const int* child_map);   // Pi tiles of depth d < L
+void launch_assemble_dense(H2& h, double* A, int64_t lda);  // depth d_top blocks
+void launch_assemble_kernel_dense(H2& h, double* A, int64_t lda);  // no far blocks
+void launch_potrf(H2& h, double* A, int64_t N);   // blocked Cholesky, sets flags[0]
+void launch_cast_precision(H2& h, int p);         // FP64 -> FP32 / BF16 copies
+
+// ------------------------------------------------------------ apply kernels
+// All vectors are in the precision's vector type: double (P64) or float.
+void launch_gemv(H2& h, int p, const Launch& l, const void* x_all);
+void launch_reduce(H2& h, int p, int d, const View* v0, int base0, const View* v1,
+                   int base1, const void* addend, void* out);
+void launch_transfer_up(H2& h, int p, int d, const void* xchild, void* xpar);
+void launch_transfer_down(H2& h, int p, int d, const void* ypar, void* ychild,
+                          const void* addend);
+void launch_leaf_up(H2& h, int p, const void* xtree, void* xhat);
+void launch_near(H2& h, int p, const void* xtree);
+// out = alpha * Q yhat + beta * add (tree order).
+void launch_leaf_down(H2& h, int p, const void* yhat, void* out, double alpha, const void* add,
+                      double beta);
+// out[idx] = alpha * (Q yhat + near) + beta * add[idx], idx = tree position or
+// perm[tree position] when to_user.
+void launch_fine_reduce(H2& h, int p, const void* yhat, void* out, bool to_user,
+                        double alpha, const void* add, double beta);
+
+// ------------------------------------------------------------ vector kernels
+void launch_gather(H2& h, const double* user, double* tree);     // tree[i] = user[perm[i]]
+void launch_scatter(H2& h, const double* tree, double* user);    // user[perm[i]] = tree[i]
+void launch_copy(H2& h, int p, const void* src, void* dst, int64_t n);
+void launch_cast(H2& h, int pdst, void* dst, int psrc, const void* src, int64_t n);
+// y = a*x + b*y  (vector type of p)
+void launch_axpby(H2& h, int p, int64_t n, double a, const void* x, double b, void* y);
+// Partial sums of x.y (FP64 accumulation) into part[0 .. nparts(n)).
+int dot_parts(int64_t n);
+void launch_dot(H2& h, int p, int64_t n, const void* x, const void* y, double* part);
+// CG step halves; scalars are read from partial-sum arrays on the device.
+void launch_cg_update(H2& h, int p, int64_t n, void* e, const void* pv, void* s,
+                      const void* q, const double* gamma_part, const double* delta_part,
+                      double* gamma_new_part);
+void launch_cg_pupdate(H2& h, int p, int64_t n, void* pv, const void* s,
+                       const double* gamma_old_part, const double* gamma_new_part);
+void launch_chol_solve(H2& h, const double* L, int64_t N, double* x);   // in place
+void launch_check_finite(H2& h, int p, int64_t n, const void* x);      // sets flags[1]
+
+}  // namespace h2mg

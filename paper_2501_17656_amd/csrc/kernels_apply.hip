@@ -1,0 +1,579 @@
+// Apply kernels of the H2 matvec and of the restricted operators.
+//
+// Section 3.1: y = A x is computed by the upsweep x_i = V_i x_{i-1} (leaf
+// bases then transfers), the per-level coupling products, the downsweep
+// y_{i-1} = D_i x_{i-1} + U_i y_i, and the close (near-field) leaf blocks
+// y = D x + U_1 y_1.  Section 3.3: a restricted operator A_k has the same
+// structure with the projected close blocks of its depth in place of D.
+//
+// Every r x r block product is HBM-bound (one FMA per stored word), so the
+// blocks are stored once (upper triangle, symmetric operators) in the tiled
+// layout of device_common.h and each wave streams one run of blocks of a
+// block row: it accumulates B x_t for the row in registers and emits
+// B^T x_s for the block's column, which a reduce pass gathers in a fixed
+// order (deterministic, no atomics).
+#include <hip/hip_runtime.h>
+
+#include <stdexcept>
+#include <string>
+
+#include "h2_impl.h"
+
+namespace h2mg {
+
+namespace {
+
+void check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename Tv> __device__ inline Tv zero() { return Tv(0); }
+
+// ------------------------------------------------------------ symmetric block GEMV
+// One wave per task (row gid s, blocks [b0, b1)).  partial[task] = sum_b B_b x_{col b};
+// colpart[b] = B_b^T x_s for every off-diagonal block.
+template <int T, typename Tb, typename Tv>
+__global__ __launch_bounds__(256) void k_bsr_gemv(const int* __restrict__ tasks, int ntasks,
+                                                  const Tb* __restrict__ blk,
+                                                  const int* __restrict__ blk_col,
+                                                  const Tv* __restrict__ x, Tv* __restrict__ partial,
+                                                  Tv* __restrict__ colpart, int r) {
+  const int wave = int((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (wave >= ntasks) return;
+  const int lane = threadIdx.x & 63;
+  const int a = lane >> 3, b = lane & 7;
+  const int row = tasks[3 * wave], b0 = tasks[3 * wave + 1], b1 = tasks[3 * wave + 2];
+  Tv xs[T], acc[T];
+#pragma unroll
+  for (int u = 0; u < T; ++u) {
+    const int i = a * T + u;
+    xs[u] = i < r ? x[int64_t(row) * r + i] : zero<Tv>();
+    acc[u] = zero<Tv>();
+  }
+  for (int bi = b0; bi < b1; ++bi) {
+    const int col = blk_col[bi];
+    Tv xt[T];
+#pragma unroll
+    for (int v = 0; v < T; ++v) {
+      const int j = b * T + v;
+      xt[v] = j < r ? x[int64_t(col) * r + j] : zero<Tv>();
+    }
+    Tv B[T * T];
+    load_subtile<T, Tb, Tv>(blk + int64_t(bi) * tile_elems(T), lane, B);
+#pragma unroll
+    for (int u = 0; u < T; ++u)
+#pragma unroll
+      for (int v = 0; v < T; ++v) acc[u] += B[u * T + v] * xt[v];
+    if (col != row) {
+      Tv z[T];
+#pragma unroll
+      for (int v = 0; v < T; ++v) {
+        Tv s = zero<Tv>();
+#pragma unroll
+        for (int u = 0; u < T; ++u) s += B[u * T + v] * xs[u];
+        s += shfl_xor(s, 8);
+        s += shfl_xor(s, 16);
+        s += shfl_xor(s, 32);
+        z[v] = s;
+      }
+      if (a == 0) {
+#pragma unroll
+        for (int v = 0; v < T; ++v) {
+          const int j = b * T + v;
+          if (j < r) colpart[int64_t(bi) * r + j] = z[v];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < T; ++u) {
+    Tv s = acc[u];
+    s += shfl_xor(s, 1);
+    s += shfl_xor(s, 2);
+    s += shfl_xor(s, 4);
+    acc[u] = s;
+  }
+  if (b == 0) {
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+      const int i = a * T + u;
+      if (i < r) partial[int64_t(wave) * r + i] = acc[u];
+    }
+  }
+}
+
+struct RedSrc {
+  const int* row_task_ptr;
+  const int* col_ptr;
+  const int* col_blk;
+  int base;
+};
+
+// out[s] = addend[s] + sum of task partials of row s + sum of column
+// contributions of blocks whose column is s, in a fixed order.
+template <typename Tv>
+__global__ __launch_bounds__(256) void k_reduce(int nrows, RedSrc s0, RedSrc s1, int nsrc,
+                                                const Tv* __restrict__ partial,
+                                                const Tv* __restrict__ colpart,
+                                                const Tv* __restrict__ addend, Tv* __restrict__ out,
+                                                int r) {
+  const int row = int((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int i = threadIdx.x & 63;
+  if (row >= nrows || i >= r) return;
+  Tv v = addend ? addend[int64_t(row) * r + i] : zero<Tv>();
+  for (int q = 0; q < nsrc; ++q) {
+    const RedSrc& s = q == 0 ? s0 : s1;
+    for (int t = s.row_task_ptr[row]; t < s.row_task_ptr[row + 1]; ++t)
+      v += partial[int64_t(s.base + t) * r + i];
+    for (int c = s.col_ptr[row]; c < s.col_ptr[row + 1]; ++c)
+      v += colpart[int64_t(s.col_blk[c]) * r + i];
+  }
+  out[int64_t(row) * r + i] = v;
+}
+
+// ------------------------------------------------------------ transfers
+// xpar[s] = sum_c E_c^T xchild[c] over the two children of s (depth d -> d+1 kids).
+template <int T, typename Tb, typename Tv>
+__global__ __launch_bounds__(256) void k_transfer_up(int nparents, int gidc0,
+                                                     const Tb* __restrict__ E,
+                                                     const Tv* __restrict__ xchild,
+                                                     Tv* __restrict__ xpar, int r) {
+  const int s = int((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (s >= nparents) return;
+  const int lane = threadIdx.x & 63;
+  const int a = lane >> 3, b = lane & 7;
+  Tv z[T];
+#pragma unroll
+  for (int v = 0; v < T; ++v) z[v] = zero<Tv>();
+  for (int q = 0; q < 2; ++q) {
+    const int c = 2 * s + q;
+    Tv xs[T];
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+      const int i = a * T + u;
+      xs[u] = i < r ? xchild[int64_t(c) * r + i] : zero<Tv>();
+    }
+    Tv B[T * T];
+    load_subtile<T, Tb, Tv>(E + int64_t(gidc0 + c) * tile_elems(T), lane, B);
+#pragma unroll
+    for (int v = 0; v < T; ++v)
+#pragma unroll
+      for (int u = 0; u < T; ++u) z[v] += B[u * T + v] * xs[u];
+  }
+#pragma unroll
+  for (int v = 0; v < T; ++v) {
+    Tv s2 = z[v];
+    s2 += shfl_xor(s2, 8);
+    s2 += shfl_xor(s2, 16);
+    s2 += shfl_xor(s2, 32);
+    z[v] = s2;
+  }
+  if (a == 0) {
+#pragma unroll
+    for (int v = 0; v < T; ++v) {
+      const int j = b * T + v;
+      if (j < r) xpar[int64_t(s) * r + j] = z[v];
+    }
+  }
+}
+
+// ychild[c] = addend[c] + E_c ypar[c / 2] for every child c at depth d+1.
+template <int T, typename Tb, typename Tv>
+__global__ __launch_bounds__(256) void k_transfer_down(int nchildren, int gidc0,
+                                                       const Tb* __restrict__ E,
+                                                       const Tv* __restrict__ ypar,
+                                                       Tv* __restrict__ ychild,
+                                                       const Tv* __restrict__ addend, int r) {
+  const int c = int((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (c >= nchildren) return;
+  const int lane = threadIdx.x & 63;
+  const int a = lane >> 3, b = lane & 7;
+  const int s = c >> 1;
+  Tv xt[T];
+#pragma unroll
+  for (int v = 0; v < T; ++v) {
+    const int j = b * T + v;
+    xt[v] = j < r ? ypar[int64_t(s) * r + j] : zero<Tv>();
+  }
+  Tv B[T * T];
+  load_subtile<T, Tb, Tv>(E + int64_t(gidc0 + c) * tile_elems(T), lane, B);
+  Tv acc[T];
+#pragma unroll
+  for (int u = 0; u < T; ++u) {
+    Tv s2 = zero<Tv>();
+#pragma unroll
+    for (int v = 0; v < T; ++v) s2 += B[u * T + v] * xt[v];
+    s2 += shfl_xor(s2, 1);
+    s2 += shfl_xor(s2, 2);
+    s2 += shfl_xor(s2, 4);
+    acc[u] = s2;
+  }
+  if (b == 0) {
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+      const int i = a * T + u;
+      if (i < r)
+        ychild[int64_t(c) * r + i] = acc[u] + (addend ? addend[int64_t(c) * r + i] : zero<Tv>());
+    }
+  }
+}
+
+// ------------------------------------------------------------ leaf bases
+// xhat[leaf] = Q_leaf^T x_leaf; 4 waves split the leaf's rows.
+template <typename Tq, typename Tv>
+__global__ __launch_bounds__(256) void k_leaf_up(const int* __restrict__ leaf_off,
+                                                 const Tq* __restrict__ Qr,
+                                                 const Tv* __restrict__ x, Tv* __restrict__ xhat,
+                                                 int r) {
+  __shared__ Tv red[4][64];
+  const int leaf = blockIdx.x;
+  const int w = threadIdx.x >> 6, j = threadIdx.x & 63;
+  const int s0 = leaf_off[leaf], n = leaf_off[leaf + 1] - s0;
+  Tv acc = zero<Tv>();
+  if (j < r)
+    for (int i = w; i < n; i += 4)
+      acc += ld_as<Tv, Tq>(Qr[int64_t(s0 + i) * r + j]) * x[s0 + i];
+  red[w][j] = acc;
+  __syncthreads();
+  if (w == 0 && j < r) xhat[int64_t(leaf) * r + j] = (red[0][j] + red[1][j]) + (red[2][j] + red[3][j]);
+}
+
+// ------------------------------------------------------------ near field
+// Close leaf pairs (s <= t) evaluated on the fly from the points: one
+// workgroup per task (row leaf s, pairs [p0, p1)), 16 x 16 threads, each
+// thread an 8 x 8 sub-tile of a 128 x 128 tile.  Row sums go to
+// partial[task], column sums of off-diagonal pairs to colpart[pair].
+template <typename Tv, typename Te>
+__global__ __launch_bounds__(256) void k_near(const int* __restrict__ tasks,
+                                              const int* __restrict__ pair_col,
+                                              const int* __restrict__ leaf_off,
+                                              const double* __restrict__ pts, int dim,
+                                              const Tv* __restrict__ x, Tv* __restrict__ partial,
+                                              Tv* __restrict__ colpart, int ld, KernelParams kp) {
+  constexpr int TILE = 128;
+  __shared__ double ps[TILE * 3];
+  __shared__ double pt[TILE * 3];
+  __shared__ Tv xsl[TILE];
+  __shared__ Tv xtl[TILE];
+  __shared__ Tv red[16][TILE + 1];
+  const int task = blockIdx.x, tid = threadIdx.x;
+  const int ti = tid >> 4, tj = tid & 15;
+  const int sl = tasks[3 * task], p0 = tasks[3 * task + 1], p1 = tasks[3 * task + 2];
+  const int s0 = leaf_off[sl], ns = leaf_off[sl + 1] - s0;
+  for (int rt = 0; rt < ns; rt += TILE) {
+    const int nrow = min(TILE, ns - rt);
+    __syncthreads();
+    for (int idx = tid; idx < TILE * dim; idx += 256) {
+      const int i = idx / dim;
+      ps[idx] = pts[int64_t(s0 + rt + min(i, nrow - 1)) * dim + idx % dim];
+    }
+    for (int i = tid; i < TILE; i += 256) xsl[i] = i < nrow ? x[s0 + rt + i] : zero<Tv>();
+    __syncthreads();
+    double pi[8][3];
+    Tv xi[8], racc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = ti + 16 * u;
+      for (int a = 0; a < 3; ++a) pi[u][a] = a < dim ? ps[i * dim + a] : 0.0;
+      xi[u] = xsl[i];
+      racc[u] = zero<Tv>();
+    }
+    for (int p = p0; p < p1; ++p) {
+      const int tl = pair_col[p];
+      const bool diag = tl == sl;
+      const int t0 = leaf_off[tl], nt = leaf_off[tl + 1] - t0;
+      for (int ct = 0; ct < nt; ct += TILE) {
+        const int ncol = min(TILE, nt - ct);
+        __syncthreads();
+        for (int idx = tid; idx < TILE * dim; idx += 256) {
+          const int j = idx / dim;
+          pt[idx] = pts[int64_t(t0 + ct + min(j, ncol - 1)) * dim + idx % dim];
+        }
+        for (int j = tid; j < TILE; j += 256) xtl[j] = j < ncol ? x[t0 + ct + j] : zero<Tv>();
+        __syncthreads();
+#pragma unroll 2
+        for (int v = 0; v < 8; ++v) {
+          const int j = tj + 16 * v;
+          double pj[3];
+          for (int a = 0; a < 3; ++a) pj[a] = a < dim ? pt[j * dim + a] : 0.0;
+          const Tv xj = xtl[j];
+          Tv cacc = zero<Tv>();
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            double r2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+              const double dx = pi[u][a] - pj[a];
+              r2 += dx * dx;
+            }
+            Tv k = Tv(kernel_r2(kp, Te(r2)));
+            if (diag && rt + ti + 16 * u == ct + j) k += Tv(kp.shift);
+            racc[u] += k * xj;
+            cacc += k * xi[u];
+          }
+          red[ti][j] = cacc;
+        }
+        if (!diag) {
+          __syncthreads();
+          if (tid < TILE) {
+            Tv s = zero<Tv>();
+#pragma unroll
+            for (int q = 0; q < 16; ++q) s += red[q][tid];
+            if (tid < ncol) {
+              Tv* dst = colpart + int64_t(p) * ld + ct + tid;
+              *dst = rt == 0 ? s : *dst + s;
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      Tv s = racc[u];
+      s += shfl_xor(s, 1);
+      s += shfl_xor(s, 2);
+      s += shfl_xor(s, 4);
+      s += shfl_xor(s, 8);
+      racc[u] = s;
+    }
+    if (tj == 0) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = ti + 16 * u;
+        if (i < nrow) partial[int64_t(task) * ld + rt + i] = racc[u];
+      }
+    }
+  }
+}
+
+// out[idx(i)] = alpha * (Q_leaf yhat_leaf + near sums)_i + beta * add[idx(i)]
+// for the rows i of one leaf per workgroup; idx = i or perm[i].
+template <typename Tq, typename Tv>
+__global__ __launch_bounds__(256) void k_fine_reduce(
+    const int* __restrict__ leaf_off, const Tq* __restrict__ Qc, const Tv* __restrict__ yhat, int r,
+    const int* __restrict__ row_task_ptr, const int* __restrict__ col_ptr,
+    const int* __restrict__ col_pair, const Tv* __restrict__ partial,
+    const Tv* __restrict__ colpart, int ld, const int64_t* __restrict__ perm, Tv* __restrict__ out,
+    double alpha, const Tv* __restrict__ add, double beta) {
+  __shared__ Tv yh[64];
+  const int leaf = blockIdx.x;
+  const int s0 = leaf_off[leaf], n = leaf_off[leaf + 1] - s0;
+  if (threadIdx.x < r) yh[threadIdx.x] = yhat[int64_t(leaf) * r + threadIdx.x];
+  __syncthreads();
+  const int t0 = row_task_ptr[leaf], t1 = row_task_ptr[leaf + 1];
+  const int c0 = col_ptr[leaf], c1 = col_ptr[leaf + 1];
+  const Tq* Q = Qc + int64_t(s0) * r;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    Tv v = zero<Tv>();
+    for (int j = 0; j < r; ++j) v += ld_as<Tv, Tq>(Q[int64_t(j) * n + i]) * yh[j];
+    for (int t = t0; t < t1; ++t) v += partial[int64_t(t) * ld + i];
+    for (int c = c0; c < c1; ++c) v += colpart[int64_t(col_pair[c]) * ld + i];
+    const int64_t idx = perm ? perm[s0 + i] : int64_t(s0 + i);
+    Tv o = Tv(alpha) * v;
+    if (add) o += Tv(beta) * add[idx];
+    out[idx] = o;
+  }
+}
+
+// out[idx(i)] = alpha * (Q_leaf yhat_leaf)_i + beta * add[idx(i)] (prolongation
+// from the depth-L coefficients to the points; tree order).
+template <typename Tq, typename Tv>
+__global__ __launch_bounds__(256) void k_leaf_down(const int* __restrict__ leaf_off,
+                                                   const Tq* __restrict__ Qc,
+                                                   const Tv* __restrict__ yhat, int r,
+                                                   Tv* __restrict__ out, double alpha,
+                                                   const Tv* __restrict__ add, double beta) {
+  __shared__ Tv yh[64];
+  const int leaf = blockIdx.x;
+  const int s0 = leaf_off[leaf], n = leaf_off[leaf + 1] - s0;
+  if (threadIdx.x < r) yh[threadIdx.x] = yhat[int64_t(leaf) * r + threadIdx.x];
+  __syncthreads();
+  const Tq* Q = Qc + int64_t(s0) * r;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    Tv v = zero<Tv>();
+    for (int j = 0; j < r; ++j) v += ld_as<Tv, Tq>(Q[int64_t(j) * n + i]) * yh[j];
+    Tv o = Tv(alpha) * v;
+    if (add) o += Tv(beta) * add[s0 + i];
+    out[s0 + i] = o;
+  }
+}
+
+// ------------------------------------------------------------ dispatch helpers
+template <typename F>
+void dispatch_T(int T, F&& f) {
+  switch (T) {
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    default: f(std::integral_constant<int, 8>{}); break;
+  }
+}
+
+inline int grid_waves(int64_t waves) { return int((waves + 3) / 4); }
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers
+void launch_gemv(H2& h, int p, const Launch& l, const void* x_all) {
+  if (l.ntasks == 0) return;
+  dispatch_T(h.T, [&](auto Tc) {
+    constexpr int T = decltype(Tc)::value;
+    const dim3 g(grid_waves(l.ntasks)), b(256);
+    if (p == P64)
+      hipLaunchKernelGGL((k_bsr_gemv<T, double, double>), g, b, 0, h.stream, l.task, l.ntasks,
+                         static_cast<const double*>(h.prec[P64].blk), h.blk_col,
+                         static_cast<const double*>(x_all), h.partial, h.colpart, h.r);
+    else if (p == P32)
+      hipLaunchKernelGGL((k_bsr_gemv<T, float, float>), g, b, 0, h.stream, l.task, l.ntasks,
+                         static_cast<const float*>(h.prec[P32].blk), h.blk_col,
+                         static_cast<const float*>(x_all), reinterpret_cast<float*>(h.partial),
+                         reinterpret_cast<float*>(h.colpart), h.r);
+    else
+      hipLaunchKernelGGL((k_bsr_gemv<T, bf16, float>), g, b, 0, h.stream, l.task, l.ntasks,
+                         static_cast<const bf16*>(h.prec[P16].blk), h.blk_col,
+                         static_cast<const float*>(x_all), reinterpret_cast<float*>(h.partial),
+                         reinterpret_cast<float*>(h.colpart), h.r);
+  });
+  check_launch("bsr_gemv");
+}
+
+void launch_reduce(H2& h, int p, int d, const View* v0, int base0, const View* v1, int base1,
+                   const void* addend, void* out) {
+  const int nrows = 1 << d;
+  RedSrc s0{v0->row_task_ptr, v0->col_ptr, v0->col_blk, base0};
+  RedSrc s1 = v1 ? RedSrc{v1->row_task_ptr, v1->col_ptr, v1->col_blk, base1} : s0;
+  const int nsrc = v1 ? 2 : 1;
+  const dim3 g(grid_waves(nrows)), b(256);
+  if (p == P64)
+    hipLaunchKernelGGL(k_reduce<double>, g, b, 0, h.stream, nrows, s0, s1, nsrc, h.partial,
+                       h.colpart, static_cast<const double*>(addend), static_cast<double*>(out), h.r);
+  else
+    hipLaunchKernelGGL(k_reduce<float>, g, b, 0, h.stream, nrows, s0, s1, nsrc,
+                       reinterpret_cast<const float*>(h.partial),
+                       reinterpret_cast<const float*>(h.colpart),
+                       static_cast<const float*>(addend), static_cast<float*>(out), h.r);
+  check_launch("reduce");
+}
+
+void launch_transfer_up(H2& h, int p, int d, const void* xchild, void* xpar) {
+  const int npar = 1 << d;
+  const int gidc0 = (1 << (d + 1)) - 1;
+  dispatch_T(h.T, [&](auto Tc) {
+    constexpr int T = decltype(Tc)::value;
+    const dim3 g(grid_waves(npar)), b(256);
+    if (p == P64)
+      hipLaunchKernelGGL((k_transfer_up<T, double, double>), g, b, 0, h.stream, npar, gidc0,
+                         static_cast<const double*>(h.prec[P64].E), static_cast<const double*>(xchild),
+                         static_cast<double*>(xpar), h.r);
+    else if (p == P32)
+      hipLaunchKernelGGL((k_transfer_up<T, float, float>), g, b, 0, h.stream, npar, gidc0,
+                         static_cast<const float*>(h.prec[P32].E), static_cast<const float*>(xchild),
+                         static_cast<float*>(xpar), h.r);
+    else
+      hipLaunchKernelGGL((k_transfer_up<T, bf16, float>), g, b, 0, h.stream, npar, gidc0,
+                         static_cast<const bf16*>(h.prec[P16].E), static_cast<const float*>(xchild),
+                         static_cast<float*>(xpar), h.r);
+  });
+  check_launch("transfer_up");
+}
+
+void launch_transfer_down(H2& h, int p, int d, const void* ypar, void* ychild, const void* addend) {
+  const int nch = 1 << (d + 1);
+  const int gidc0 = (1 << (d + 1)) - 1;
+  dispatch_T(h.T, [&](auto Tc) {
+    constexpr int T = decltype(Tc)::value;
+    const dim3 g(grid_waves(nch)), b(256);
+    if (p == P64)
+      hipLaunchKernelGGL((k_transfer_down<T, double, double>), g, b, 0, h.stream, nch, gidc0,
+                         static_cast<const double*>(h.prec[P64].E), static_cast<const double*>(ypar),
+                         static_cast<double*>(ychild), static_cast<const double*>(addend), h.r);
+    else if (p == P32)
+      hipLaunchKernelGGL((k_transfer_down<T, float, float>), g, b, 0, h.stream, nch, gidc0,
+                         static_cast<const float*>(h.prec[P32].E), static_cast<const float*>(ypar),
+                         static_cast<float*>(ychild), static_cast<const float*>(addend), h.r);
+    else
+      hipLaunchKernelGGL((k_transfer_down<T, bf16, float>), g, b, 0, h.stream, nch, gidc0,
+                         static_cast<const bf16*>(h.prec[P16].E), static_cast<const float*>(ypar),
+                         static_cast<float*>(ychild), static_cast<const float*>(addend), h.r);
+  });
+  check_launch("transfer_down");
+}
+
+void launch_leaf_up(H2& h, int p, const void* xtree, void* xhat) {
+  const dim3 g(h.nleaf), b(256);
+  if (p == P64)
+    hipLaunchKernelGGL((k_leaf_up<double, double>), g, b, 0, h.stream, h.leaf_off,
+                       static_cast<const double*>(h.prec[P64].Qr), static_cast<const double*>(xtree),
+                       static_cast<double*>(xhat), h.r);
+  else if (p == P32)
+    hipLaunchKernelGGL((k_leaf_up<float, float>), g, b, 0, h.stream, h.leaf_off,
+                       static_cast<const float*>(h.prec[P32].Qr), static_cast<const float*>(xtree),
+                       static_cast<float*>(xhat), h.r);
+  else
+    hipLaunchKernelGGL((k_leaf_up<bf16, float>), g, b, 0, h.stream, h.leaf_off,
+                       static_cast<const bf16*>(h.prec[P16].Qr), static_cast<const float*>(xtree),
+                       static_cast<float*>(xhat), h.r);
+  check_launch("leaf_up");
+}
+
+void launch_near(H2& h, int p, const void* xtree) {
+  if (h.near.ntasks == 0) return;
+  const dim3 g(h.near.ntasks), b(256);
+  if (p == P64)
+    hipLaunchKernelGGL((k_near<double, double>), g, b, 0, h.stream, h.near.task, h.near.pair_col,
+                       h.leaf_off, h.pts, h.dim, static_cast<const double*>(xtree), h.near_partial,
+                       h.near_colpart, h.near.ld, h.kp);
+  else
+    hipLaunchKernelGGL((k_near<float, float>), g, b, 0, h.stream, h.near.task, h.near.pair_col,
+                       h.leaf_off, h.pts, h.dim, static_cast<const float*>(xtree),
+                       reinterpret_cast<float*>(h.near_partial),
+                       reinterpret_cast<float*>(h.near_colpart), h.near.ld, h.kp);
+  check_launch("near");
+}
+
+void launch_fine_reduce(H2& h, int p, const void* yhat, void* out, bool to_user, double alpha,
+                        const void* add, double beta) {
+  const dim3 g(h.nleaf), b(256);
+  const int64_t* perm = to_user ? h.perm : nullptr;
+  if (p == P64)
+    hipLaunchKernelGGL((k_fine_reduce<double, double>), g, b, 0, h.stream, h.leaf_off,
+                       static_cast<const double*>(h.prec[P64].Qc), static_cast<const double*>(yhat),
+                       h.r, h.near.row_task_ptr, h.near.col_ptr, h.near.col_pair, h.near_partial,
+                       h.near_colpart, h.near.ld, perm, static_cast<double*>(out), alpha,
+                       static_cast<const double*>(add), beta);
+  else if (p == P32)
+    hipLaunchKernelGGL((k_fine_reduce<float, float>), g, b, 0, h.stream, h.leaf_off,
+                       static_cast<const float*>(h.prec[P32].Qc), static_cast<const float*>(yhat),
+                       h.r, h.near.row_task_ptr, h.near.col_ptr, h.near.col_pair,
+                       reinterpret_cast<const float*>(h.near_partial),
+                       reinterpret_cast<const float*>(h.near_colpart), h.near.ld, perm,
+                       static_cast<float*>(out), alpha, static_cast<const float*>(add), beta);
+  else
+    hipLaunchKernelGGL((k_fine_reduce<bf16, float>), g, b, 0, h.stream, h.leaf_off,
+                       static_cast<const bf16*>(h.prec[P16].Qc), static_cast<const float*>(yhat),
+                       h.r, h.near.row_task_ptr, h.near.col_ptr, h.near.col_pair,
+                       reinterpret_cast<const float*>(h.near_partial),
+                       reinterpret_cast<const float*>(h.near_colpart), h.near.ld, perm,
+                       static_cast<float*>(out), alpha, static_cast<const float*>(add), beta);
+  check_launch("fine_reduce");
+}
+
+void launch_leaf_down(H2& h, int p, const void* yhat, void* out, double alpha, const void* add,
+                      double beta) {
+  const dim3 g(h.nleaf), b(256);
+  if (p == P64)
+    hipLaunchKernelGGL((k_leaf_down<double, double>), g, b, 0, h.stream, h.leaf_off,
+                       static_cast<const double*>(h.prec[P64].Qc), static_cast<const double*>(yhat),
+                       h.r, static_cast<double*>(out), alpha, static_cast<const double*>(add), beta);
+  else if (p == P32)
+    hipLaunchKernelGGL((k_leaf_down<float, float>), g, b, 0, h.stream, h.leaf_off,
+                       static_cast<const float*>(h.prec[P32].Qc), static_cast<const float*>(yhat),
+                       h.r, static_cast<float*>(out), alpha, static_cast<const float*>(add), beta);
+  else
+    hipLaunchKernelGGL((k_leaf_down<bf16, float>), g, b, 0, h.stream, h.leaf_off,
+                       static_cast<const bf16*>(h.prec[P16].Qc), static_cast<const float*>(yhat),
+                       h.r, static_cast<float*>(out), alpha, static_cast<const float*>(add), beta);
+  check_launch("leaf_down");
+}
+
+}  // namespace h2mg

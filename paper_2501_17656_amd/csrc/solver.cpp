@@ -1,0 +1,269 @@
+// The H2-MG solver: Algorithm 1 (Section 3.3) with CG smoothing, repeated
+// V-cycles, and FP64 iterative refinement around a low-precision V-cycle.
+//
+// Every step runs on the device; the host only enqueues kernels and reads
+// the FP64 residual norm (a few hundred partial sums) once per cycle to
+// decide whether to stop.  CG scalars stay on the device as fixed-order
+// partial sums (kernels_solve.hip).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <stdexcept>
+#include <vector>
+
+#include "h2_build.h"
+
+namespace h2mg {
+
+namespace {
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+inline int vprec(int p) { return p == P64 ? P64 : P32; }   // vector type of an operator precision
+inline size_t vbytes(int p) { return p == P64 ? 8 : 4; }
+
+// Per-precision V-cycle vectors: r_k and e~_k per level, CG temporaries.
+struct Work {
+  std::vector<void*> r, et;
+  void *s = nullptr, *pv = nullptr, *q = nullptr, *tmp = nullptr;
+  double* gpart[2] = {nullptr, nullptr};
+  double* dpart = nullptr;
+};
+
+Work make_work(H2& h, int p) {
+  Work w;
+  const size_t vb = vbytes(p);
+  w.r.resize(h.levels + 1);
+  w.et.resize(h.levels + 1);
+  for (int k = 1; k <= h.levels; ++k) {
+    w.r[k] = h.arena.alloc(size_t(h.level_size(k)) * vb);
+    w.et[k] = h.arena.alloc(size_t(h.level_size(k)) * vb);
+  }
+  w.s = h.arena.alloc(size_t(h.n) * vb);
+  w.pv = h.arena.alloc(size_t(h.n) * vb);
+  w.q = h.arena.alloc(size_t(h.n) * vb);
+  w.tmp = h.arena.alloc(size_t(h.n) * vb);
+  w.gpart[0] = h.dot_part + 512;
+  w.gpart[1] = h.dot_part + 1024;
+  w.dpart = h.dot_part + 1536;
+  return w;
+}
+
+void release_work(H2& h, Work& w) {
+  for (int k = 1; k <= h.levels; ++k) {
+    h.arena.release(w.r[k]);
+    h.arena.release(w.et[k]);
+  }
+  h.arena.release(w.s);
+  h.arena.release(w.pv);
+  h.arena.release(w.q);
+  h.arena.release(w.tmp);
+}
+
+void zero(H2& h, void* v, int64_t n, int p) {
+  hip_check(hipMemsetAsync(v, 0, size_t(n) * vbytes(p), h.stream), "memset");
+}
+
+// e = Iter(A_k, rhs, e0): n CG steps; e holds e0 on entry unless e0_zero.
+void cg(H2& h, int p, int k, Work& w, const void* rhs, void* e, bool e0_zero, int nsteps) {
+  const int vp = vprec(p);
+  const int64_t N = h.level_size(k);
+  if (e0_zero) zero(h, e, N, vp);
+  if (nsteps <= 0) return;
+  if (e0_zero) {
+    launch_copy(h, vp, rhs, w.s, N);
+  } else {
+    apply_level(h, p, k, e, w.q);
+    launch_copy(h, vp, rhs, w.s, N);
+    launch_axpby(h, vp, N, -1.0, w.q, 1.0, w.s);
+  }
+  launch_copy(h, vp, w.s, w.pv, N);
+  int cur = 0;
+  launch_dot(h, vp, N, w.s, w.s, w.gpart[cur]);
+  for (int it = 0; it < nsteps; ++it) {
+    apply_level(h, p, k, w.pv, w.q);
+    launch_dot(h, vp, N, w.pv, w.q, w.dpart);
+    launch_cg_update(h, vp, N, e, w.pv, w.s, w.q, w.gpart[cur], w.dpart, w.gpart[1 - cur]);
+    if (it + 1 < nsteps) launch_cg_pupdate(h, vp, N, w.pv, w.s, w.gpart[cur], w.gpart[1 - cur]);
+    cur = 1 - cur;
+  }
+}
+
+// Direct solve on the coarsest level (FP64 Cholesky factor): e = A_l^{-1} r.
+void coarse_solve(H2& h, int p, const void* r, void* e) {
+  const int vp = vprec(p);
+  if (vp == P64) {
+    launch_copy(h, P64, r, e, h.Nl);
+    launch_chol_solve(h, h.chol, h.Nl, static_cast<double*>(e));
+  } else {
+    launch_cast(h, P64, h.vtree2, P32, r, h.Nl);
+    launch_chol_solve(h, h.chol, h.Nl, h.vtree2);
+    launch_cast(h, P32, e, P64, h.vtree2, h.Nl);
+  }
+}
+
+// One V-cycle on the correction equation A e_1 = r_1 (w.r[1] holds r_1,
+// tree order); the result e_1 is left in w.et[1].
+void vcycle(H2& h, int p, Work& w, int n_f, int n_c) {
+  const int vp = vprec(p);
+  const int l = h.levels;
+  for (int k = 1; k < l; ++k) {
+    const int nk = k == 1 ? n_f : n_c;
+    const int64_t N = h.level_size(k);
+    cg(h, p, k, w, w.r[k], w.et[k], true, nk);
+    // restriction of the residual: r_{k+1} = U_k^T (r_k - A_k e~_k)
+    apply_level(h, p, k, w.et[k], w.tmp);
+    launch_axpby(h, vp, N, 1.0, w.r[k], -1.0, w.tmp);
+    restrict_level(h, p, k, w.tmp, w.r[k + 1]);
+  }
+  coarse_solve(h, p, w.r[l], w.et[l]);
+  for (int k = l - 1; k >= 1; --k) {
+    const int nk = k == 1 ? n_f : n_c;
+    prolong_level(h, p, k, w.et[k + 1], w.et[k], w.et[k], 1.0);   // e~_k += U_k e_{k+1}
+    cg(h, p, k, w, w.r[k], w.et[k], false, nk);
+  }
+}
+
+double host_norm(H2& h, const double* v, int64_t n) {
+  const int np = dot_parts(n);
+  launch_dot(h, P64, n, v, v, h.dot_part);
+  std::vector<double> part(np);
+  hip_check(hipMemcpyAsync(part.data(), h.dot_part, np * sizeof(double), hipMemcpyDeviceToHost, h.stream),
+            "norm readback");
+  hip_check(hipStreamSynchronize(h.stream), "sync");
+  double s = 0.0;
+  for (int i = 0; i < np; ++i) s += part[i];
+  return std::sqrt(s);
+}
+
+void read_flags(H2& h, int* f) {
+  hip_check(hipMemcpyAsync(f, h.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, h.stream), "flags");
+  hip_check(hipStreamSynchronize(h.stream), "sync");
+}
+
+}  // namespace
+
+h2mg_status solve(H2& h, const double* b, double* x, const SolveParams& sp, h2mg_solve_info* info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  h.history.clear();
+  const int p = sp.precision == 0 ? P64 : sp.precision == 1 ? P32 : P16;
+  h2mg_status st = setup_mg(h, p == P64 ? 0 : (1 << p));
+  if (st != H2MG_OK) return st;
+  Work w64, wlp;
+  bool have_lp = false;
+  h2mg_status result = H2MG_OK;
+  int cycles = 0;
+  bool converged = false;
+  double rel = 0.0;
+  try {
+    w64 = make_work(h, P64);
+    if (p != P64) {
+      wlp = make_work(h, p);
+      have_lp = true;
+    }
+    const int64_t n = h.n;
+    double* bt = static_cast<double*>(h.arena.alloc(size_t(n) * 8));
+    double* xt = static_cast<double*>(h.arena.alloc(size_t(n) * 8));
+    double* res = static_cast<double*>(w64.r[1]);
+    launch_gather(h, b, bt);
+    if (sp.use_x0) launch_gather(h, x, xt);
+    else zero(h, xt, n, P64);
+    hip_check(hipMemsetAsync(h.flags, 0, 4 * sizeof(int), h.stream), "memset");
+    launch_check_finite(h, P64, n, bt);
+    int f[4];
+    read_flags(h, f);
+    if (f[1]) {
+      h.arena.release(bt);
+      h.arena.release(xt);
+      release_work(h, w64);
+      if (have_lp) release_work(h, wlp);
+      return fail(H2MG_ERR_INVALID_ARG, "b contains a non-finite value");
+    }
+    const double nb = host_norm(h, bt, n);
+    if (nb == 0.0) {
+      zero(h, xt, n, P64);
+      h.history.push_back(0.0);
+      converged = true;
+    } else {
+      for (int cyc = 0;; ++cyc) {
+        // res = b - A_H2 x (FP64)
+        apply_fine(h, P64, xt, res, -1.0, bt, 1.0);
+        const double rn = host_norm(h, res, n);
+        read_flags(h, f);
+        rel = rn / nb;
+        h.history.push_back(rel);
+        cycles = cyc;
+        if (f[0]) { result = fail(H2MG_ERR_NOT_SPD, "CG met p^T A p <= 0 (operator not SPD)"); break; }
+        if (!std::isfinite(rel)) { result = fail(H2MG_ERR_NUMERIC, "non-finite residual after %d cycles", cyc); break; }
+        if (rel < sp.rtol) { converged = true; break; }
+        if (cyc >= sp.max_cycles) {
+          result = fail(H2MG_ERR_NOT_CONVERGED, "no convergence in %d cycles (rel. residual %.3e)",
+                        sp.max_cycles, rel);
+          break;
+        }
+        if (p == P64) {
+          vcycle(h, P64, w64, sp.n_fine, sp.n_coarse);
+          launch_axpby(h, P64, n, 1.0, w64.et[1], 1.0, xt);
+        } else {
+          launch_cast(h, P32, wlp.r[1], P64, res, n);
+          vcycle(h, p, wlp, sp.n_fine, sp.n_coarse);
+          launch_cast(h, P64, h.vtree, P32, wlp.et[1], n);
+          launch_axpby(h, P64, n, 1.0, h.vtree, 1.0, xt);
+        }
+      }
+    }
+    launch_scatter(h, xt, x);
+    hip_check(hipStreamSynchronize(h.stream), "solve");
+    h.arena.release(bt);
+    h.arena.release(xt);
+    release_work(h, w64);
+    if (have_lp) release_work(h, wlp);
+  } catch (const std::bad_alloc&) {
+    return fail(H2MG_ERR_OOM, "device allocation failed in the solve");
+  } catch (const std::exception& ex) {
+    return fail(H2MG_ERR_HIP, "%s", ex.what());
+  }
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (info) {
+    info->cycles = cycles;
+    info->converged = converged ? 1 : 0;
+    info->rel_residual = h.history.empty() ? 0.0 : h.history.back();
+    info->solve_seconds = secs;
+    info->history_len = int(h.history.size());
+  }
+  return result;
+}
+
+h2mg_status vcycle_once(H2& h, const double* x0, const double* b, double* x_out, const SolveParams& sp) {
+  h2mg_status st = setup_mg(h, 0);
+  if (st != H2MG_OK) return st;
+  try {
+    Work w = make_work(h, P64);
+    const int64_t n = h.n;
+    double* bt = static_cast<double*>(h.arena.alloc(size_t(n) * 8));
+    double* xt = static_cast<double*>(h.arena.alloc(size_t(n) * 8));
+    launch_gather(h, b, bt);
+    launch_gather(h, x0, xt);
+    hip_check(hipMemsetAsync(h.flags, 0, 4 * sizeof(int), h.stream), "memset");
+    apply_fine(h, P64, xt, w.r[1], -1.0, bt, 1.0);   // r_1 = b - A x_0
+    vcycle(h, P64, w, sp.n_fine, sp.n_coarse);
+    launch_axpby(h, P64, n, 1.0, w.et[1], 1.0, xt);  // x* = x_0 + e_1
+    launch_scatter(h, xt, x_out);
+    int f[4];
+    read_flags(h, f);
+    h.arena.release(bt);
+    h.arena.release(xt);
+    release_work(h, w);
+    if (f[0]) return fail(H2MG_ERR_NOT_SPD, "CG met p^T A p <= 0 (operator not SPD)");
+  } catch (const std::bad_alloc&) {
+    return fail(H2MG_ERR_OOM, "device allocation failed in the V-cycle");
+  } catch (const std::exception& ex) {
+    return fail(H2MG_ERR_HIP, "%s", ex.what());
+  }
+  return H2MG_OK;
+}
+
+}  // namespace h2mg

@@ -1,0 +1,184 @@
+"""Thin Python layer over the C ABI (argument marshalling only).
+
+Device buffers are torch tensors on the current HIP device; work is queued
+on torch's current stream.  No numerical step happens here.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+
+from . import _lib
+from ._lib import check, lib
+
+KERNELS = {"exp": 0, "gauss": 1, "matern32": 2}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_f64(t, n=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError(f"{name} must be a float64 tensor on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} must have {n} elements (got {t.numel()})")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """Host-side cluster tree and block partition of a point set."""
+
+    def __init__(self, points: np.ndarray, leaf: int, eta: float, m: int):
+        pts = np.ascontiguousarray(points, dtype=np.float64)
+        n, dim = pts.shape
+        opts = _lib.BuildOpts(int(leaf), float(eta), int(m))
+        h = ctypes.c_void_p()
+        check(lib().h2mg_plan_create(pts.ctypes.data_as(ctypes.c_void_p), n, dim,
+                                     ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+        info = _lib.PlanInfo()
+        check(lib().h2mg_plan_query(h, ctypes.byref(info)))
+        self.n, self.dim, self.depth = info.n, info.dim, info.depth
+        self.d_top = None if info.d_top < 0 else info.d_top
+        self.rank, self.leaf_min, self.leaf_max = info.rank, info.leaf_min, info.leaf_max
+
+    def perm(self) -> np.ndarray:
+        out = np.empty(self.n, dtype=np.int64)
+        check(lib().h2mg_plan_perm(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def offsets(self, depth: int) -> np.ndarray:
+        out = np.empty((1 << depth) + 1, dtype=np.int64)
+        check(lib().h2mg_plan_offsets(self._h, depth, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def pairs(self, depth: int, far: bool) -> np.ndarray:
+        cnt = ctypes.c_int64()
+        check(lib().h2mg_plan_pair_count(self._h, depth, int(far), ctypes.byref(cnt)))
+        out = np.empty((cnt.value, 2), dtype=np.int64)
+        if cnt.value:
+            check(lib().h2mg_plan_pairs(self._h, depth, int(far), out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().h2mg_plan_destroy(self._h)
+            self._h = None
+
+
+class H2Matrix:
+    """H2 approximation of a kernel matrix, built and applied on the GPU."""
+
+    def __init__(self, points, kernel: str = "matern32", length_scale: float = 0.2,
+                 shift: float = 1e-3, leaf: int = 128, eta: float = 0.7, m: int = 4):
+        pts = points if points.is_contiguous() else points.contiguous()
+        n, dim = pts.shape
+        _dev_f64(pts, name="points")
+        self.n, self.dim = int(n), int(dim)
+        ker = _lib.Kernel(KERNELS[kernel], float(length_scale), float(shift))
+        opts = _lib.BuildOpts(int(leaf), float(eta), int(m))
+        h = ctypes.c_void_p()
+        check(lib().h2mg_build(ctypes.c_void_p(pts.data_ptr()), self.n, self.dim, ctypes.byref(ker),
+                               ctypes.byref(opts), _stream(), ctypes.byref(h)))
+        self._h = h
+
+    # ------------------------------------------------------------ products
+    def matvec(self, x, out=None):
+        import torch
+        y = torch.empty_like(x) if out is None else out
+        check(lib().h2mg_matvec(self._h, _dev_f64(x, self.n, "x"), _dev_f64(y, self.n, "y"), _stream()))
+        return y
+
+    def setup(self, precisions=("fp64",)) -> None:
+        mask = 0
+        for p in precisions:
+            mask |= 1 << PRECISIONS[p]
+        check(lib().h2mg_setup_mg(self._h, mask, _stream()))
+
+    @property
+    def levels(self) -> int:
+        v = ctypes.c_int32()
+        check(lib().h2mg_level_count(self._h, ctypes.byref(v)))
+        return v.value
+
+    def level_size(self, level: int) -> int:
+        v = ctypes.c_int64()
+        check(lib().h2mg_level_size(self._h, level, ctypes.byref(v)))
+        return v.value
+
+    def level_apply(self, level: int, x, out=None):
+        import torch
+        y = torch.empty_like(x) if out is None else out
+        nk = self.level_size(level)
+        check(lib().h2mg_level_apply(self._h, level, _dev_f64(x, nk, "x"), _dev_f64(y, nk, "y"), _stream()))
+        return y
+
+    def restrict(self, level: int, r):
+        import torch
+        out = torch.empty(self.level_size(level + 1), dtype=torch.float64, device=r.device)
+        check(lib().h2mg_restrict(self._h, level, _dev_f64(r, self.level_size(level), "r"),
+                                  _dev_f64(out), _stream()))
+        return out
+
+    def prolong(self, level: int, e_next):
+        import torch
+        out = torch.empty(self.level_size(level), dtype=torch.float64, device=e_next.device)
+        check(lib().h2mg_prolong(self._h, level, _dev_f64(e_next, self.level_size(level + 1), "e"),
+                                 _dev_f64(out), _stream()))
+        return out
+
+    # ------------------------------------------------------------ solves
+    @staticmethod
+    def _opts(rtol, n_fine, n_coarse, max_cycles, precision, use_x0):
+        return _lib.SolveOpts(int(n_fine), int(n_coarse), float(rtol), int(max_cycles),
+                              PRECISIONS[precision], int(use_x0))
+
+    def vcycle(self, x0, b, n_fine: int = 1, n_coarse: int = 40, out=None):
+        import torch
+        x = torch.empty_like(b) if out is None else out
+        o = self._opts(1e-8, n_fine, n_coarse, 1, "fp64", 1)
+        check(lib().h2mg_vcycle(self._h, _dev_f64(x0, self.n, "x0"), _dev_f64(b, self.n, "b"),
+                                _dev_f64(x, self.n, "x"), ctypes.byref(o), _stream()))
+        return x
+
+    def solve(self, b, rtol: float = 1e-8, n_fine: int = 1, n_coarse: int = 40,
+              max_cycles: int = 500, precision: str = "fp64", x0=None, raise_on_error: bool = True):
+        """Solve A_H2 x = b.  Returns (x, info dict)."""
+        import torch
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        o = self._opts(rtol, n_fine, n_coarse, max_cycles, precision, x0 is not None)
+        info = _lib.SolveInfo()
+        st = lib().h2mg_solve(self._h, _dev_f64(b, self.n, "b"), _dev_f64(x, self.n, "x"),
+                              ctypes.byref(o), ctypes.byref(info), _stream())
+        hist = (ctypes.c_double * max(info.history_len, 1))()
+        lib().h2mg_solve_history(self._h, hist, info.history_len)
+        out = {"cycles": info.cycles, "converged": bool(info.converged),
+               "rel_residual": info.rel_residual, "solve_seconds": info.solve_seconds,
+               "history": list(hist)[:info.history_len], "status": _lib.STATUS.get(st, st)}
+        if st != 0 and raise_on_error:
+            check(st)
+        return x, out
+
+    def memory_bytes(self) -> int:
+        v = ctypes.c_int64()
+        check(lib().h2mg_memory_bytes(self._h, ctypes.byref(v)))
+        return v.value
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            check(lib().h2mg_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -99,6 +99,15 @@ def test_blockwise_matvec_equals_densified_and_is_symmetric():
     np.testing.assert_allclose(h.matvec(2.0 * x - z), 2.0 * y - h.matvec(z), rtol=1e-12, atol=1e-12)
 
 
+def test_sampled_rows_equal_full_matvec():
+    h = _small(n=1200, leaf=32, m=3)
+    x = synth.normal_vector(h.n, 5)
+    yt = h.matvec_tree(x[h.tree.perm])
+    for leaf in (0, 13, 2 ** h.L - 1):
+        r = h.rows(h.L, leaf)
+        np.testing.assert_allclose(h.matvec_rows(x, leaf), yt[r], rtol=1e-13, atol=1e-13)
+
+
 def test_no_far_blocks_means_exact_kernel_matrix():
     h = _small(n=500, leaf=16, eta=1e-9)
     assert h.d_top is None
