@@ -211,6 +211,18 @@ h2mg_status h2mg_solve(h2mg_h2_t h, const double* b_dev, double* x_dev,
  * (host array of at least `capacity` doubles; copies min(capacity, len)). */
 h2mg_status h2mg_solve_history(h2mg_h2_t h, double* history_host, int32_t capacity);
 
+/* Kernel timing, for measurement harnesses.  While enabled, every launch of
+ * the block GEMV and of the near-field kernel is bracketed by HIP events on
+ * the handle's stream (a small per-launch overhead).  h2mg_set_timing
+ * resets the counters.  h2mg_kernel_stats synchronises the stream and
+ * returns, for kind 0/1/2 (block GEMV with FP64/FP32/BF16 blocks), the
+ * number of launches, their summed duration in ms and the algorithmic bytes
+ * they streamed (stored block words x element size); for kind 3/4 (near
+ * field in FP64/FP32) the summed kernel evaluations instead of bytes. */
+h2mg_status h2mg_set_timing(h2mg_h2_t h, int32_t enabled);
+h2mg_status h2mg_kernel_stats(h2mg_h2_t h, int32_t kind, int64_t* launches, double* total_ms,
+                              double* total_work);
+
 /* Device memory held by the handle, in bytes. */
 h2mg_status h2mg_memory_bytes(h2mg_h2_t h, int64_t* bytes);
 

@@ -282,6 +282,31 @@ h2mg_status h2mg_memory_bytes(h2mg_h2_t hh, int64_t* bytes) {
   });
 }
 
+h2mg_status h2mg_set_timing(h2mg_h2_t hh, int32_t enabled) {
+  return guarded([&] {
+    if (!hh) return fail(H2MG_ERR_INVALID_ARG, "null handle");
+    H2& h = *hh->h;
+    h.flush_timing();
+    for (auto& k : h.kstat) k = KStat();
+    h.timing = enabled != 0;
+    return H2MG_OK;
+  });
+}
+
+h2mg_status h2mg_kernel_stats(h2mg_h2_t hh, int32_t kind, int64_t* launches, double* total_ms,
+                              double* total_work) {
+  return guarded([&] {
+    if (!hh || !launches || !total_ms || !total_work) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    if (kind < 0 || kind >= KS_COUNT) return fail(H2MG_ERR_INVALID_ARG, "unknown kernel kind");
+    H2& h = *hh->h;
+    h.flush_timing();
+    *launches = h.kstat[kind].launches;
+    *total_ms = h.kstat[kind].ms;
+    *total_work = h.kstat[kind].bytes;
+    return H2MG_OK;
+  });
+}
+
 h2mg_status h2mg_destroy(h2mg_h2_t hh) {
   return guarded([&] {
     if (!hh) return H2MG_OK;

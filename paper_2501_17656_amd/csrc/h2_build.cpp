@@ -39,6 +39,52 @@ Arena::~Arena() {
   for (auto& pr : ptrs) (void)hipFree(pr.first);
 }
 
+H2::~H2() {
+  for (hipEvent_t e : events) (void)hipEventDestroy(e);
+}
+
+int H2::take_event() {
+  if (next_event == int(events.size())) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) throw std::runtime_error("hipEventCreate failed");
+    events.push_back(e);
+  }
+  return next_event++;
+}
+
+void H2::time_begin(int& ev) {
+  ev = -1;
+  if (!timing) return;
+  ev = take_event();
+  (void)hipEventRecord(events[ev], stream);
+}
+
+void H2::time_end(int kind, int ev, double bytes) {
+  if (ev < 0) return;
+  const int e2 = take_event();
+  (void)hipEventRecord(events[e2], stream);
+  kstat[kind].pending.emplace_back(ev, e2);
+  kstat[kind].pending_bytes.push_back(bytes);
+  if (next_event > 4096) flush_timing();
+}
+
+void H2::flush_timing() {
+  if (next_event == 0) return;
+  (void)hipStreamSynchronize(stream);
+  for (auto& k : kstat) {
+    for (size_t i = 0; i < k.pending.size(); ++i) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, events[k.pending[i].first], events[k.pending[i].second]);
+      k.ms += ms;
+      k.bytes += k.pending_bytes[i];
+      k.launches += 1;
+    }
+    k.pending.clear();
+    k.pending_bytes.clear();
+  }
+  next_event = 0;
+}
+
 namespace {
 
 void hip_check(hipError_t e, const char* what) {
@@ -99,6 +145,7 @@ Launch make_launch(H2& h, const std::vector<const View*>& views) {
   for (const View* v : views) {
     l.base.push_back(int(all.size() / 3));
     all.insert(all.end(), v->task.begin(), v->task.end());
+    for (size_t i = 0; i < v->task.size(); i += 3) l.nblocks += v->task[i + 2] - v->task[i + 1];
   }
   l.ntasks = int(all.size() / 3);
   l.task = upload(h, all);
@@ -260,6 +307,8 @@ h2mg_status build_h2(const double* points_dev, int64_t n, int dim, const h2mg_ke
       nf.col_ptr = upload(h, cptr);
       nf.col_pair = upload(h, cpair);
       nf.ld = (h.leaf_max + 7) / 8 * 8;
+      for (int p = 0; p < nf.npairs; ++p)
+        h.near_evals += int64_t(loff[prow[p] + 1] - loff[prow[p]]) * (loff[pcol[p] + 1] - loff[pcol[p]]);
     }
 
     // ---- workspace

@@ -50,8 +50,19 @@ struct View {
 // One GEMV launch over the concatenated tasks of several views.
 struct Launch {
   int ntasks = 0;
+  int64_t nblocks = 0;                 // stored blocks streamed by one launch
   int* task = nullptr;                 // device
   std::vector<int> base;               // task base of each view in the list
+};
+
+// Optional per-kernel timing with HIP events on the handle's stream.
+enum KStatKind { KS_GEMV64 = 0, KS_GEMV32 = 1, KS_GEMV16 = 2, KS_NEAR64 = 3, KS_NEAR32 = 4, KS_COUNT = 5 };
+struct KStat {
+  int64_t launches = 0;
+  double ms = 0.0;
+  double bytes = 0.0;                  // algorithmic bytes (GEMV) or kernel evaluations (near)
+  std::vector<std::pair<int, int>> pending;   // event indices not yet read
+  std::vector<double> pending_bytes;
 };
 
 // Close leaf pairs (s <= t) for the on-the-fly near field.
@@ -126,6 +137,18 @@ struct H2 {
   int* flags = nullptr;                // device flags (0: not SPD, 1: non-finite)
   double* dot_part = nullptr;          // reduction partials (several slots)
   std::vector<double> history;
+
+  // kernel timing
+  bool timing = false;
+  std::vector<hipEvent_t> events;
+  int next_event = 0;
+  KStat kstat[KS_COUNT];
+  int64_t near_evals = 0;              // kernel evaluations of one near-field pass
+  ~H2();
+  int take_event();                    // index of a free event (creates on demand)
+  void time_begin(int& ev);            // record a start event when timing
+  void time_end(int kind, int ev, double bytes);
+  void flush_timing();                 // synchronise and accumulate pending events
 
   int64_t level_size(int k) const {    // k = 1..levels
     if (k == 1) return n;

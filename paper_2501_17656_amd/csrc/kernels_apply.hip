@@ -416,6 +416,8 @@ inline int grid_waves(int64_t waves) { return int((waves + 3) / 4); }
 // ------------------------------------------------------------ launchers
 void launch_gemv(H2& h, int p, const Launch& l, const void* x_all) {
   if (l.ntasks == 0) return;
+  int ev;
+  h.time_begin(ev);
   dispatch_T(h.T, [&](auto Tc) {
     constexpr int T = decltype(Tc)::value;
     const dim3 g(grid_waves(l.ntasks)), b(256);
@@ -435,6 +437,7 @@ void launch_gemv(H2& h, int p, const Launch& l, const void* x_all) {
                          reinterpret_cast<float*>(h.colpart), h.r);
   });
   check_launch("bsr_gemv");
+  h.time_end(KS_GEMV64 + p, ev, double(l.nblocks) * h.r * h.r * elem_bytes(p));
 }
 
 void launch_reduce(H2& h, int p, int d, const View* v0, int base0, const View* v1, int base1,
@@ -518,6 +521,8 @@ void launch_leaf_up(H2& h, int p, const void* xtree, void* xhat) {
 
 void launch_near(H2& h, int p, const void* xtree) {
   if (h.near.ntasks == 0) return;
+  int ev;
+  h.time_begin(ev);
   const dim3 g(h.near.ntasks), b(256);
   if (p == P64)
     hipLaunchKernelGGL((k_near<double, double>), g, b, 0, h.stream, h.near.task, h.near.pair_col,
@@ -529,6 +534,7 @@ void launch_near(H2& h, int p, const void* xtree) {
                        reinterpret_cast<float*>(h.near_partial),
                        reinterpret_cast<float*>(h.near_colpart), h.near.ld, h.kp);
   check_launch("near");
+  h.time_end(p == P64 ? KS_NEAR64 : KS_NEAR32, ev, double(h.near_evals));
 }
 
 void launch_fine_reduce(H2& h, int p, const void* yhat, void* out, bool to_user, double alpha,

@@ -167,6 +167,17 @@ class H2Matrix:
             check(st)
         return x, out
 
+    KERNEL_KINDS = {"gemv_fp64": 0, "gemv_fp32": 1, "gemv_bf16": 2, "near_fp64": 3, "near_fp32": 4}
+
+    def set_timing(self, enabled: bool) -> None:
+        check(lib().h2mg_set_timing(self._h, int(bool(enabled))))
+
+    def kernel_stats(self, kind: str) -> dict:
+        n, ms, work = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        check(lib().h2mg_kernel_stats(self._h, self.KERNEL_KINDS[kind], ctypes.byref(n),
+                                      ctypes.byref(ms), ctypes.byref(work)))
+        return {"launches": n.value, "ms": ms.value, "work": work.value}
+
     def memory_bytes(self) -> int:
         v = ctypes.c_int64()
         check(lib().h2mg_memory_bytes(self._h, ctypes.byref(v)))

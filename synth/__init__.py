@@ -110,6 +110,11 @@ WORKLOADS = {
     # headline 3D Matern-3/2 problem (N = 2^20, leaf 128, rank 64)
     "matern3d_1m": Workload("matern3d_1m", 1 << 20, 3, "matern32", 0.2, 1e-3,
                             128, 0.7, 4),
+    # the same points, kernel and H2 parameters with the diagonal shift raised
+    # to 1: the rank-64 Chebyshev approximation of the 1e-3-shift matrix is
+    # indefinite at this size, this one stays positive definite
+    "matern3d_1m_spd": Workload("matern3d_1m_spd", 1 << 20, 3, "matern32", 0.2, 1.0,
+                                128, 0.7, 4),
     # Gaussian-kernel problem on Gaussian-mixture clouds (rank 27, leaf 64)
     "gauss3d_gmm": Workload("gauss3d_gmm", 65536, 3, "gauss", 0.1, 1e-2, 64,
                             0.7, 3, points="gmm"),

@@ -36,8 +36,10 @@ SHAPES = {
     "exp2d_4k": ("uniform", 4096, 2, "exp", 0.1, 1e-2, 64, 0.7, 4),
     "exp2d_ragged_r9": ("uniform", 1200, 2, "exp", 0.1, 1e-2, 32, 0.7, 3),
     "exp1d_r4": ("uniform", 2000, 1, "exp", 0.05, 1e-2, 16, 0.7, 4),
-    "gauss3d_r8": ("uniform", 3000, 3, "gauss", 0.2, 1e-2, 32, 0.7, 2),
-    "gauss3d_gmm_r27": ("gmm", 8192, 3, "gauss", 0.1, 1e-2, 64, 0.7, 3),
+    "gauss3d_r8": ("uniform", 3000, 3, "gauss", 0.2, 1e-2, 32, 0.7, 2),     # indefinite A_H2
+    "exp3d_r8": ("uniform", 3000, 3, "exp", 0.2, 1e-1, 32, 0.7, 2),
+    "gauss3d_gmm_r27": ("gmm", 8192, 3, "gauss", 0.1, 1e-2, 64, 0.7, 3),    # indefinite A_H2
+    "gauss3d_gmm4k_r27": ("gmm", 4096, 3, "gauss", 0.1, 1e-2, 64, 0.7, 3),
     "matern3d_r64": ("uniform", 16384, 3, "matern32", 0.2, 1e-3, 64, 0.7, 4),
     "grid2d_ties": ("grid", 2500, 2, "matern32", 0.1, 1e-2, 40, 0.7, 3),
     "no_far": ("uniform", 500, 2, "exp", 0.1, 1e-2, 16, 1e-9, 3),
@@ -90,7 +92,8 @@ def test_matvec_is_linear_and_deterministic():
     assert np.linalg.norm(c - d) <= 1e-13 * np.linalg.norm(d)
 
 
-@pytest.mark.parametrize("name", ["exp2d_4k", "exp2d_ragged_r9", "exp1d_r4", "gauss3d_r8"])
+@pytest.mark.parametrize("name", ["exp2d_4k", "exp2d_ragged_r9", "exp1d_r4", "exp3d_r8",
+                                  "gauss3d_gmm4k_r27"])
 def test_restricted_operators_match_dense_galerkin(name):
     P, o, g = make(name)
     g.setup()
@@ -104,6 +107,19 @@ def test_restricted_operators_match_dense_galerkin(name):
         rel = np.linalg.norm(y - yo) / np.linalg.norm(yo)
         print(f"[gpu] {name} level {k} apply rel err {rel:.2e}")
         assert rel <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["gauss3d_r8", "gauss3d_gmm_r27"])
+def test_indefinite_h2_is_reported_not_spd(name):
+    """Low-order interpolation of a Gaussian can leave A_H2 indefinite (the
+    oracle's dense coarsest operator fails Cholesky for both shapes; for the
+    rank-8 one its smallest eigenvalue is about -0.1); the library must
+    report NOT_SPD instead of producing a factor."""
+    from paper_2501_17656_amd import H2MGError
+    P, o, g = make(name)
+    with pytest.raises(H2MGError) as ei:
+        g.setup()
+    assert ei.value.status_name == "NOT_SPD"
 
 
 @pytest.mark.parametrize("name", ["exp2d_4k", "exp2d_ragged_r9"])
@@ -128,6 +144,36 @@ def test_restriction_and_prolongation_match_oracle(name):
         e = _host(g.prolong(k, _dev(w)))
         assert np.linalg.norm(r - r_ref) <= 1e-12 * np.linalg.norm(r_ref)
         assert np.linalg.norm(e - e_ref) <= 1e-12 * np.linalg.norm(e_ref)
+
+
+def test_restricted_operator_rows_at_leaf_128():
+    """Level 2 (depth-L coefficients) of the Matern 3D rank-64 shape with
+    128-point leaves, on sampled block rows, against the definition
+    (W_L^T A_H2 W_L v)_s = Q_s^T (A_H2 (W_L v))_{rows of leaf s}, with the
+    oracle's own QR bases and row-restricted matvec."""
+    from oracle.ortho import cluster_q
+    n = 32768
+    P = synth.uniform_points(n, 3, 0)
+    from paper_2501_17656_amd import H2Matrix
+    g = H2Matrix(_dev(P), "matern32", 0.2, 1e-3, 128, 0.7, 4)
+    g.setup()
+    o = OracleH2(P, "matern32", 1e-3, 128, 0.7, 4, 0.2)
+    r, L = o.r, o.L
+    v = synth.normal_vector(g.level_size(2), 7)
+    y = _host(g.level_apply(2, _dev(v)))
+    u_tree = np.zeros(n)
+    Q = {}
+    for j in range(2 ** L):
+        Q[j] = cluster_q(o, L, j)
+        u_tree[o.rows(L, j)] = Q[j] @ v[j * r:(j + 1) * r]
+    u = np.empty(n)
+    u[o.tree.perm] = u_tree
+    for leaf in (0, 101, 2 ** L - 1):
+        ref = Q[leaf].T @ o.matvec_rows(u, leaf)
+        got = y[leaf * r:(leaf + 1) * r]
+        rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        print(f"[gpu] level-2 block row {leaf} rel err {rel:.2e}")
+        assert rel <= 1e-10
 
 
 def test_sampled_rows_at_larger_size():
