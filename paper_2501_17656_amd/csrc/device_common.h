@@ -77,9 +77,12 @@ __host__ __device__ inline int tile_offset(int i, int j, int T) {
   return ((e / K) * 64 + lane) * K + (e % K);
 }
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 // Load the T*T elements of this lane's sub-tile (row-major u*T + v) from
-// the tile starting at `tile`.
-template <int T, typename Tb, typename Tacc>
+// the tile starting at `tile`.  NT: non-temporal (streaming) loads, for
+// blocks read once per product so they do not evict reused vectors.
+template <int T, typename Tb, typename Tacc, bool NT = false>
 __device__ inline void load_subtile(const Tb* __restrict__ tile, int lane, Tacc (&B)[T * T]) {
   constexpr int K = tile_K<Tb>(T);
   constexpr int NC = T * T / K;
@@ -88,8 +91,9 @@ __device__ inline void load_subtile(const Tb* __restrict__ tile, int lane, Tacc 
     const Tb* p = tile + (c * 64 + lane) * K;
     if constexpr (K * sizeof(Tb) == 16) {
       // one 16-byte load per chunk
-      union { uint4 q; Tb e[K]; } u;
-      u.q = *reinterpret_cast<const uint4*>(p);
+      union { u32x4 q; Tb e[K]; } u;
+      if constexpr (NT) u.q = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+      else u.q = *reinterpret_cast<const u32x4*>(p);
 #pragma unroll
       for (int k = 0; k < K; ++k) B[c * K + k] = ld_as<Tacc, Tb>(u.e[k]);
     } else {

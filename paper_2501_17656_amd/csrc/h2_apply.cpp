@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <stdexcept>
+#include <vector>
 
 #include "h2_build.h"
 
@@ -32,18 +33,19 @@ void apply_fine(H2& h, int p, const void* xt, void* out, double alpha, const voi
     launch_leaf_up(h, p, xt, at_depth(xall, p, h.L, r));
     for (int d = h.L - 1; d >= h.d_top; --d)
       launch_transfer_up(h, p, d, at_depth(xall, p, d + 1, r), at_depth(xall, p, d, r));
-    // couplings of every depth in one launch
+    // couplings of every depth in one launch, then one reduce for all depths
     launch_gemv(h, p, h.fine_launch, xall);
-    // downsweep: y_d = S_d x_d + E y_{d-1}
+    std::vector<const View*> vs;
+    std::vector<int> bs;
     for (int d = h.d_top; d <= h.L; ++d) {
-      const void* addend = nullptr;
-      if (d > h.d_top) {
-        launch_transfer_down(h, p, d - 1, at_depth(yall, p, d - 1, r), at_depth(yall, p, d, r), nullptr);
-        addend = at_depth(yall, p, d, r);
-      }
-      launch_reduce(h, p, d, &h.sview[d], h.fine_launch.base[d - h.d_top], nullptr, 0, addend,
-                    at_depth(yall, p, d, r));
+      vs.push_back(&h.sview[d]);
+      bs.push_back(h.fine_launch.base[d - h.d_top]);
     }
+    launch_reduce(h, p, h.d_top, h.L, vs.data(), bs.data(), nullptr, nullptr, yall, nullptr);
+    // downsweep: y_d += E y_{d-1}
+    for (int d = h.d_top + 1; d <= h.L; ++d)
+      launch_transfer_down(h, p, d - 1, at_depth(yall, p, d - 1, r), at_depth(yall, p, d, r),
+                           at_depth(yall, p, d, r));
   }
   // near field and leaf downsweep: y = D x + Q y_L
   launch_near(h, p, xt);
@@ -60,20 +62,26 @@ void apply_coarse(H2& h, int p, int k, const void* x, void* y) {
     launch_transfer_up(h, p, q, at_depth(xall, p, q + 1, r), at_depth(xall, p, q, r));
   const Launch& l = h.coarse_launch[d];
   launch_gemv(h, p, l, xall);
-  for (int q = h.d_top; q <= d; ++q) {
-    const void* addend = nullptr;
-    if (q > h.d_top) {
-      launch_transfer_down(h, p, q - 1, at_depth(yall, p, q - 1, r), at_depth(yall, p, q, r), nullptr);
-      addend = at_depth(yall, p, q, r);
-    }
-    if (q < d) {
-      launch_reduce(h, p, q, &h.sview[q], l.base[q - h.d_top], nullptr, 0, addend,
-                    at_depth(yall, p, q, r));
-    } else {
-      const int nv = d - h.d_top;   // views before Pi_d
-      launch_reduce(h, p, d, &h.pview[d], l.base[nv], &h.sview[d], l.base[nv + 1], addend, y);
-    }
+  // partial sums of every depth: S_q for q < d, Pi_d and S_d at depth d
+  std::vector<const View*> v0, v1;
+  std::vector<int> b0, b1;
+  for (int q = h.d_top; q < d; ++q) {
+    v0.push_back(&h.sview[q]);
+    b0.push_back(l.base[q - h.d_top]);
+    v1.push_back(nullptr);
+    b1.push_back(0);
   }
+  const int nv = d - h.d_top;
+  v0.push_back(&h.pview[d]);
+  b0.push_back(l.base[nv]);
+  v1.push_back(&h.sview[d]);
+  b1.push_back(l.base[nv + 1]);
+  launch_reduce(h, p, h.d_top, d, v0.data(), b0.data(), v1.data(), b1.data(), yall,
+                d == h.d_top ? y : nullptr);
+  // downsweep, the last step writing the output
+  for (int q = h.d_top + 1; q <= d; ++q)
+    launch_transfer_down(h, p, q - 1, at_depth(yall, p, q - 1, r), q == d ? y : at_depth(yall, p, q, r),
+                         at_depth(yall, p, q, r));
 }
 
 void apply_level(H2& h, int p, int k, const void* x, void* y) {

@@ -133,6 +133,9 @@ View make_view(H2& h, int d, int first, int count) {
   std::vector<int> fill(cptr.begin(), cptr.end() - 1);
   for (int b = first; b < first + count; ++b)
     if (h.blk_col_h[b] != h.blk_row_h[b]) cblk[fill[h.blk_col_h[b] - gid0]++] = b;
+  v.slot_base = h.nslot;
+  for (size_t c = 0; c < cblk.size(); ++c) h.blk_slot_h[cblk[c]] = h.nslot + int(c);
+  h.nslot += int(cblk.size());
   v.row_task_ptr = upload(h, rtp);
   v.col_ptr = upload(h, cptr);
   v.col_blk = upload(h, cblk);
@@ -249,6 +252,7 @@ h2mg_status build_h2(const double* points_dev, int64_t n, int dim, const h2mg_ke
     h.nblk = int(h.blk_row_h.size());
     h.blk_row = upload(h, h.blk_row_h);
     h.blk_col = upload(h, h.blk_col_h);
+    h.blk_slot_h.assign(h.nblk, -1);
     h.sview.resize(h.L + 1);
     h.pview.resize(h.L + 1);
     h.coarse_launch.resize(h.L + 1);
@@ -257,6 +261,7 @@ h2mg_status build_h2(const double* points_dev, int64_t n, int dim, const h2mg_ke
         h.sview[d] = make_view(h, d, h.s_first[d], h.s_count[d]);
         h.pview[d] = make_view(h, d, h.p_first[d], h.p_count[d]);
       }
+      h.blk_slot = upload(h, h.blk_slot_h);
       std::vector<const View*> vs;
       for (int d = h.d_top; d <= h.L; ++d) vs.push_back(&h.sview[d]);
       h.fine_launch = make_launch(h, vs);
@@ -316,7 +321,7 @@ h2mg_status build_h2(const double* points_dev, int64_t n, int dim, const h2mg_ke
     h.xall = h.arena.make<double>(size_t(h.ngid) * rr);
     h.yall = h.arena.make<double>(size_t(h.ngid) * rr);
     h.partial = h.arena.make<double>(size_t(std::max(h.max_tasks, 1)) * rr);
-    h.colpart = h.arena.make<double>(size_t(std::max(h.nblk, 1)) * rr);
+    h.colpart = h.arena.make<double>(size_t(std::max(h.nslot, 1)) * rr);
     h.near_partial = h.arena.make<double>(size_t(std::max(h.near.ntasks, 1)) * h.near.ld);
     h.near_colpart = h.arena.make<double>(size_t(std::max(h.near.npairs, 1)) * h.near.ld);
     h.vtree = h.arena.make<double>(h.n);

@@ -45,6 +45,7 @@ struct View {
   int* row_task_ptr = nullptr;         // device: 2^depth + 1, offsets into this view's tasks
   int* col_ptr = nullptr;              // device: 2^depth + 1
   int* col_blk = nullptr;              // device: stored off-diagonal blocks by column
+  int slot_base = 0;                   // first column-contribution slot of this view
 };
 
 // One GEMV launch over the concatenated tasks of several views.
@@ -107,8 +108,11 @@ struct H2 {
   // Pi of depth d in [p_first[d], p_first[d] + p_count[d])
   int nblk = 0;
   std::vector<int> blk_row_h, blk_col_h;   // gids
+  std::vector<int> blk_slot_h;
   int* blk_row = nullptr;
   int* blk_col = nullptr;
+  int* blk_slot = nullptr;             // column-contribution slot of each stored block
+  int nslot = 0;
   std::vector<int> s_first, s_count, p_first, p_count;
   std::vector<View> sview, pview;
   NearField near;
@@ -172,8 +176,13 @@ void launch_cast_precision(H2& h, int p);         // FP64 -> FP32 / BF16 copies
 // ------------------------------------------------------------ apply kernels
 // All vectors are in the precision's vector type: double (P64) or float.
 void launch_gemv(H2& h, int p, const Launch& l, const void* x_all);
-void launch_reduce(H2& h, int p, int d, const View* v0, int base0, const View* v1,
-                   int base1, const void* addend, void* out);
+// For every depth d in [d0, d1]: y_d = sum of the task partials and column
+// contributions of views v0[d] (and v1[d] when not null) of that depth,
+// written at out + offset of depth d (gid-indexed buffer) -- or, for depth
+// d1 only, at out_last when it is not null.  base0/base1: task bases of the
+// views in the launch that produced the partials.
+void launch_reduce(H2& h, int p, int d0, int d1, const View* const* v0, const int* base0,
+                   const View* const* v1, const int* base1, void* out, void* out_last);
 void launch_transfer_up(H2& h, int p, int d, const void* xchild, void* xpar);
 void launch_transfer_down(H2& h, int p, int d, const void* ypar, void* ychild,
                           const void* addend);

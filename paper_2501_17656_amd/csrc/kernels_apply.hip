@@ -31,36 +31,106 @@ void check_launch(const char* what) {
 template <typename Tv> __device__ inline Tv zero() { return Tv(0); }
 
 // ------------------------------------------------------------ symmetric block GEMV
+// Sum over the 8 lanes that share b (lane bits 3..5 = a) of T values each,
+// as a butterfly transpose-reduce: afterwards lane (a, b) holds the full sum
+// of value index a (T = 8), or of index a >> (3 - log2 T) for smaller T.
+template <int T, typename Tv>
+__device__ inline Tv transpose_reduce_a(Tv (&z)[T], int a) {
+  if constexpr (T == 1) {
+    Tv s = z[0];
+    s += shfl_xor(s, 8);
+    s += shfl_xor(s, 16);
+    s += shfl_xor(s, 32);
+    return s;
+  } else {
+    // halve the value set at each step, masks 32, 16, 8 (a bits 2, 1, 0)
+    constexpr int H = T / 2;
+    const bool hi = (a >> 2) & 1;
+    Tv v1[H];
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      const Tv keep = hi ? z[k + H] : z[k];
+      const Tv send = hi ? z[k] : z[k + H];
+      v1[k] = keep + shfl_xor(send, 32);
+    }
+    if constexpr (H == 1) {
+      Tv s = v1[0];
+      s += shfl_xor(s, 16);
+      s += shfl_xor(s, 8);
+      return s;
+    } else {
+      constexpr int Q = H / 2;
+      const bool mid = (a >> 1) & 1;
+      Tv v2[Q];
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        const Tv keep = mid ? v1[k + Q] : v1[k];
+        const Tv send = mid ? v1[k] : v1[k + Q];
+        v2[k] = keep + shfl_xor(send, 16);
+      }
+      if constexpr (Q == 1) {
+        Tv s = v2[0];
+        s += shfl_xor(s, 8);
+        return s;
+      } else {
+        const bool lo = a & 1;
+        const Tv keep = lo ? v2[1] : v2[0];
+        const Tv send = lo ? v2[0] : v2[1];
+        return keep + shfl_xor(send, 8);
+      }
+    }
+  }
+}
+
+// Value index held by lane a after transpose_reduce_a.
+template <int T>
+__device__ inline int reduced_index(int a) {
+  if constexpr (T == 1) return 0;
+  else if constexpr (T == 2) return (a >> 2) & 1;
+  else if constexpr (T == 4) return ((a >> 2) & 1) * 2 + ((a >> 1) & 1);
+  else return ((a >> 2) & 1) * 4 + ((a >> 1) & 1) * 2 + (a & 1);
+}
+
 // One wave per task (row gid s, blocks [b0, b1)).  partial[task] = sum_b B_b x_{col b};
-// colpart[b] = B_b^T x_s for every off-diagonal block.
-template <int T, typename Tb, typename Tv>
+// colpart[slot of b] = B_b^T x_s for every off-diagonal block (slots are
+// ordered by column, so the reduce reads each column's run contiguously).
+// FULL: r == 8T (no padding, no guards).  Each iteration requests its tile
+// first, then the coefficients of its column (the next column index is
+// prefetched by a scalar load), so one tile is in flight per wave while the
+// previous is consumed; FP32/BF16 tiles use non-temporal loads (measured
+// faster there, slower for FP64 tiles).
+template <int T, bool FULL, typename Tb, typename Tv>
 __global__ __launch_bounds__(256) void k_bsr_gemv(const int* __restrict__ tasks, int ntasks,
                                                   const Tb* __restrict__ blk,
                                                   const int* __restrict__ blk_col,
+                                                  const int* __restrict__ blk_slot,
                                                   const Tv* __restrict__ x, Tv* __restrict__ partial,
                                                   Tv* __restrict__ colpart, int r) {
-  const int wave = int((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  constexpr bool NTL = sizeof(Tb) < 8;
+  const int wave = __builtin_amdgcn_readfirstlane(int((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   if (wave >= ntasks) return;
   const int lane = threadIdx.x & 63;
   const int a = lane >> 3, b = lane & 7;
   const int row = tasks[3 * wave], b0 = tasks[3 * wave + 1], b1 = tasks[3 * wave + 2];
+  const int rr = FULL ? 8 * T : r;
   Tv xs[T], acc[T];
 #pragma unroll
   for (int u = 0; u < T; ++u) {
     const int i = a * T + u;
-    xs[u] = i < r ? x[int64_t(row) * r + i] : zero<Tv>();
+    xs[u] = (FULL || i < rr) ? x[int64_t(row) * rr + i] : zero<Tv>();
     acc[u] = zero<Tv>();
   }
+  int col = blk_col[b0];
   for (int bi = b0; bi < b1; ++bi) {
-    const int col = blk_col[bi];
+    Tv B[T * T];
+    load_subtile<T, Tb, Tv, NTL>(blk + int64_t(bi) * tile_elems(T), lane, B);
+    const int col_next = bi + 1 < b1 ? blk_col[bi + 1] : col;
     Tv xt[T];
 #pragma unroll
     for (int v = 0; v < T; ++v) {
       const int j = b * T + v;
-      xt[v] = j < r ? x[int64_t(col) * r + j] : zero<Tv>();
+      xt[v] = (FULL || j < rr) ? x[int64_t(col) * rr + j] : zero<Tv>();
     }
-    Tv B[T * T];
-    load_subtile<T, Tb, Tv>(blk + int64_t(bi) * tile_elems(T), lane, B);
 #pragma unroll
     for (int u = 0; u < T; ++u)
 #pragma unroll
@@ -72,19 +142,15 @@ __global__ __launch_bounds__(256) void k_bsr_gemv(const int* __restrict__ tasks,
         Tv s = zero<Tv>();
 #pragma unroll
         for (int u = 0; u < T; ++u) s += B[u * T + v] * xs[u];
-        s += shfl_xor(s, 8);
-        s += shfl_xor(s, 16);
-        s += shfl_xor(s, 32);
         z[v] = s;
       }
-      if (a == 0) {
-#pragma unroll
-        for (int v = 0; v < T; ++v) {
-          const int j = b * T + v;
-          if (j < r) colpart[int64_t(bi) * r + j] = z[v];
-        }
-      }
+      const Tv zs = transpose_reduce_a<T, Tv>(z, a);
+      const int v = reduced_index<T>(a);
+      const int j = b * T + v;
+      if ((T == 8 || (a & ((8 / T) - 1)) == 0) && (FULL || j < rr))
+        colpart[int64_t(blk_slot[bi]) * rr + j] = zs;
     }
+    col = col_next;
   }
 #pragma unroll
   for (int u = 0; u < T; ++u) {
@@ -98,38 +164,68 @@ __global__ __launch_bounds__(256) void k_bsr_gemv(const int* __restrict__ tasks,
 #pragma unroll
     for (int u = 0; u < T; ++u) {
       const int i = a * T + u;
-      if (i < r) partial[int64_t(wave) * r + i] = acc[u];
+      if (FULL || i < rr) partial[int64_t(wave) * rr + i] = acc[u];
     }
   }
 }
 
-struct RedSrc {
-  const int* row_task_ptr;
-  const int* col_ptr;
-  const int* col_blk;
-  int base;
+// Sources of one depth for the reduce: task partials of the row (contiguous
+// in the launch) and column contributions (contiguous slots).
+struct RedDepth {
+  const int* rtp[2];     // row -> task offsets within the view
+  const int* cptr[2];    // row -> column-slot offsets within the view
+  int base[2];           // task base of the view in the GEMV launch
+  int slot[2];           // slot base of the view
+  int nsrc;
+  int row0;              // first grid row of this depth
+  int64_t out_off;       // element offset of the depth in the output buffer
+};
+constexpr int MAX_RED_DEPTHS = 20;
+struct RedArgs {
+  RedDepth dep[MAX_RED_DEPTHS];
+  int ndep;
+  int nrows;
 };
 
-// out[s] = addend[s] + sum of task partials of row s + sum of column
-// contributions of blocks whose column is s, in a fixed order.
+// One wave per row of any depth: out = sum of its partials, in a fixed order.
 template <typename Tv>
-__global__ __launch_bounds__(256) void k_reduce(int nrows, RedSrc s0, RedSrc s1, int nsrc,
-                                                const Tv* __restrict__ partial,
-                                                const Tv* __restrict__ colpart,
-                                                const Tv* __restrict__ addend, Tv* __restrict__ out,
-                                                int r) {
-  const int row = int((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+__global__ __launch_bounds__(256) void k_reduce(RedArgs A, const Tv* __restrict__ partial,
+                                                const Tv* __restrict__ colpart, Tv* __restrict__ out,
+                                                Tv* __restrict__ out_last, int r) {
+  const int grow = int((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const int i = threadIdx.x & 63;
-  if (row >= nrows || i >= r) return;
-  Tv v = addend ? addend[int64_t(row) * r + i] : zero<Tv>();
-  for (int q = 0; q < nsrc; ++q) {
-    const RedSrc& s = q == 0 ? s0 : s1;
-    for (int t = s.row_task_ptr[row]; t < s.row_task_ptr[row + 1]; ++t)
-      v += partial[int64_t(s.base + t) * r + i];
-    for (int c = s.col_ptr[row]; c < s.col_ptr[row + 1]; ++c)
-      v += colpart[int64_t(s.col_blk[c]) * r + i];
+  if (grow >= A.nrows) return;
+  int q = 0;
+  while (q + 1 < A.ndep && A.dep[q + 1].row0 <= grow) ++q;
+  const RedDepth& D = A.dep[q];
+  const int row = grow - D.row0;
+  if (i >= r) return;
+  Tv v0 = zero<Tv>(), v1 = zero<Tv>(), v2 = zero<Tv>(), v3 = zero<Tv>();
+  for (int sidx = 0; sidx < D.nsrc; ++sidx) {
+    const Tv* pp = partial + int64_t(D.base[sidx]) * r + i;
+    int t = D.rtp[sidx][row];
+    const int t1 = D.rtp[sidx][row + 1];
+    for (; t + 4 <= t1; t += 4) {
+      v0 += pp[int64_t(t) * r];
+      v1 += pp[int64_t(t + 1) * r];
+      v2 += pp[int64_t(t + 2) * r];
+      v3 += pp[int64_t(t + 3) * r];
+    }
+    for (; t < t1; ++t) v0 += pp[int64_t(t) * r];
+    const Tv* cp = colpart + int64_t(D.slot[sidx]) * r + i;
+    int c = D.cptr[sidx][row];
+    const int c1 = D.cptr[sidx][row + 1];
+    for (; c + 4 <= c1; c += 4) {
+      v0 += cp[int64_t(c) * r];
+      v1 += cp[int64_t(c + 1) * r];
+      v2 += cp[int64_t(c + 2) * r];
+      v3 += cp[int64_t(c + 3) * r];
+    }
+    for (; c < c1; ++c) v0 += cp[int64_t(c) * r];
   }
-  out[int64_t(row) * r + i] = v;
+  const Tv v = (v0 + v1) + (v2 + v3);
+  if (out_last && q == A.ndep - 1) out_last[int64_t(row) * r + i] = v;
+  else out[D.out_off + int64_t(row) * r + i] = v;
 }
 
 // ------------------------------------------------------------ transfers
@@ -421,40 +517,64 @@ void launch_gemv(H2& h, int p, const Launch& l, const void* x_all) {
   dispatch_T(h.T, [&](auto Tc) {
     constexpr int T = decltype(Tc)::value;
     const dim3 g(grid_waves(l.ntasks)), b(256);
-    if (p == P64)
-      hipLaunchKernelGGL((k_bsr_gemv<T, double, double>), g, b, 0, h.stream, l.task, l.ntasks,
-                         static_cast<const double*>(h.prec[P64].blk), h.blk_col,
-                         static_cast<const double*>(x_all), h.partial, h.colpart, h.r);
-    else if (p == P32)
-      hipLaunchKernelGGL((k_bsr_gemv<T, float, float>), g, b, 0, h.stream, l.task, l.ntasks,
-                         static_cast<const float*>(h.prec[P32].blk), h.blk_col,
-                         static_cast<const float*>(x_all), reinterpret_cast<float*>(h.partial),
-                         reinterpret_cast<float*>(h.colpart), h.r);
-    else
-      hipLaunchKernelGGL((k_bsr_gemv<T, bf16, float>), g, b, 0, h.stream, l.task, l.ntasks,
-                         static_cast<const bf16*>(h.prec[P16].blk), h.blk_col,
-                         static_cast<const float*>(x_all), reinterpret_cast<float*>(h.partial),
-                         reinterpret_cast<float*>(h.colpart), h.r);
+    auto go = [&](auto fullc) {
+      constexpr bool F = decltype(fullc)::value;
+      if (p == P64)
+        hipLaunchKernelGGL((k_bsr_gemv<T, F, double, double>), g, b, 0, h.stream, l.task, l.ntasks,
+                           static_cast<const double*>(h.prec[P64].blk), h.blk_col, h.blk_slot,
+                           static_cast<const double*>(x_all), h.partial, h.colpart, h.r);
+      else if (p == P32)
+        hipLaunchKernelGGL((k_bsr_gemv<T, F, float, float>), g, b, 0, h.stream, l.task, l.ntasks,
+                           static_cast<const float*>(h.prec[P32].blk), h.blk_col, h.blk_slot,
+                           static_cast<const float*>(x_all), reinterpret_cast<float*>(h.partial),
+                           reinterpret_cast<float*>(h.colpart), h.r);
+      else
+        hipLaunchKernelGGL((k_bsr_gemv<T, F, bf16, float>), g, b, 0, h.stream, l.task, l.ntasks,
+                           static_cast<const bf16*>(h.prec[P16].blk), h.blk_col, h.blk_slot,
+                           static_cast<const float*>(x_all), reinterpret_cast<float*>(h.partial),
+                           reinterpret_cast<float*>(h.colpart), h.r);
+    };
+    if (h.r == 8 * T) go(std::true_type{});
+    else go(std::false_type{});
   });
   check_launch("bsr_gemv");
   h.time_end(KS_GEMV64 + p, ev, double(l.nblocks) * h.r * h.r * elem_bytes(p));
 }
 
-void launch_reduce(H2& h, int p, int d, const View* v0, int base0, const View* v1, int base1,
-                   const void* addend, void* out) {
-  const int nrows = 1 << d;
-  RedSrc s0{v0->row_task_ptr, v0->col_ptr, v0->col_blk, base0};
-  RedSrc s1 = v1 ? RedSrc{v1->row_task_ptr, v1->col_ptr, v1->col_blk, base1} : s0;
-  const int nsrc = v1 ? 2 : 1;
-  const dim3 g(grid_waves(nrows)), b(256);
+void launch_reduce(H2& h, int p, int d0, int d1, const View* const* v0, const int* base0,
+                   const View* const* v1, const int* base1, void* out, void* out_last) {
+  RedArgs A{};
+  A.ndep = d1 - d0 + 1;
+  if (A.ndep > MAX_RED_DEPTHS) throw std::runtime_error("too many depths for one reduce");
+  int rows = 0;
+  for (int q = 0; q < A.ndep; ++q) {
+    const int d = d0 + q;
+    RedDepth& D = A.dep[q];
+    D.rtp[0] = v0[q]->row_task_ptr;
+    D.cptr[0] = v0[q]->col_ptr;
+    D.base[0] = base0[q];
+    D.slot[0] = v0[q]->slot_base;
+    D.nsrc = 1;
+    if (v1 && v1[q]) {
+      D.rtp[1] = v1[q]->row_task_ptr;
+      D.cptr[1] = v1[q]->col_ptr;
+      D.base[1] = base1[q];
+      D.slot[1] = v1[q]->slot_base;
+      D.nsrc = 2;
+    }
+    D.row0 = rows;
+    D.out_off = int64_t((1 << d) - 1) * h.r;
+    rows += 1 << d;
+  }
+  A.nrows = rows;
+  const dim3 g(grid_waves(rows)), b(256);
   if (p == P64)
-    hipLaunchKernelGGL(k_reduce<double>, g, b, 0, h.stream, nrows, s0, s1, nsrc, h.partial,
-                       h.colpart, static_cast<const double*>(addend), static_cast<double*>(out), h.r);
+    hipLaunchKernelGGL(k_reduce<double>, g, b, 0, h.stream, A, h.partial, h.colpart,
+                       static_cast<double*>(out), static_cast<double*>(out_last), h.r);
   else
-    hipLaunchKernelGGL(k_reduce<float>, g, b, 0, h.stream, nrows, s0, s1, nsrc,
-                       reinterpret_cast<const float*>(h.partial),
-                       reinterpret_cast<const float*>(h.colpart),
-                       static_cast<const float*>(addend), static_cast<float*>(out), h.r);
+    hipLaunchKernelGGL(k_reduce<float>, g, b, 0, h.stream, A, reinterpret_cast<const float*>(h.partial),
+                       reinterpret_cast<const float*>(h.colpart), static_cast<float*>(out),
+                       static_cast<float*>(out_last), h.r);
   check_launch("reduce");
 }
 
