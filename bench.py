@@ -47,6 +47,11 @@ def parse():
                     help="workload of part A ('' to skip part A)")
     ap.add_argument("--headline-cycles", type=int, default=4)
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--spd-probe", default="",
+                    help="n:cycles:shift,... run FP64 V-cycles of the headline shape and report "
+                         "the Rayleigh quotient of the final iterate")
+    ap.add_argument("--spd-probe-oracle", action="store_true",
+                    help="also evaluate the Rayleigh quotient with the CPU oracle's matvec")
     ap.add_argument("--n", type=int, default=0, help="override the number of points")
     ap.add_argument("--max-cycles", type=int, default=500)
     ap.add_argument("--mixed", default="fp32", choices=["fp32", "bf16"])
@@ -61,6 +66,28 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def profiled_traffic(kind):
+    """HBM bytes per launch of the block GEMV measured by rocprofv3 counters
+    (profiles/gemv_counters_*.md), or None when the kernel source changed
+    since the counters were taken."""
+    import glob
+    import hashlib
+    import re
+    csrc = os.path.join(ROOT, "paper_2501_17656_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("kernels_apply.hip", "device_common.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    cur = h.hexdigest()[:16]
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "gemv_counters_*.md"))):
+        with open(path) as fh:
+            for line in fh:
+                m = re.match(r"\s*traffic (\S+) src=(\S+) per_launch_bytes=(\S+)", line)
+                if m and m.group(1) == kind and m.group(2) == cur:
+                    return float(m.group(3))
+    return None
+
+
 def block_gemv_roofline(g, kind, bytes_per_sec_peak=HBM_PEAK_GBS):
     st = g.kernel_stats(kind)
     if st["launches"] == 0 or st["ms"] == 0:
@@ -69,7 +96,8 @@ def block_gemv_roofline(g, kind, bytes_per_sec_peak=HBM_PEAK_GBS):
     avg_bytes = st["work"] / st["launches"]
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": bytes_per_sec_peak,
-            "unit": "GB/s", "frac": round(achieved / bytes_per_sec_peak, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / bytes_per_sec_peak, 4),
+            "traffic": profiled_traffic(kind),
             "kernel": f"k_bsr_gemv ({kind})", "launches": st["launches"],
             "avg_launch_ms": round(avg_ms, 4), "avg_bytes_per_launch": avg_bytes}
 
@@ -118,6 +146,39 @@ def copy_probe(gb: float = 8.0, reps: int = 5):
     dt = (time.perf_counter() - t0) / reps
     print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8,
                       "reps": reps, "gbs_read_plus_write": round(2 * n * 8 / dt / 1e9, 1)}))
+
+
+def spd_probe(args, torch, synth, H2Matrix):
+    """Positive-definiteness probe of the H2 approximation of the headline
+    shape: after `cycles` FP64 V-cycles on A_H2 x = b, report the residual
+    history and x^T A_H2 x / x^T x (negative: A_H2 is indefinite)."""
+    import dataclasses
+    base = synth.workload(args.headline or "matern3d_1m")
+    for item in args.spd_probe.split(","):
+        n, cycles, shift = item.split(":")
+        w = dataclasses.replace(base.scaled(int(n)), shift=float(shift))
+        P = w.make_points()
+        pts = torch.from_numpy(P).cuda()
+        b = torch.from_numpy(w.make_rhs()).cuda()
+        g = H2Matrix(pts, w.kernel, w.length_scale, w.shift, w.leaf, w.eta, w.cheb_m)
+        g.setup()
+        x, info = g.solve(b, rtol=1e-8, max_cycles=int(cycles), raise_on_error=False)
+        ax = g.matvec(x)
+        torch.cuda.synchronize()
+        rq = float((x @ ax) / (x @ x))
+        out = {"spd_probe": w.name, "n": w.n, "shift": w.shift, "cycles": info["cycles"],
+               "status": info["status"], "rel_residual": info["rel_residual"],
+               "residual_history_every_10": [round(v, 4) for v in info["history"][::10]],
+               "x_norm": float(x.norm()), "rayleigh_gpu": rq}
+        if args.spd_probe_oracle:
+            from oracle.h2 import H2 as OracleH2
+            xh = x.cpu().numpy()
+            o = OracleH2(P, w.kernel, w.shift, w.leaf, w.eta, w.cheb_m, w.length_scale)
+            out["rayleigh_oracle"] = float(xh @ o.matvec(xh) / (xh @ xh))
+        print(json.dumps(out), flush=True)
+        g.close()
+        del pts, b, x, ax
+        torch.cuda.empty_cache()
 
 
 def part_a(args, torch, synth, H2Matrix):
@@ -198,6 +259,9 @@ def main():
 
     if args.copy_probe:
         copy_probe()
+        return
+    if args.spd_probe:
+        spd_probe(args, torch, synth, H2Matrix)
         return
     headline = part_a(args, torch, synth, H2Matrix) if args.headline else None
     if headline:
