@@ -12,7 +12,10 @@ diagonal shift raised to 1 (positive definite approximation).  One step =
 build the H2 matrix (tree, bases, couplings), build the hierarchy (projected
 close blocks, coarsest Cholesky, FP32 copies), solve A_H2 x = b to a 1e-8
 relative residual in FP64, then again with FP32 operators inside FP64
-iterative refinement.  `value` is the mixed-precision time-to-1e-8.
+iterative refinement, both with the block smoother on the diagonal blocks.
+`value` is the mixed-precision time-to-1e-8.  After the timed step the same
+two solves are repeated with the paper's plain CG smoother and reported
+(--no-cg skips them).
 
 Inputs are generated on the host and copied to HBM before the timed region;
 every numerical step runs in libh2mg.so.  Prints one JSON line.
@@ -55,6 +58,9 @@ def parse():
     ap.add_argument("--n", type=int, default=0, help="override the number of points")
     ap.add_argument("--max-cycles", type=int, default=500)
     ap.add_argument("--mixed", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--smoother", default="bj", choices=["bj", "cg"])
+    ap.add_argument("--no-cg", action="store_true",
+                    help="skip the paper's plain-CG smoother solves after the timed step")
     ap.add_argument("--matvec-reps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-leaves", type=int, default=3)
@@ -219,6 +225,8 @@ def part_a(args, torch, synth, H2Matrix):
                     raise_on_error=False)
     rlm = block_gemv_roofline(g, "gemv_" + args.mixed)
     g.set_timing(False)
+    _, ibj = g.solve(b, rtol=1e-8, max_cycles=args.headline_cycles, precision="fp64",
+                     smoother="bj", raise_on_error=False)
     out = {
         "workload": f"{w.name}: N={w.n}, {w.kernel} l={w.length_scale} + {w.shift}*I, leaf {w.leaf}, "
                     f"eta {w.eta}, rank {w.rank}",
@@ -234,6 +242,8 @@ def part_a(args, torch, synth, H2Matrix):
         "fp64_residual_history": [round(v, 4) for v in i64["history"]],
         "mixed_steps_run": im["cycles"], "mixed_s_per_step": round(im["solve_seconds"] / max(im["cycles"], 1), 3),
         "mixed_residual_history": [round(v, 4) for v in im["history"]],
+        "block_smoother_fp64": {"cycles_run": ibj["cycles"], "status": ibj["status"],
+                                "residual_history": [round(v, 4) for v in ibj["history"]]},
         "converges": False,
         "why": ("the rank-64 Chebyshev H2 approximation of this matrix is indefinite at this size "
                 "(negative Rayleigh quotients of diverged V-cycle iterates from N = 65536 on), so "
@@ -294,7 +304,7 @@ def main():
             f"memory {g.memory_bytes() / 1e9:.1f} GB")
         g.set_timing(True)
         x64, i64 = g.solve(b_d, rtol=1e-8, max_cycles=args.max_cycles, precision="fp64",
-                           raise_on_error=False)
+                           smoother=args.smoother, raise_on_error=False)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         log(f"fp64 solve {t3 - t2:.2f} s, cycles {i64['cycles']}, rel res {i64['rel_residual']:.2e}, "
@@ -302,7 +312,7 @@ def main():
         rl64 = block_gemv_roofline(g, "gemv_fp64")
         g.set_timing(True)
         xm, im = g.solve(b_d, rtol=1e-8, max_cycles=args.max_cycles, precision=args.mixed,
-                         raise_on_error=False)
+                         smoother=args.smoother, raise_on_error=False)
         torch.cuda.synchronize()
         t4 = time.perf_counter()
         log(f"{args.mixed}+fp64 refinement solve {t4 - t3:.2f} s, steps {im['cycles']}, "
@@ -334,6 +344,22 @@ def main():
         times.append(time.perf_counter() - t0)
     g = rec["g"]
     res64, resm = rec["i64"], rec["im"]
+    cg_runs = None
+    if not args.no_cg and args.smoother != "cg":
+        cg_runs = {}
+        for prec in ("fp64", args.mixed):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = g.solve(b_d, rtol=1e-8, max_cycles=args.max_cycles, precision=prec,
+                              smoother="cg", raise_on_error=False)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            log(f"paper CG smoother, {prec}: {dt:.2f} s, cycles {info['cycles']}, "
+                f"rel res {info['rel_residual']:.2e}, status {info['status']}")
+            cg_runs[prec] = {"time_to_1e-8_s": round(dt, 3), "cycles": info["cycles"],
+                             "converged": info["converged"], "rel_residual": info["rel_residual"]}
+        cg_runs["speedup_mixed_vs_fp64"] = round(cg_runs["fp64"]["time_to_1e-8_s"] /
+                                                 cg_runs[args.mixed]["time_to_1e-8_s"], 3)
     mixed_ok = resm["converged"]
     # agreement of the two solutions (both at 1e-8 relative residual)
     dx = float((rec["xm"] - rec["x64"]).norm() / rec["x64"].norm())
@@ -355,8 +381,9 @@ def main():
                          f"l={w.length_scale} + {w.shift}*I (shift raised from 1e-3: the rank-64 "
                          f"Chebyshev approximation of the 1e-3 matrix is indefinite), leaf {w.leaf}, "
                          f"eta {w.eta}, Chebyshev {w.cheb_m}^{w.dim} (rank {w.rank}), b ~ N(0,1), "
-                         f"rtol 1e-8, n_f=1, n_c=40; step = build + hierarchy + FP64 solve + "
-                         f"{args.mixed}-refinement solve"),
+                         f"rtol 1e-8, n_f=1, n_c=40, smoother {args.smoother} "
+                         f"({'CG preconditioned by the diagonal blocks' if args.smoother == 'bj' else 'plain CG'}); "
+                         f"step = build + hierarchy + FP64 solve + {args.mixed}-refinement solve"),
             "levels": g.levels,
         },
         "fp64_time_to_1e-8_s": round(rec["fp64_s"], 3),
@@ -373,6 +400,7 @@ def main():
         "device_memory_gb": round(g.memory_bytes() / 1e9, 1),
         "roofline": rec["rlm"] if mixed_ok and rec["rlm"] else rec["rl64"],
         "roofline_fp64_gemv": rec["rl64"],
+        "paper_cg_smoother": cg_runs,
         "headline_shift_1e-3": headline,
     }
     if not args.no_cpu:

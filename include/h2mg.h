@@ -89,8 +89,18 @@ typedef enum h2mg_precision {
   H2MG_BF16_IR = 2       /* V-cycle on BF16 operators inside FP64 refinement */
 } h2mg_precision;
 
+/* Smoothers (Iter in Algorithm 1).  H2MG_SMOOTHER_CG: plain CG, the paper's
+ * choice (Section 3.3).  H2MG_SMOOTHER_BLOCK_JACOBI: CG preconditioned by the
+ * inverse diagonal blocks of each level's operator -- the leaf blocks
+ * K_ss + shift*I on the finest level (requires leaves of at most 128
+ * points), the projected diagonal blocks on coarser levels. */
+typedef enum h2mg_smoother {
+  H2MG_SMOOTHER_CG = 0,
+  H2MG_SMOOTHER_BLOCK_JACOBI = 1
+} h2mg_smoother;
+
 /* Solver options (Section 3.3, Algorithm 1 and the remark on fine and
- * coarse iterations).  n_fine / n_coarse CG steps pre- and post-smoothing on
+ * coarse iterations).  n_fine / n_coarse smoothing steps pre and post on
  * the finest / coarser levels; the solve stops when
  * ||b - A_H2 x||_2 / ||b||_2 < rtol, measured in FP64, or after max_cycles
  * V-cycles (FP64) or refinement steps (mixed forms, one V-cycle each). */
@@ -101,6 +111,7 @@ typedef struct h2mg_solve_opts {
   int32_t max_cycles;    /* >= 0 */
   int32_t precision;     /* h2mg_precision */
   int32_t use_x0;        /* 1: x holds the initial guess; 0: start from 0 */
+  int32_t smoother;      /* h2mg_smoother */
 } h2mg_solve_opts;
 
 typedef struct h2mg_solve_info {

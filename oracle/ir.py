@@ -56,7 +56,8 @@ def lowered(H, precision: str):
 
 
 def ir_solve(H, b: np.ndarray, precision: str = "fp32", rtol: float = 1e-8,
-             max_outer: int = 500, n_f: int = 1, n_c: int = 40) -> SolveResult:
+             max_outer: int = 500, n_f: int = 1, n_c: int = 40,
+             smoother: str = "cg") -> SolveResult:
     A = H.ops[0]
     Hl = lowered(H, precision)
     factor = coarsest_factor(H.ops[-1])
@@ -73,5 +74,6 @@ def ir_solve(H, b: np.ndarray, precision: str = "fp32", rtol: float = 1e-8,
             return SolveResult(x, it, True, hist)
         if it == max_outer:
             break
-        x = x + vcycle(Hl, np.zeros_like(b), res, n_f, n_c, factor, r1=res)
+        x = x + vcycle(Hl, np.zeros_like(b), res, n_f, n_c, factor, r1=res,
+                       smoother=smoother)
     return SolveResult(x, max_outer, False, hist)

@@ -16,7 +16,10 @@ Readings:
 * both pre- and post-smoothing use n_f steps on level 1 and n_c elsewhere;
 * outer loop: x_0 = 0; before each cycle the FP64 residual b - A_H2 x is
   measured and the loop stops when ||b - A_H2 x|| / ||b|| < rtol
-  (rtol = 1e-8) or after max_cycles cycles.
+  (rtol = 1e-8) or after max_cycles cycles;
+* smoother "bj": preconditioned CG with M = the diagonal blocks of each
+  level's operator (leaf blocks of A_H2 on level 1, one r x r block per
+  cluster on coarser levels): a block smoother on the diagonal blocks.
 """
 from __future__ import annotations
 
@@ -25,7 +28,7 @@ import dataclasses
 import numpy as np
 import scipy.linalg
 
-from .cg import cg
+from .cg import block_jacobi, cg, pcg
 
 
 @dataclasses.dataclass
@@ -40,34 +43,59 @@ def coarsest_factor(A: np.ndarray):
     return scipy.linalg.cho_factor(A, lower=True)
 
 
+def level_offsets(H, i):
+    """Row blocks of level i+1 (0-based i): leaves on level 1, clusters of r
+    coefficients on coarser levels."""
+    h2 = H.h2
+    if i == 0:
+        return h2.tree.offsets[h2.L]
+    nb = H.ops[i].shape[0] // h2.r
+    return np.arange(nb + 1) * h2.r
+
+
+def smoothers(H, smoother):
+    if smoother == "cg":
+        return None
+    if smoother == "bj":
+        return [block_jacobi(H.ops[i], level_offsets(H, i)) for i in range(len(H.ops) - 1)]
+    raise ValueError(smoother)
+
+
 def vcycle(H, x0: np.ndarray, b: np.ndarray, n_f: int = 1, n_c: int = 40,
-           factor=None, r1=None) -> np.ndarray:
+           factor=None, r1=None, smoother="cg", precs=None) -> np.ndarray:
     """One V-cycle of Algorithm 1 on the dense hierarchy H (tree order)."""
     ops, P = H.ops, H.prolong
     l = len(ops)
     if factor is None:
         factor = coarsest_factor(ops[-1])
+    if precs is None:
+        precs = smoothers(H, smoother)
+
+    def iterate(i, rhs, e0, n):
+        if precs is None:
+            return cg(ops[i].__matmul__, rhs, e0, n)
+        return pcg(ops[i].__matmul__, precs[i], rhs, e0, n)
     r = [None] * l
     et = [None] * l
     r[0] = b - ops[0] @ x0 if r1 is None else r1
     for i in range(l - 1):
         n = n_f if i == 0 else n_c
-        apply = ops[i].__matmul__
-        et[i] = cg(apply, r[i], None, n)
-        r[i + 1] = P[i].T @ (r[i] - apply(et[i]))
+        et[i] = iterate(i, r[i], None, n)
+        r[i + 1] = P[i].T @ (r[i] - ops[i] @ et[i])
     e = scipy.linalg.cho_solve(factor, r[l - 1])
     for i in range(l - 2, -1, -1):
         n = n_f if i == 0 else n_c
         et[i] = et[i] + P[i] @ e
-        e = cg(ops[i].__matmul__, r[i], et[i], n)
+        e = iterate(i, r[i], et[i], n)
     return x0 + e
 
 
 def solve(H, b: np.ndarray, rtol: float = 1e-8, max_cycles: int = 500,
-          n_f: int = 1, n_c: int = 40, x0=None) -> SolveResult:
+          n_f: int = 1, n_c: int = 40, x0=None, smoother="cg") -> SolveResult:
     """Repeated V-cycles on A_H2 x = b (b and x in tree order)."""
     A = H.ops[0]
     factor = coarsest_factor(H.ops[-1])
+    precs = smoothers(H, smoother)
     x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
     nb = float(np.linalg.norm(b))
     hist = []
@@ -81,7 +109,7 @@ def solve(H, b: np.ndarray, rtol: float = 1e-8, max_cycles: int = 500,
             return SolveResult(x, cyc, True, hist)
         if cyc == max_cycles:
             break
-        x = vcycle(H, x, b, n_f, n_c, factor, r1=res)
+        x = vcycle(H, x, b, n_f, n_c, factor, r1=res, precs=precs)
     return SolveResult(x, max_cycles, False, hist)
 
 

@@ -26,6 +26,7 @@ struct SolveParams {
   int max_cycles = 500;
   int precision = 0;
   bool use_x0 = false;
+  int smoother = 0;      // 0: CG, 1: block-Jacobi preconditioned CG
 };
 // Solve A_H2 x = b; b, x device, user order.  Fills info.
 h2mg_status solve(H2& h, const double* b, double* x, const SolveParams& sp, h2mg_solve_info* info);

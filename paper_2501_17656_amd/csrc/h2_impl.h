@@ -142,6 +142,12 @@ struct H2 {
   double* dot_part = nullptr;          // reduction partials (several slots)
   std::vector<double> history;
 
+  // block-Jacobi smoother: inverse diagonal blocks per level and precision
+  bool bj_built[3] = {false, false, false};
+  int bj_ld = 0;                       // padded leaf block size of the finest level
+  void* bj_fine[3] = {nullptr, nullptr, nullptr};   // nleaf blocks of bj_ld^2
+  void* bj_coarse[3] = {nullptr, nullptr, nullptr}; // per gid r^2 (depths d_top+1..L)
+
   // kernel timing
   bool timing = false;
   std::vector<hipEvent_t> events;
@@ -172,6 +178,11 @@ void launch_assemble_dense(H2& h, double* A, int64_t lda);  // depth d_top block
 void launch_assemble_kernel_dense(H2& h, double* A, int64_t lda);  // no far blocks
 void launch_potrf(H2& h, double* A, int64_t N);   // blocked Cholesky, sets flags[0]
 void launch_cast_precision(H2& h, int p);         // FP64 -> FP32 / BF16 copies
+// Inverses of the block-Jacobi blocks: leaf blocks K_ss + shift (FP64) and the
+// projected diagonal blocks of depths d_top+1..L (FP64); sets flags[0] on a
+// non-positive pivot.
+void launch_bj_inverse_fine(H2& h, double* out, int ld);
+void launch_bj_inverse_coarse(H2& h, int d, const int* diag_blk, double* out);
 
 // ------------------------------------------------------------ apply kernels
 // All vectors are in the precision's vector type: double (P64) or float.
@@ -214,5 +225,8 @@ void launch_cg_pupdate(H2& h, int p, int64_t n, void* pv, const void* s,
                        const double* gamma_old_part, const double* gamma_new_part);
 void launch_chol_solve(H2& h, const double* L, int64_t N, double* x);   // in place
 void launch_check_finite(H2& h, int p, int64_t n, const void* x);      // sets flags[1]
+// z = M^{-1} s on one level (block-Jacobi): level 1 uses the leaf blocks,
+// level k >= 2 the r x r blocks of its depth.
+void launch_bj_apply(H2& h, int p, int k, const void* s, void* z);
 
 }  // namespace h2mg

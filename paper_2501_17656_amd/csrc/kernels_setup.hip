@@ -546,6 +546,77 @@ __global__ __launch_bounds__(NT) void k_syrk_update(double* A, int64_t N, int64_
   }
 }
 
+// ------------------------------------------------------------ block-Jacobi inverses
+// In-place Gauss-Jordan inversion of an n x n SPD matrix in LDS (row-major,
+// stride n), without pivoting (the pivots of an SPD matrix stay positive).
+__device__ void gauss_jordan_spd(double* A, int n, double* fk, int* flag) {
+  const int tid = threadIdx.x;
+  for (int k = 0; k < n; ++k) {
+    __syncthreads();
+    const double piv = A[k * n + k];
+    if (!(piv > 0.0)) {
+      if (tid == 0) atomicOr(flag, 1);
+      return;
+    }
+    const double ip = 1.0 / piv;
+    for (int i = tid; i < n; i += NT) fk[i] = A[i * n + k];
+    __syncthreads();
+    for (int j = tid; j < n; j += NT) A[k * n + j] = (j == k ? 1.0 : A[k * n + j]) * ip;
+    __syncthreads();
+    for (int idx = tid; idx < n * n; idx += NT) {
+      const int i = idx / n, j = idx % n;
+      if (i == k) continue;
+      const double a = j == k ? 0.0 : A[idx];
+      A[idx] = a - fk[i] * A[k * n + j];
+    }
+  }
+  __syncthreads();
+}
+
+// Inverse of K_ss + shift I for every leaf s, written as ld x ld blocks
+// (entries beyond the leaf size are zero).
+__global__ __launch_bounds__(NT) void k_bj_inv_fine(const int* __restrict__ leaf_off,
+                                                    const double* __restrict__ pts, int dim,
+                                                    KernelParams kp, double* __restrict__ out,
+                                                    int ld, int* flag) {
+  extern __shared__ double smem[];
+  const int leaf = blockIdx.x, tid = threadIdx.x;
+  const int s0 = leaf_off[leaf], n = leaf_off[leaf + 1] - s0;
+  double* A = smem;
+  double* fk = A + size_t(n) * n;
+  for (int idx = tid; idx < n * n; idx += NT) {
+    const int i = idx / n, j = idx % n;
+    double r2 = 0.0;
+    for (int a = 0; a < dim; ++a) {
+      const double dx = pts[int64_t(s0 + i) * dim + a] - pts[int64_t(s0 + j) * dim + a];
+      r2 += dx * dx;
+    }
+    A[idx] = kernel_r2(kp, r2) + (i == j ? kp.shift : 0.0);
+  }
+  gauss_jordan_spd(A, n, fk, flag);
+  double* o = out + int64_t(leaf) * ld * ld;
+  for (int idx = tid; idx < ld * ld; idx += NT) {
+    const int i = idx / ld, j = idx % ld;
+    o[idx] = (i < n && j < n) ? A[i * n + j] : 0.0;
+  }
+}
+
+// Inverse of the diagonal block of every cluster at depth d (its projected
+// close block with itself), written r x r at the cluster's gid.
+__global__ __launch_bounds__(NT) void k_bj_inv_coarse(int d, const int* __restrict__ diag_blk,
+                                                      const double* __restrict__ blk, int r, int T,
+                                                      double* __restrict__ out, int* flag) {
+  extern __shared__ double smem[];
+  const int c = blockIdx.x, tid = threadIdx.x;
+  double* A = smem;
+  double* fk = A + size_t(r) * r;
+  const double* tl = blk + int64_t(diag_blk[c]) * tile_elems(T);
+  for (int idx = tid; idx < r * r; idx += NT) A[idx] = tl[tile_offset<double>(idx / r, idx % r, T)];
+  gauss_jordan_spd(A, r, fk, flag);
+  double* o = out + int64_t((1 << d) - 1 + c) * r * r;
+  for (int idx = tid; idx < r * r; idx += NT) o[idx] = A[idx];
+}
+
 // ------------------------------------------------------------ precision copies
 template <typename Td>
 __global__ __launch_bounds__(NT) void k_cast_tiles(const double* __restrict__ src, Td* __restrict__ dst,
@@ -664,6 +735,22 @@ void launch_potrf(H2& h, double* A, int64_t N) {
     }
   }
   check_launch("potrf");
+}
+
+void launch_bj_inverse_fine(H2& h, double* out, int ld) {
+  const int n = h.leaf_max;
+  const size_t lds = (size_t(n) * n + n) * sizeof(double);
+  allow_lds(k_bj_inv_fine, lds);
+  hipLaunchKernelGGL(k_bj_inv_fine, dim3(h.nleaf), dim3(NT), lds, h.stream, h.leaf_off, h.pts,
+                     h.dim, h.kp, out, ld, h.flags);
+  check_launch("bj_inv_fine");
+}
+
+void launch_bj_inverse_coarse(H2& h, int d, const int* diag_blk, double* out) {
+  const size_t lds = (size_t(h.r) * h.r + h.r) * sizeof(double);
+  hipLaunchKernelGGL(k_bj_inv_coarse, dim3(1 << d), dim3(NT), lds, h.stream, d, diag_blk,
+                     static_cast<const double*>(h.prec[P64].blk), h.r, h.T, out, h.flags);
+  check_launch("bj_inv_coarse");
 }
 
 void launch_cast_precision(H2& h, int p) {

@@ -141,6 +141,28 @@ __global__ __launch_bounds__(NT) void k_check_finite(int64_t n, const Tv* __rest
   if (i < n && !isfinite(double(x[i]))) atomicOr(flag, 1);
 }
 
+// z_b = M_b^{-1} s_b for every diagonal block b (one workgroup per block):
+// rows [off[b], off[b+1]) when off is given, else [b*stride, (b+1)*stride).
+// The stored inverses are symmetric, so thread i reads column i of block b,
+// coalesced across threads.
+template <typename Tm, typename Tv>
+__global__ __launch_bounds__(NT) void k_bj_apply(const int* __restrict__ off, int stride,
+                                                 const Tm* __restrict__ Minv, int ld,
+                                                 const Tv* __restrict__ s, Tv* __restrict__ z) {
+  __shared__ Tv sl[256];
+  const int b = blockIdx.x;
+  const int s0 = off ? off[b] : b * stride;
+  const int n = off ? off[b + 1] - s0 : stride;
+  for (int i = threadIdx.x; i < n; i += NT) sl[i] = s[s0 + i];
+  __syncthreads();
+  const Tm* M = Minv + int64_t(b) * ld * ld;
+  for (int i = threadIdx.x; i < n; i += NT) {
+    Tv acc = Tv(0);
+    for (int j = 0; j < n; ++j) acc += Tv(M[int64_t(j) * ld + i]) * sl[j];
+    z[s0 + i] = acc;
+  }
+}
+
 // ------------------------------------------------------------ triangular solves
 constexpr int NB = 64;
 
@@ -308,6 +330,28 @@ void launch_chol_solve(H2& h, const double* L, int64_t N, double* x) {
       hipLaunchKernelGGL(k_gemv_bwd, dim3(blocks(k0)), dim3(NT), 0, h.stream, L, N, k0, x);
   }
   check_launch("chol_solve");
+}
+
+void launch_bj_apply(H2& h, int p, int k, const void* s, void* z) {
+  const bool fine = k == 1;
+  const int d = h.level_depth(k);
+  const int nb = fine ? h.nleaf : (1 << d);
+  const int* off = fine ? h.leaf_off : nullptr;
+  const int ld = fine ? h.bj_ld : h.r;
+  const int stride = h.r;
+  const size_t eb = p == P64 ? 8 : 4;
+  const char* base = static_cast<const char*>(fine ? h.bj_fine[p == P64 ? P64 : P32]
+                                                   : h.bj_coarse[p == P64 ? P64 : P32]);
+  if (!fine) base += size_t((1 << d) - 1) * h.r * h.r * eb;
+  if (p == P64)
+    hipLaunchKernelGGL((k_bj_apply<double, double>), dim3(nb), dim3(NT), 0, h.stream, off, stride,
+                       reinterpret_cast<const double*>(base), ld, static_cast<const double*>(s),
+                       static_cast<double*>(z));
+  else
+    hipLaunchKernelGGL((k_bj_apply<float, float>), dim3(nb), dim3(NT), 0, h.stream, off, stride,
+                       reinterpret_cast<const float*>(base), ld, static_cast<const float*>(s),
+                       static_cast<float*>(z));
+  check_launch("bj_apply");
 }
 
 void launch_check_finite(H2& h, int p, int64_t n, const void* x) {

@@ -28,7 +28,8 @@ inline size_t vbytes(int p) { return p == P64 ? 8 : 4; }
 // Per-precision V-cycle vectors: r_k and e~_k per level, CG temporaries.
 struct Work {
   std::vector<void*> r, et;
-  void *s = nullptr, *pv = nullptr, *q = nullptr, *tmp = nullptr;
+  void *s = nullptr, *pv = nullptr, *q = nullptr, *tmp = nullptr, *z = nullptr;
+  int smoother = 0;
   double* gpart[2] = {nullptr, nullptr};
   double* dpart = nullptr;
 };
@@ -46,6 +47,7 @@ Work make_work(H2& h, int p) {
   w.pv = h.arena.alloc(size_t(h.n) * vb);
   w.q = h.arena.alloc(size_t(h.n) * vb);
   w.tmp = h.arena.alloc(size_t(h.n) * vb);
+  w.z = h.arena.alloc(size_t(h.n) * vb);
   w.gpart[0] = h.dot_part + 512;
   w.gpart[1] = h.dot_part + 1024;
   w.dpart = h.dot_part + 1536;
@@ -61,16 +63,25 @@ void release_work(H2& h, Work& w) {
   h.arena.release(w.pv);
   h.arena.release(w.q);
   h.arena.release(w.tmp);
+  h.arena.release(w.z);
 }
 
 void zero(H2& h, void* v, int64_t n, int p) {
   hip_check(hipMemsetAsync(v, 0, size_t(n) * vbytes(p), h.stream), "memset");
 }
 
-// e = Iter(A_k, rhs, e0): n CG steps; e holds e0 on entry unless e0_zero.
+void read_flags(H2& h, int* f) {
+  hip_check(hipMemcpyAsync(f, h.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, h.stream), "flags");
+  hip_check(hipStreamSynchronize(h.stream), "sync");
+}
+
+// e = Iter(A_k, rhs, e0): n CG steps (plain, or preconditioned by the
+// block-Jacobi inverses when w.smoother == 1); e holds e0 on entry unless
+// e0_zero.
 void cg(H2& h, int p, int k, Work& w, const void* rhs, void* e, bool e0_zero, int nsteps) {
   const int vp = vprec(p);
   const int64_t N = h.level_size(k);
+  const bool pre = w.smoother == 1;
   if (e0_zero) zero(h, e, N, vp);
   if (nsteps <= 0) return;
   if (e0_zero) {
@@ -80,16 +91,78 @@ void cg(H2& h, int p, int k, Work& w, const void* rhs, void* e, bool e0_zero, in
     launch_copy(h, vp, rhs, w.s, N);
     launch_axpby(h, vp, N, -1.0, w.q, 1.0, w.s);
   }
-  launch_copy(h, vp, w.s, w.pv, N);
   int cur = 0;
-  launch_dot(h, vp, N, w.s, w.s, w.gpart[cur]);
+  if (pre) {
+    launch_bj_apply(h, p, k, w.s, w.z);
+    launch_copy(h, vp, w.z, w.pv, N);
+    launch_dot(h, vp, N, w.s, w.z, w.gpart[cur]);
+  } else {
+    launch_copy(h, vp, w.s, w.pv, N);
+    launch_dot(h, vp, N, w.s, w.s, w.gpart[cur]);
+  }
+  double* scratch = h.dot_part + 2048;
   for (int it = 0; it < nsteps; ++it) {
     apply_level(h, p, k, w.pv, w.q);
     launch_dot(h, vp, N, w.pv, w.q, w.dpart);
-    launch_cg_update(h, vp, N, e, w.pv, w.s, w.q, w.gpart[cur], w.dpart, w.gpart[1 - cur]);
-    if (it + 1 < nsteps) launch_cg_pupdate(h, vp, N, w.pv, w.s, w.gpart[cur], w.gpart[1 - cur]);
+    if (pre) {
+      launch_cg_update(h, vp, N, e, w.pv, w.s, w.q, w.gpart[cur], w.dpart, scratch);
+      launch_bj_apply(h, p, k, w.s, w.z);
+      launch_dot(h, vp, N, w.s, w.z, w.gpart[1 - cur]);
+      if (it + 1 < nsteps) launch_cg_pupdate(h, vp, N, w.pv, w.z, w.gpart[cur], w.gpart[1 - cur]);
+    } else {
+      launch_cg_update(h, vp, N, e, w.pv, w.s, w.q, w.gpart[cur], w.dpart, w.gpart[1 - cur]);
+      if (it + 1 < nsteps) launch_cg_pupdate(h, vp, N, w.pv, w.s, w.gpart[cur], w.gpart[1 - cur]);
+    }
     cur = 1 - cur;
   }
+}
+
+// Inverse diagonal blocks for the block-Jacobi smoother (built once per
+// handle; FP32 copies for the low-precision forms).
+h2mg_status ensure_block_jacobi(H2& h, int p) {
+  if (!h.bj_built[P64]) {
+    if (h.leaf_max > 128)
+      return fail(H2MG_ERR_INVALID_ARG,
+                  "the block smoother needs leaves of at most 128 points (largest has %d)",
+                  h.leaf_max);
+    h.bj_ld = h.leaf_max;
+    double* fine = h.arena.make<double>(size_t(h.nleaf) * h.bj_ld * h.bj_ld);
+    double* coarse = h.arena.make<double>(size_t(h.ngid) * h.r * h.r);
+    hip_check(hipMemsetAsync(h.flags, 0, 4 * sizeof(int), h.stream), "memset");
+    launch_bj_inverse_fine(h, fine, h.bj_ld);
+    for (int d = h.d_top + 1; d <= h.L && h.d_top >= 0; ++d) {
+      std::vector<int> diag;
+      for (int b = h.p_first[d]; b < h.p_first[d] + h.p_count[d]; ++b)
+        if (h.blk_row_h[b] == h.blk_col_h[b]) diag.push_back(b);
+      if (int(diag.size()) != (1 << d)) return fail(H2MG_ERR_STATE, "missing diagonal block at depth %d", d);
+      int* dd = h.arena.make<int>(diag.size());
+      hip_check(hipMemcpyAsync(dd, diag.data(), diag.size() * sizeof(int), hipMemcpyHostToDevice, h.stream),
+                "upload");
+      launch_bj_inverse_coarse(h, d, dd, coarse);
+      hip_check(hipStreamSynchronize(h.stream), "bj");
+      h.arena.release(dd);
+    }
+    int f[4];
+    read_flags(h, f);
+    if (f[0]) {
+      h.arena.release(fine);
+      h.arena.release(coarse);
+      return fail(H2MG_ERR_NOT_SPD, "a diagonal block of the block smoother is not positive definite");
+    }
+    h.bj_fine[P64] = fine;
+    h.bj_coarse[P64] = coarse;
+    h.bj_built[P64] = true;
+  }
+  if (p != P64 && !h.bj_built[P32]) {
+    const int64_t nf = int64_t(h.nleaf) * h.bj_ld * h.bj_ld, nc = int64_t(h.ngid) * h.r * h.r;
+    h.bj_fine[P32] = h.arena.alloc(size_t(nf) * 4);
+    h.bj_coarse[P32] = h.arena.alloc(size_t(nc) * 4);
+    launch_cast(h, P32, h.bj_fine[P32], P64, h.bj_fine[P64], nf);
+    launch_cast(h, P32, h.bj_coarse[P32], P64, h.bj_coarse[P64], nc);
+    hip_check(hipStreamSynchronize(h.stream), "bj cast");
+    h.bj_built[P32] = true;
+  }
+  return H2MG_OK;
 }
 
 // Direct solve on the coarsest level (FP64 Cholesky factor): e = A_l^{-1} r.
@@ -139,10 +212,6 @@ double host_norm(H2& h, const double* v, int64_t n) {
   return std::sqrt(s);
 }
 
-void read_flags(H2& h, int* f) {
-  hip_check(hipMemcpyAsync(f, h.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, h.stream), "flags");
-  hip_check(hipStreamSynchronize(h.stream), "sync");
-}
 
 }  // namespace
 
@@ -152,6 +221,16 @@ h2mg_status solve(H2& h, const double* b, double* x, const SolveParams& sp, h2mg
   const int p = sp.precision == 0 ? P64 : sp.precision == 1 ? P32 : P16;
   h2mg_status st = setup_mg(h, p == P64 ? 0 : (1 << p));
   if (st != H2MG_OK) return st;
+  if (sp.smoother == 1) {
+    try {
+      st = ensure_block_jacobi(h, p);
+    } catch (const std::bad_alloc&) {
+      return fail(H2MG_ERR_OOM, "device allocation failed for the block smoother");
+    } catch (const std::exception& ex) {
+      return fail(H2MG_ERR_HIP, "%s", ex.what());
+    }
+    if (st != H2MG_OK) return st;
+  }
   Work w64, wlp;
   bool have_lp = false;
   h2mg_status result = H2MG_OK;
@@ -160,8 +239,10 @@ h2mg_status solve(H2& h, const double* b, double* x, const SolveParams& sp, h2mg
   double rel = 0.0;
   try {
     w64 = make_work(h, P64);
+    w64.smoother = sp.smoother;
     if (p != P64) {
       wlp = make_work(h, p);
+      wlp.smoother = sp.smoother;
       have_lp = true;
     }
     const int64_t n = h.n;
@@ -241,7 +322,12 @@ h2mg_status vcycle_once(H2& h, const double* x0, const double* b, double* x_out,
   h2mg_status st = setup_mg(h, 0);
   if (st != H2MG_OK) return st;
   try {
+    if (sp.smoother == 1) {
+      st = ensure_block_jacobi(h, P64);
+      if (st != H2MG_OK) return st;
+    }
     Work w = make_work(h, P64);
+    w.smoother = sp.smoother;
     const int64_t n = h.n;
     double* bt = static_cast<double*>(h.arena.alloc(size_t(n) * 8));
     double* xt = static_cast<double*>(h.arena.alloc(size_t(n) * 8));

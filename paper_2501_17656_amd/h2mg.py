@@ -15,6 +15,7 @@ from ._lib import check, lib
 
 KERNELS = {"exp": 0, "gauss": 1, "matern32": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
+SMOOTHERS = {"cg": 0, "bj": 1}
 
 
 def _stream():
@@ -137,24 +138,25 @@ class H2Matrix:
 
     # ------------------------------------------------------------ solves
     @staticmethod
-    def _opts(rtol, n_fine, n_coarse, max_cycles, precision, use_x0):
+    def _opts(rtol, n_fine, n_coarse, max_cycles, precision, use_x0, smoother="cg"):
         return _lib.SolveOpts(int(n_fine), int(n_coarse), float(rtol), int(max_cycles),
-                              PRECISIONS[precision], int(use_x0))
+                              PRECISIONS[precision], int(use_x0), SMOOTHERS[smoother])
 
-    def vcycle(self, x0, b, n_fine: int = 1, n_coarse: int = 40, out=None):
+    def vcycle(self, x0, b, n_fine: int = 1, n_coarse: int = 40, out=None, smoother: str = "cg"):
         import torch
         x = torch.empty_like(b) if out is None else out
-        o = self._opts(1e-8, n_fine, n_coarse, 1, "fp64", 1)
+        o = self._opts(1e-8, n_fine, n_coarse, 1, "fp64", 1, smoother)
         check(lib().h2mg_vcycle(self._h, _dev_f64(x0, self.n, "x0"), _dev_f64(b, self.n, "b"),
                                 _dev_f64(x, self.n, "x"), ctypes.byref(o), _stream()))
         return x
 
     def solve(self, b, rtol: float = 1e-8, n_fine: int = 1, n_coarse: int = 40,
-              max_cycles: int = 500, precision: str = "fp64", x0=None, raise_on_error: bool = True):
+              max_cycles: int = 500, precision: str = "fp64", x0=None, raise_on_error: bool = True,
+              smoother: str = "cg"):
         """Solve A_H2 x = b.  Returns (x, info dict)."""
         import torch
         x = torch.zeros_like(b) if x0 is None else x0.clone()
-        o = self._opts(rtol, n_fine, n_coarse, max_cycles, precision, x0 is not None)
+        o = self._opts(rtol, n_fine, n_coarse, max_cycles, precision, x0 is not None, smoother)
         info = _lib.SolveInfo()
         st = lib().h2mg_solve(self._h, _dev_f64(b, self.n, "b"), _dev_f64(x, self.n, "x"),
                               ctypes.byref(o), ctypes.byref(info), _stream())

@@ -33,15 +33,15 @@ def hier(name):
     return _hier[name]
 
 
-def _vcycle_pair(name, nc):
+def _vcycle_pair(name, nc, smoother="cg"):
     P, o, g = make(name)
     H = hier(name)
     n = len(P)
     b = synth.normal_vector(n, 1)
     x0 = 0.1 * synth.normal_vector(n, 5)
-    xg = _host(g.vcycle(_dev(x0), _dev(b), n_coarse=nc))
+    xg = _host(g.vcycle(_dev(x0), _dev(b), n_coarse=nc, smoother=smoother))
     perm = o.tree.perm
-    xt = vcycle(H, x0[perm], b[perm], 1, nc)
+    xt = vcycle(H, x0[perm], b[perm], 1, nc, smoother=smoother)
     xo = np.empty(n)
     xo[perm] = xt
     return P, o, H, b, x0, xg, xo
@@ -95,6 +95,31 @@ def test_fp64_solve_matches_oracle(name):
     # cycle counts scatter under rounding (the oracle alone gives 56-71 cycles
     # on the ragged shape for 1e-15 perturbations of b): same order only
     assert ref.cycles / 1.6 - 5 <= info["cycles"] <= 1.6 * ref.cycles + 5
+
+
+@pytest.mark.parametrize("name", ["exp2d_4k", "exp2d_ragged_r9", "exp3d_r8"])
+def test_block_smoother_vcycle_matches_oracle(name):
+    """Block-Jacobi preconditioned CG smoothing (leaf blocks K_ss + shift on
+    level 1, projected diagonal blocks above): iterate parity at n_c = 2."""
+    P, o, H, b, x0, xg, xo = _vcycle_pair(name, 2, smoother="bj")
+    rel = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+    print(f"[gpu] {name} block smoother n_c=2 rel diff {rel:.2e}")
+    assert rel <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["exp2d_4k", "exp3d_r8"])
+def test_block_smoother_solve_matches_oracle(name):
+    P, o, g = make(name)
+    H = hier(name)
+    b = synth.normal_vector(len(P), 1)
+    xg, info = g.solve(_dev(b), rtol=1e-8, smoother="bj")
+    xg = _host(xg)
+    ref = solve_user(o, H, b, rtol=1e-8, smoother="bj")
+    res = np.linalg.norm(b - o.matvec(xg)) / np.linalg.norm(b)
+    print(f"[gpu] {name} block smoother cycles gpu {info['cycles']} oracle {ref.cycles} residual {res:.2e}")
+    assert info["converged"] and res < 1e-8
+    assert ref.cycles / 1.6 - 5 <= info["cycles"] <= 1.6 * ref.cycles + 5
+    assert np.linalg.norm(xg - ref.x) <= np.linalg.cond(H.ops[0]) * 1e-8 * np.linalg.norm(ref.x)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])

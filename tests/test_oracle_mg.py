@@ -12,7 +12,7 @@ import scipy.sparse.linalg
 import torch
 
 import synth
-from oracle.cg import NotSPD, cg
+from oracle.cg import NotSPD, block_jacobi, cg, pcg
 from oracle.galerkin import Hierarchy, galerkin
 from oracle.h2 import H2
 from oracle.ir import ir_solve, round_bf16, round_fp32
@@ -107,6 +107,32 @@ def test_cg_zero_rhs_and_breakdown():
         cg(np.diag([1.0, -1.0, 2.0]).__matmul__, np.array([0.0, 1.0, 0.0]), None, 2)
 
 
+def test_pcg_identity_preconditioner_is_cg_and_matches_scipy():
+    A = _spd(60, 2, 1e4)
+    b = synth.normal_vector(60, 3)
+    e0 = synth.normal_vector(60, 4)
+    for n in (1, 4, 9):
+        np.testing.assert_allclose(pcg(A.__matmul__, lambda v: v.copy(), b, e0, n),
+                                   cg(A.__matmul__, b, e0, n), rtol=1e-12, atol=1e-14)
+    offs = [0, 20, 45, 60]
+    Minv = block_jacobi(A, offs)
+    Mdense = np.zeros_like(A)
+    for s, e in zip(offs[:-1], offs[1:]):
+        Mdense[s:e, s:e] = np.linalg.inv(A[s:e, s:e])
+    np.testing.assert_allclose(Minv(b), Mdense @ b, rtol=1e-10)
+    for n in (1, 3, 8):
+        ref, _ = scipy.sparse.linalg.cg(A, b, x0=e0, rtol=0.0, atol=0.0, maxiter=n,
+                                        M=scipy.sparse.linalg.LinearOperator(A.shape, matvec=Minv))
+        np.testing.assert_allclose(pcg(A.__matmul__, Minv, b, e0, n), ref, rtol=1e-8, atol=1e-12)
+
+
+def test_pcg_with_one_exact_block_solves_in_one_step():
+    A = _spd(30, 5, 1e3)
+    b = synth.normal_vector(30, 6)
+    e = pcg(A.__matmul__, block_jacobi(A, [0, 30]), b, None, 1)
+    np.testing.assert_allclose(e, np.linalg.solve(A, b), rtol=1e-9)
+
+
 # ---------------------------------------------------------------- V-cycle
 def test_single_level_is_a_direct_solve():
     P = synth.uniform_points(400, 2, 1)
@@ -146,6 +172,22 @@ def test_vcycle_error_monotone_and_converges_to_cholesky(small):
     assert res.converged and res.history[-1] < 1e-8
     kappa = np.linalg.cond(A)
     assert np.linalg.norm(res.x - xs) <= kappa * 1e-8 * np.linalg.norm(xs)
+
+
+def test_block_smoother_vcycle_contracts_and_converges(small):
+    h, H = small
+    A = H.ops[0]
+    b = synth.normal_vector(h.n, 8)
+    xs = np.linalg.solve(A, b)
+    x = np.zeros(h.n)
+    prev = np.inf
+    for _ in range(4):
+        x = vcycle(H, x, b, 1, 40, smoother="bj")
+        err = np.sqrt((x - xs) @ A @ (x - xs))
+        assert err <= prev * (1 + 1e-12)
+        prev = err
+    res = solve(H, b, rtol=1e-8, smoother="bj")
+    assert res.converged and res.history[-1] < 1e-8
 
 
 def test_vcycle_is_affine_in_initial_guess(small):
