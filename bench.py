@@ -63,7 +63,8 @@ def parse():
                     help="skip the paper's plain-CG smoother solves after the timed step")
     ap.add_argument("--matvec-reps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-leaves", type=int, default=3)
+    ap.add_argument("--no-c1", action="store_true", help="skip the small-configuration latency run")
+    ap.add_argument("--cpu-leaves", type=int, default=48)
     ap.add_argument("--json-out", default="")
     return ap.parse_args()
 
@@ -187,6 +188,97 @@ def spd_probe(args, torch, synth, H2Matrix):
         torch.cuda.empty_cache()
 
 
+def stored_near_matvec(args, torch, g, w, time_matvecs):
+    """The fine H2 matvec with the close leaf blocks stored as FP64 tiles:
+    time per product, algorithmic bytes (near tiles + couplings + the two
+    leaf-basis copies + transfers + vectors) and the fraction of HBM peak.
+    The tiles are released afterwards."""
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.store_near(True)
+        torch.cuda.synchronize()
+        t_store = time.perf_counter() - t0
+    except Exception as ex:       # the tiles do not fit next to the operator
+        return {"error": str(ex)}
+    ms = time_matvecs()
+    nst, gst = g.kernel_stats("near_gemv_fp64"), g.kernel_stats("gemv_fp64")
+    launches = max(nst["launches"], 1)
+    near_b = nst["work"] / launches
+    coup_b = gst["work"] / max(gst["launches"], 1)
+    r = w.rank
+    L = (g.level_size(2) // r).bit_length() - 1 if g.levels > 1 else 0
+    d_top = L - g.levels + 2
+    transfer_b = 2 * ((1 << (L + 1)) - (1 << (d_top + 1))) * r * r * 8 if g.levels > 1 else 0
+    basis_b = 2 * w.n * r * 8
+    vec_b = 3 * w.n * 8
+    total = near_b + coup_b + basis_b + transfer_b + vec_b
+    near_ms = nst["ms"] / launches
+    out = {
+        "layout": "near field stored: 64x64 FP64 tiles over leaf chunks, upper triangle; "
+                  "couplings stored upper triangle",
+        "store_s": round(t_store, 3),
+        "matvec_ms": round(ms, 3),
+        "algorithmic_gb": round(total / 1e9, 2),
+        "near_tiles_gb": round(near_b / 1e9, 2), "couplings_gb": round(coup_b / 1e9, 2),
+        "bases_transfers_vectors_gb": round((basis_b + transfer_b + vec_b) / 1e9, 2),
+        "matvec_gbs": round(total / (ms * 1e-3) / 1e9, 1),
+        "matvec_frac_of_hbm_peak": round(total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3),
+        "near_gemv_ms": round(near_ms, 3),
+        "near_gemv_gbs": round(near_b / (near_ms * 1e-3) / 1e9, 1) if near_ms else None,
+        "device_memory_gb": round(g.memory_bytes() / 1e9, 1),
+    }
+    g.store_near(False)
+    torch.cuda.synchronize()
+    log(f"stored-near matvec: {out['matvec_ms']} ms, {out['matvec_gbs']} GB/s "
+        f"({out['matvec_frac_of_hbm_peak']:.0%} of peak), near GEMV {out['near_gemv_gbs']} GB/s")
+    return out
+
+
+def c1_latency(args, torch, synth, H2Matrix):
+    """The small configuration (exp kernel, N = 4096 in 2D, leaf 64, rank 16):
+    cache-resident and launch-bound, so it measures latency, with the
+    oracle's full solve of the same problem timed beside it."""
+    w = synth.workload("exp2d_4k")
+    P, b = w.make_points(), w.make_rhs()
+    pts = torch.from_numpy(P).cuda()
+    bd = torch.from_numpy(b).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = H2Matrix(pts, w.kernel, w.length_scale, w.shift, w.leaf, w.eta, w.cheb_m)
+    g.setup(("fp64", "fp32"))
+    torch.cuda.synchronize()
+    out = {"workload": f"{w.name}: N={w.n}, {w.kernel} l={w.length_scale} + {w.shift}*I, "
+                       f"leaf {w.leaf}, eta {w.eta}, rank {w.rank}, rtol 1e-8",
+           "build_and_setup_s": round(time.perf_counter() - t0, 4)}
+    for smoother in ("cg", "bj"):
+        for prec in ("fp64", "fp32"):
+            g.solve(bd, rtol=1e-8, precision=prec, smoother=smoother, raise_on_error=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = g.solve(bd, rtol=1e-8, precision=prec, smoother=smoother, raise_on_error=False)
+            torch.cuda.synchronize()
+            out[f"{smoother}_{prec}"] = {"time_to_1e-8_s": round(time.perf_counter() - t0, 4),
+                                         "cycles": info["cycles"], "converged": info["converged"]}
+    g.close()
+    if not args.no_cpu:
+        from oracle.galerkin import Hierarchy
+        from oracle.h2 import H2 as OracleH2
+        from oracle.vcycle import solve_user
+        t0 = time.perf_counter()
+        o = OracleH2(P, w.kernel, w.shift, w.leaf, w.eta, w.cheb_m, w.length_scale)
+        H = Hierarchy(o)
+        t1 = time.perf_counter()
+        res = solve_user(o, H, b, rtol=1e-8)
+        t2 = time.perf_counter()
+        out["oracle_cg_fp64"] = {"time_to_1e-8_s": round(t2 - t1, 3), "setup_s": round(t1 - t0, 3),
+                                 "cycles": res.cycles, "converged": res.converged,
+                                 "threads": int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count())}
+    log(f"C1 {w.name}: " + ", ".join(f"{k} {v['time_to_1e-8_s']} s/{v['cycles']} cycles"
+                                      for k, v in out.items() if isinstance(v, dict)))
+    return out
+
+
 def part_a(args, torch, synth, H2Matrix):
     """The exact headline workload: build, setup, matvec and a few cycles."""
     w = synth.workload(args.headline)
@@ -199,23 +291,32 @@ def part_a(args, torch, synth, H2Matrix):
     g = H2Matrix(pts, w.kernel, w.length_scale, w.shift, w.leaf, w.eta, w.cheb_m)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    y = torch.empty_like(x)
+
+    def time_matvecs():
+        g.matvec(x, out=y)
+        torch.cuda.synchronize()
+        g.set_timing(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.matvec_reps):
+            g.matvec(x, out=y)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.matvec_reps
+
+    # matvec with the near field evaluated from the points (the solver's form)
+    mv_ms = time_matvecs()
+    gst, nst = g.kernel_stats("gemv_fp64"), g.kernel_stats("near_fp64")
+    gemv_bytes = gst["work"] / max(gst["launches"], 1)
+    # matvec with the near field stored (FP64 tiles of the close leaf blocks)
+    stored = stored_near_matvec(args, torch, g, w, time_matvecs)
+    g.set_timing(False)
+    torch.cuda.synchronize()
+    t1b = time.perf_counter()
     g.setup(("fp64", args.mixed))
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    # matvec: the stored-operator part streams the couplings of every depth
-    y = torch.empty_like(x)
-    g.matvec(x, out=y)
-    torch.cuda.synchronize()
-    g.set_timing(True)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(args.matvec_reps):
-        g.matvec(x, out=y)
-    e1.record()
-    torch.cuda.synchronize()
-    mv_ms = e0.elapsed_time(e1) / args.matvec_reps
-    gst, nst = g.kernel_stats("gemv_fp64"), g.kernel_stats("near_fp64")
-    gemv_bytes = gst["work"] / max(gst["launches"], 1)
     g.set_timing(True)
     _, i64 = g.solve(b, rtol=1e-8, max_cycles=args.headline_cycles, precision="fp64",
                      raise_on_error=False)
@@ -230,8 +331,9 @@ def part_a(args, torch, synth, H2Matrix):
     out = {
         "workload": f"{w.name}: N={w.n}, {w.kernel} l={w.length_scale} + {w.shift}*I, leaf {w.leaf}, "
                     f"eta {w.eta}, rank {w.rank}",
-        "build_s": round(t1 - t0, 3), "setup_s": round(t2 - t1, 3), "levels": g.levels,
+        "build_s": round(t1 - t0, 3), "setup_s": round(t2 - t1b, 3), "levels": g.levels,
         "device_memory_gb": round(g.memory_bytes() / 1e9, 1),
+        "matvec_stored_near": stored,
         "matvec_ms": round(mv_ms, 3),
         "matvec_gemv_ms": round(gst["ms"] / max(gst["launches"], 1), 3),
         "matvec_gemv_gbs": round(gemv_bytes / (gst["ms"] / max(gst["launches"], 1) * 1e-3) / 1e9, 1),
@@ -273,6 +375,7 @@ def main():
     if args.spd_probe:
         spd_probe(args, torch, synth, H2Matrix)
         return
+    c1 = None if args.no_c1 else c1_latency(args, torch, synth, H2Matrix)
     headline = part_a(args, torch, synth, H2Matrix) if args.headline else None
     if headline:
         log(f"part A: build {headline['build_s']} s, matvec {headline['matvec_ms']} ms, "
@@ -401,6 +504,7 @@ def main():
         "roofline": rec["rlm"] if mixed_ok and rec["rlm"] else rec["rl64"],
         "roofline_fp64_gemv": rec["rl64"],
         "paper_cg_smoother": cg_runs,
+        "c1_small_config": c1,
         "headline_shift_1e-3": headline,
     }
     if not args.no_cpu:

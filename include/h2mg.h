@@ -166,8 +166,9 @@ typedef struct h2mg_h2_s* h2mg_h2_t;
  * kernel (Section 3.1): tree and partition on the host, then on the device
  * the orthonormal nested bases (leaf bases Q, transfers E), and the
  * orthogonalised far couplings S of every depth.  Near leaf blocks are
- * evaluated on the fly in every product.  Errors as h2mg_plan_create, plus
- * INVALID_ARG for a null pointer or a bad kernel, OOM, HIP.  Blocks until
+ * evaluated on the fly in every product unless h2mg_store_near stores them.
+ * Errors as h2mg_plan_create, plus INVALID_ARG for a null pointer or a bad
+ * kernel, OOM, HIP.  Blocks until
  * the build is complete. */
 h2mg_status h2mg_build(const double* points_dev, int64_t n, int32_t dim,
                        const h2mg_kernel* kernel, const h2mg_build_opts* opts,
@@ -178,6 +179,19 @@ h2mg_status h2mg_build(const double* points_dev, int64_t n, int32_t dim,
  * x_dev, y_dev: device, length n, user order; they must not overlap. */
 h2mg_status h2mg_matvec(h2mg_h2_t h, const double* x_dev, double* y_dev,
                         hipStream_t stream);
+
+/* Store the near field (Section 3.1: the dense close leaf blocks D of the
+ * matvec y = D x + U_1 y_1).  enable != 0 evaluates every close leaf pair
+ * once, as 64 x 64 FP64 tiles between chunks of at most 64 points of a leaf
+ * (upper triangle of the symmetric operator; at n = 2^20 with leaf 128 this
+ * is 126 GB), and every later FP64 fine-level product (h2mg_matvec,
+ * level 1 of h2mg_level_apply, the FP64 residuals and smoothing of
+ * h2mg_solve) streams those tiles instead of evaluating the kernel.  FP32 and
+ * BF16 products keep evaluating the near field.  enable == 0 releases the
+ * tiles.  Results agree with the evaluated near field up to rounding order.
+ * Errors: OOM (nothing is kept; the evaluated near field stays in use), HIP.
+ * Blocks until the tiles are complete. */
+h2mg_status h2mg_store_near(h2mg_h2_t h, int32_t enable, hipStream_t stream);
 
 /* Build the H2-MG hierarchy (Section 3.3): restricted operators
  * A_k = U_{k-1}^T A_{k-1} V_{k-1}^T for every level, i.e. the projected close
@@ -229,7 +243,9 @@ h2mg_status h2mg_solve_history(h2mg_h2_t h, double* history_host, int32_t capaci
  * returns, for kind 0/1/2 (block GEMV with FP64/FP32/BF16 blocks), the
  * number of launches, their summed duration in ms and the algorithmic bytes
  * they streamed (stored block words x element size); for kind 3/4 (near
- * field in FP64/FP32) the summed kernel evaluations instead of bytes. */
+ * field evaluated in FP64/FP32) the summed kernel evaluations instead of
+ * bytes; for kind 5 (block GEMV over the stored FP64 near-field tiles) the
+ * bytes of the tiles it streamed. */
 h2mg_status h2mg_set_timing(h2mg_h2_t h, int32_t enabled);
 h2mg_status h2mg_kernel_stats(h2mg_h2_t h, int32_t kind, int64_t* launches, double* total_ms,
                               double* total_work);

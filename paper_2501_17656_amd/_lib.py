@@ -68,6 +68,7 @@ SIGNATURES = {
     "h2mg_solve_history": (c_int32, [c_void_p, P_double, c_int32]),
     "h2mg_memory_bytes": (c_int32, [c_void_p, P_int64]),
     "h2mg_set_timing": (c_int32, [c_void_p, c_int32]),
+    "h2mg_store_near": (c_int32, [c_void_p, c_int32, c_void_p]),
     "h2mg_kernel_stats": (c_int32, [c_void_p, c_int32, P_int64, P_double, P_double]),
     "h2mg_destroy": (c_int32, [c_void_p]),
     "h2mg_last_error": (ctypes.c_char_p, []),

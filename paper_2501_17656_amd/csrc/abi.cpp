@@ -284,6 +284,14 @@ h2mg_status h2mg_memory_bytes(h2mg_h2_t hh, int64_t* bytes) {
   });
 }
 
+h2mg_status h2mg_store_near(h2mg_h2_t hh, int32_t enable, hipStream_t stream) {
+  return guarded([&] {
+    if (!hh) return fail(H2MG_ERR_INVALID_ARG, "null handle");
+    hh->h->stream = stream;
+    return store_near(*hh->h, enable);
+  });
+}
+
 h2mg_status h2mg_set_timing(h2mg_h2_t hh, int32_t enabled) {
   return guarded([&] {
     if (!hh) return fail(H2MG_ERR_INVALID_ARG, "null handle");

@@ -7,6 +7,10 @@ namespace h2mg {
 h2mg_status build_h2(const double* points_dev, int64_t n, int dim, const h2mg_kernel* kernel,
                      const h2mg_build_opts* opts, hipStream_t stream, H2** out);
 h2mg_status setup_mg(H2& h, int precision_mask);
+// enable != 0: evaluate the close leaf blocks once and store them (FP64
+// tiles) for every later FP64 fine product; enable == 0: release them and
+// go back to evaluating the near field in every product.
+h2mg_status store_near(H2& h, int enable);
 
 // Products in precision p (vectors double for P64, float otherwise).
 // Fine level, tree order: out = alpha * A_H2 x + beta * add (add may be null).

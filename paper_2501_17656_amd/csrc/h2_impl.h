@@ -57,7 +57,11 @@ struct Launch {
 };
 
 // Optional per-kernel timing with HIP events on the handle's stream.
-enum KStatKind { KS_GEMV64 = 0, KS_GEMV32 = 1, KS_GEMV16 = 2, KS_NEAR64 = 3, KS_NEAR32 = 4, KS_COUNT = 5 };
+enum KStatKind {
+  KS_GEMV64 = 0, KS_GEMV32 = 1, KS_GEMV16 = 2, KS_NEAR64 = 3, KS_NEAR32 = 4,
+  KS_NEARST64 = 5,                     // block GEMV over the stored near-field tiles
+  KS_COUNT = 6
+};
 struct KStat {
   int64_t launches = 0;
   double ms = 0.0;
@@ -76,6 +80,39 @@ struct NearField {
   int* col_ptr = nullptr;              // device: nleaf + 1
   int* col_pair = nullptr;             // device: off-diagonal pairs by column leaf
   int ld = 0;                          // padded leaf length of partial buffers
+};
+
+// Stored near field (optional, FP64).  Every leaf is cut into chunks of at
+// most 64 consecutive points (chunk k of leaf s covers local positions
+// 64k .. 64k+63), and the close leaf pairs (s <= t) into 64 x 64 tiles
+// between chunks: all chunk pairs of an off-diagonal leaf pair, the upper
+// triangle of chunk pairs of a diagonal one (diagonal tiles stored whole,
+// with the shift on their diagonal).  Padding rows and columns are zero.
+// Vectors on chunks are padded: position i of leaf s is element
+// chunk_base[s] * 64 + i; when every leaf holds a multiple of 64 points this
+// is the tree order itself and no padding copy is made.
+struct StoredNear {
+  bool ready = false;
+  bool identity = false;               // padded chunk order == tree order
+  int nchunk = 0;
+  int ntasks = 0;
+  int64_t nblocks = 0;
+  int nslot = 0;
+  int* chunk_base = nullptr;           // device: nleaf + 1
+  int* chunk_start = nullptr;          // device: first tree position of each chunk
+  int* chunk_n = nullptr;              // device: points in each chunk
+  int* blk_row = nullptr;              // device: row chunk of each tile
+  int* blk_col = nullptr;              // device: column chunk of each tile
+  int* blk_slot = nullptr;             // device: column-contribution slot (-1: diagonal)
+  int* task = nullptr;                 // device: (row chunk, b0, b1), at most 16 tiles
+  int* row_task_ptr = nullptr;         // device: nchunk + 1
+  int* col_ptr = nullptr;              // device: nchunk + 1
+  double* tiles = nullptr;             // nblocks tiles of 64 x 64 (T = 8 layout)
+  double* partial = nullptr;           // ntasks * 64
+  double* colpart = nullptr;           // nslot * 64
+  double* xc = nullptr;                // nchunk * 64 (padded input; null when identity)
+  double* yc = nullptr;                // nchunk * 64 (near-field product)
+  std::vector<void*> owned;            // device allocations of this structure
 };
 
 struct PrecData {                      // operator storage in one precision
@@ -116,6 +153,7 @@ struct H2 {
   std::vector<int> s_first, s_count, p_first, p_count;
   std::vector<View> sview, pview;
   NearField near;
+  StoredNear snear;
   PrecData prec[3];
 
   // launches: fine apply (S of all depths), coarse apply at depth d
@@ -178,6 +216,7 @@ void launch_assemble_dense(H2& h, double* A, int64_t lda);  // depth d_top block
 void launch_assemble_kernel_dense(H2& h, double* A, int64_t lda);  // no far blocks
 void launch_potrf(H2& h, double* A, int64_t N);   // blocked Cholesky, sets flags[0]
 void launch_cast_precision(H2& h, int p);         // FP64 -> FP32 / BF16 copies
+void launch_near_tiles(H2& h);                    // stored near-field tiles (FP64)
 // Inverses of the block-Jacobi blocks: leaf blocks K_ss + shift (FP64) and the
 // projected diagonal blocks of depths d_top+1..L (FP64); sets flags[0] on a
 // non-positive pivot.
@@ -199,11 +238,15 @@ void launch_transfer_down(H2& h, int p, int d, const void* ypar, void* ychild,
                           const void* addend);
 void launch_leaf_up(H2& h, int p, const void* xtree, void* xhat);
 void launch_near(H2& h, int p, const void* xtree);
+// Stored near field (FP64): snear.yc = D x over the chunk-padded layout.
+void launch_near_stored(H2& h, const double* xtree);
 // out = alpha * Q yhat + beta * add (tree order).
 void launch_leaf_down(H2& h, int p, const void* yhat, void* out, double alpha, const void* add,
                       double beta);
 // out[idx] = alpha * (Q yhat + near) + beta * add[idx], idx = tree position or
-// perm[tree position] when to_user.
+// perm[tree position] when to_user.  The near part comes from the stored
+// near field (snear.yc) for FP64 when it is ready, else from the on-the-fly
+// partials.
 void launch_fine_reduce(H2& h, int p, const void* yhat, void* out, bool to_user,
                         double alpha, const void* add, double beta);
 

@@ -100,12 +100,12 @@ __device__ inline int reduced_index(int a) {
 // previous is consumed; FP32/BF16 tiles use non-temporal loads (measured
 // faster there, slower for FP64 tiles).
 template <int T, bool FULL, typename Tb, typename Tv>
-__global__ __launch_bounds__(256) void k_bsr_gemv(const int* __restrict__ tasks, int ntasks,
-                                                  const Tb* __restrict__ blk,
-                                                  const int* __restrict__ blk_col,
-                                                  const int* __restrict__ blk_slot,
-                                                  const Tv* __restrict__ x, Tv* __restrict__ partial,
-                                                  Tv* __restrict__ colpart, int r) {
+__device__ __forceinline__ void bsr_gemv_wave(const int* __restrict__ tasks, int ntasks,
+                                              const Tb* __restrict__ blk,
+                                              const int* __restrict__ blk_col,
+                                              const int* __restrict__ blk_slot,
+                                              const Tv* __restrict__ x, Tv* __restrict__ partial,
+                                              Tv* __restrict__ colpart, int r) {
   constexpr bool NTL = sizeof(Tb) < 8;
   const int wave = __builtin_amdgcn_readfirstlane(int((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   if (wave >= ntasks) return;
@@ -167,6 +167,30 @@ __global__ __launch_bounds__(256) void k_bsr_gemv(const int* __restrict__ tasks,
       if (FULL || i < rr) partial[int64_t(wave) * rr + i] = acc[u];
     }
   }
+}
+
+// Couplings and projected close blocks (r x r tiles).
+template <int T, bool FULL, typename Tb, typename Tv>
+__global__ __launch_bounds__(256) void k_bsr_gemv(const int* __restrict__ tasks, int ntasks,
+                                                  const Tb* __restrict__ blk,
+                                                  const int* __restrict__ blk_col,
+                                                  const int* __restrict__ blk_slot,
+                                                  const Tv* __restrict__ x, Tv* __restrict__ partial,
+                                                  Tv* __restrict__ colpart, int r) {
+  bsr_gemv_wave<T, FULL, Tb, Tv>(tasks, ntasks, blk, blk_col, blk_slot, x, partial, colpart, r);
+}
+
+// Stored near field: 64 x 64 FP64 tiles between leaf chunks (same body; a
+// kernel of its own so profiles separate it from the coupling products).
+__global__ __launch_bounds__(256) void k_near_gemv(const int* __restrict__ tasks, int ntasks,
+                                                   const double* __restrict__ tiles,
+                                                   const int* __restrict__ blk_col,
+                                                   const int* __restrict__ blk_slot,
+                                                   const double* __restrict__ x,
+                                                   double* __restrict__ partial,
+                                                   double* __restrict__ colpart) {
+  bsr_gemv_wave<8, true, double, double>(tasks, ntasks, tiles, blk_col, blk_slot, x, partial,
+                                         colpart, 64);
 }
 
 // Sources of one depth for the reduce: task partials of the row (contiguous
@@ -449,7 +473,8 @@ __global__ __launch_bounds__(256) void k_fine_reduce(
     const int* __restrict__ leaf_off, const Tq* __restrict__ Qc, const Tv* __restrict__ yhat, int r,
     const int* __restrict__ row_task_ptr, const int* __restrict__ col_ptr,
     const int* __restrict__ col_pair, const Tv* __restrict__ partial,
-    const Tv* __restrict__ colpart, int ld, const int64_t* __restrict__ perm, Tv* __restrict__ out,
+    const Tv* __restrict__ colpart, int ld, const Tv* __restrict__ near_y,
+    const int* __restrict__ chunk_base, const int64_t* __restrict__ perm, Tv* __restrict__ out,
     double alpha, const Tv* __restrict__ add, double beta) {
   __shared__ Tv yh[64];
   const int leaf = blockIdx.x;
@@ -462,8 +487,12 @@ __global__ __launch_bounds__(256) void k_fine_reduce(
   for (int i = threadIdx.x; i < n; i += 256) {
     Tv v = zero<Tv>();
     for (int j = 0; j < r; ++j) v += ld_as<Tv, Tq>(Q[int64_t(j) * n + i]) * yh[j];
-    for (int t = t0; t < t1; ++t) v += partial[int64_t(t) * ld + i];
-    for (int c = c0; c < c1; ++c) v += colpart[int64_t(col_pair[c]) * ld + i];
+    if (near_y) {
+      v += near_y[int64_t(chunk_base[leaf]) * 64 + i];
+    } else {
+      for (int t = t0; t < t1; ++t) v += partial[int64_t(t) * ld + i];
+      for (int c = c0; c < c1; ++c) v += colpart[int64_t(col_pair[c]) * ld + i];
+    }
     const int64_t idx = perm ? perm[s0 + i] : int64_t(s0 + i);
     Tv o = Tv(alpha) * v;
     if (add) o += Tv(beta) * add[idx];
@@ -492,6 +521,19 @@ __global__ __launch_bounds__(256) void k_leaf_down(const int* __restrict__ leaf_
     if (add) o += Tv(beta) * add[s0 + i];
     out[s0 + i] = o;
   }
+}
+
+// xc[chunk_base[leaf] * 64 + i] = x[leaf_off[leaf] + i]: the tree-order
+// vector in the chunk-padded layout of the stored near field (padding
+// entries are never written and stay zero).
+__global__ __launch_bounds__(256) void k_near_pad(const int* __restrict__ leaf_off,
+                                                  const int* __restrict__ chunk_base,
+                                                  const double* __restrict__ x,
+                                                  double* __restrict__ xc) {
+  const int leaf = blockIdx.x;
+  const int s0 = leaf_off[leaf], n = leaf_off[leaf + 1] - s0;
+  double* dst = xc + int64_t(chunk_base[leaf]) * 64;
+  for (int i = threadIdx.x; i < n; i += 256) dst[i] = x[s0 + i];
 }
 
 // ------------------------------------------------------------ dispatch helpers
@@ -657,6 +699,38 @@ void launch_near(H2& h, int p, const void* xtree) {
   h.time_end(p == P64 ? KS_NEAR64 : KS_NEAR32, ev, double(h.near_evals));
 }
 
+void launch_near_stored(H2& h, const double* xtree) {
+  StoredNear& sn = h.snear;
+  if (sn.nblocks == 0) return;
+  const double* xc = xtree;
+  if (!sn.identity) {
+    hipLaunchKernelGGL(k_near_pad, dim3(h.nleaf), dim3(256), 0, h.stream, h.leaf_off,
+                       sn.chunk_base, xtree, sn.xc);
+    check_launch("near_pad");
+    xc = sn.xc;
+  }
+  int ev;
+  h.time_begin(ev);
+  hipLaunchKernelGGL(k_near_gemv, dim3(grid_waves(sn.ntasks)), dim3(256), 0, h.stream, sn.task,
+                     sn.ntasks, sn.tiles, sn.blk_col, sn.blk_slot, xc, sn.partial, sn.colpart);
+  check_launch("near_gemv");
+  h.time_end(KS_NEARST64, ev, double(sn.nblocks) * 64.0 * 64.0 * sizeof(double));
+  RedArgs A{};
+  A.ndep = 1;
+  A.nrows = sn.nchunk;
+  RedDepth& D = A.dep[0];
+  D.rtp[0] = sn.row_task_ptr;
+  D.cptr[0] = sn.col_ptr;
+  D.base[0] = 0;
+  D.slot[0] = 0;
+  D.nsrc = 1;
+  D.row0 = 0;
+  D.out_off = 0;
+  hipLaunchKernelGGL(k_reduce<double>, dim3(grid_waves(sn.nchunk)), dim3(256), 0, h.stream, A,
+                     sn.partial, sn.colpart, sn.yc, static_cast<double*>(nullptr), 64);
+  check_launch("near_reduce");
+}
+
 void launch_fine_reduce(H2& h, int p, const void* yhat, void* out, bool to_user, double alpha,
                         const void* add, double beta) {
   const dim3 g(h.nleaf), b(256);
@@ -665,21 +739,24 @@ void launch_fine_reduce(H2& h, int p, const void* yhat, void* out, bool to_user,
     hipLaunchKernelGGL((k_fine_reduce<double, double>), g, b, 0, h.stream, h.leaf_off,
                        static_cast<const double*>(h.prec[P64].Qc), static_cast<const double*>(yhat),
                        h.r, h.near.row_task_ptr, h.near.col_ptr, h.near.col_pair, h.near_partial,
-                       h.near_colpart, h.near.ld, perm, static_cast<double*>(out), alpha,
+                       h.near_colpart, h.near.ld, h.snear.ready ? h.snear.yc : nullptr,
+                       h.snear.chunk_base, perm, static_cast<double*>(out), alpha,
                        static_cast<const double*>(add), beta);
   else if (p == P32)
     hipLaunchKernelGGL((k_fine_reduce<float, float>), g, b, 0, h.stream, h.leaf_off,
                        static_cast<const float*>(h.prec[P32].Qc), static_cast<const float*>(yhat),
                        h.r, h.near.row_task_ptr, h.near.col_ptr, h.near.col_pair,
                        reinterpret_cast<const float*>(h.near_partial),
-                       reinterpret_cast<const float*>(h.near_colpart), h.near.ld, perm,
+                       reinterpret_cast<const float*>(h.near_colpart), h.near.ld,
+                       static_cast<const float*>(nullptr), h.snear.chunk_base, perm,
                        static_cast<float*>(out), alpha, static_cast<const float*>(add), beta);
   else
     hipLaunchKernelGGL((k_fine_reduce<bf16, float>), g, b, 0, h.stream, h.leaf_off,
                        static_cast<const bf16*>(h.prec[P16].Qc), static_cast<const float*>(yhat),
                        h.r, h.near.row_task_ptr, h.near.col_ptr, h.near.col_pair,
                        reinterpret_cast<const float*>(h.near_partial),
-                       reinterpret_cast<const float*>(h.near_colpart), h.near.ld, perm,
+                       reinterpret_cast<const float*>(h.near_colpart), h.near.ld,
+                       static_cast<const float*>(nullptr), h.snear.chunk_base, perm,
                        static_cast<float*>(out), alpha, static_cast<const float*>(add), beta);
   check_launch("fine_reduce");
 }

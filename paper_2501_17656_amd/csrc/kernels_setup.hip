@@ -637,6 +637,58 @@ __global__ __launch_bounds__(NT) void k_cast_flat(const double* __restrict__ src
   if (i < n) dst[i] = Conv<Td>::from_f64(src[i]);
 }
 
+// ------------------------------------------------------------ stored near field
+// One wave per 64 x 64 tile between a row chunk and a column chunk of close
+// leaves: lane (a, b) evaluates rows 8a .. 8a+7 and columns 8b .. 8b+7 of
+// the tile (kernel plus the shift where a point meets itself) and writes
+// them as 16-byte chunks of the T = 8 tile layout.  Entries outside the
+// chunks' point counts are zero.
+__global__ __launch_bounds__(NT) void k_near_tiles(int64_t nblocks, const int* __restrict__ blk_row,
+                                                   const int* __restrict__ blk_col,
+                                                   const int* __restrict__ chunk_start,
+                                                   const int* __restrict__ chunk_n,
+                                                   const double* __restrict__ pts, int dim,
+                                                   KernelParams kp, double* __restrict__ tiles) {
+  const int64_t blk = (int64_t(blockIdx.x) * NT + threadIdx.x) >> 6;
+  if (blk >= nblocks) return;
+  const int lane = threadIdx.x & 63;
+  const int a = lane >> 3, b = lane & 7;
+  const int cs = blk_row[blk], ct = blk_col[blk];
+  const int s0 = chunk_start[cs], ns = chunk_n[cs];
+  const int t0 = chunk_start[ct], nt = chunk_n[ct];
+  double pi[8][3], pj[8][3];
+  for (int u = 0; u < 8; ++u) {
+    const int i = min(8 * a + u, ns - 1), j = min(8 * b + u, nt - 1);
+    for (int q = 0; q < 3; ++q) {
+      pi[u][q] = q < dim ? pts[int64_t(s0 + i) * dim + q] : 0.0;
+      pj[u][q] = q < dim ? pts[int64_t(t0 + j) * dim + q] : 0.0;
+    }
+  }
+  double* tile = tiles + blk * tile_elems(8);
+#pragma unroll
+  for (int c = 0; c < 32; ++c) {
+    const int u = c >> 2, v0 = 2 * (c & 3);
+    const int i = 8 * a + u;
+    double val[2];
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+      const int j = 8 * b + v0 + w;
+      double r2 = 0.0;
+      for (int q = 0; q < 3; ++q) {
+        const double dx = pi[u][q] - pj[v0 + w][q];
+        r2 += dx * dx;
+      }
+      double k = kernel_r2(kp, r2);
+      if (cs == ct && i == j) k += kp.shift;
+      val[w] = (i < ns && j < nt) ? k : 0.0;
+    }
+    double2 out;
+    out.x = val[0];
+    out.y = val[1];
+    *reinterpret_cast<double2*>(tile + (c * 64 + lane) * 2) = out;
+  }
+}
+
 void check_launch(const char* what) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
@@ -677,6 +729,16 @@ void launch_couplings(H2& h, int d) {
                      h.blk_row, h.blk_col, h.dim, h.cbox, h.hbox, h.nodes1d, h.m, h.r, h.T, h.kp,
                      h.R, static_cast<double*>(h.prec[P64].blk));
   check_launch("coupling");
+}
+
+void launch_near_tiles(H2& h) {
+  const StoredNear& sn = h.snear;
+  if (sn.nblocks == 0) return;
+  const int64_t groups = (sn.nblocks + 3) / 4;
+  hipLaunchKernelGGL(k_near_tiles, dim3(unsigned(groups)), dim3(NT), 0, h.stream, sn.nblocks,
+                     sn.blk_row, sn.blk_col, sn.chunk_start, sn.chunk_n, h.pts, h.dim, h.kp,
+                     sn.tiles);
+  check_launch("near_tiles");
 }
 
 void launch_pi_leaf(H2& h) {

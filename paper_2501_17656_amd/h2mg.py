@@ -98,6 +98,11 @@ class H2Matrix:
         check(lib().h2mg_matvec(self._h, _dev_f64(x, self.n, "x"), _dev_f64(y, self.n, "y"), _stream()))
         return y
 
+    def store_near(self, enable: bool = True) -> None:
+        """Store the close leaf blocks as FP64 tiles (enable) or release them;
+        FP64 fine-level products then stream the tiles."""
+        check(lib().h2mg_store_near(self._h, int(bool(enable)), _stream()))
+
     def setup(self, precisions=("fp64",)) -> None:
         mask = 0
         for p in precisions:
@@ -169,7 +174,8 @@ class H2Matrix:
             check(st)
         return x, out
 
-    KERNEL_KINDS = {"gemv_fp64": 0, "gemv_fp32": 1, "gemv_bf16": 2, "near_fp64": 3, "near_fp32": 4}
+    KERNEL_KINDS = {"gemv_fp64": 0, "gemv_fp32": 1, "gemv_bf16": 2, "near_fp64": 3, "near_fp32": 4,
+                    "near_gemv_fp64": 5}
 
     def set_timing(self, enabled: bool) -> None:
         check(lib().h2mg_set_timing(self._h, int(bool(enabled))))
