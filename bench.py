@@ -105,7 +105,8 @@ def block_gemv_roofline(g, kind, bytes_per_sec_peak=HBM_PEAK_GBS):
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": bytes_per_sec_peak,
             "unit": "GB/s", "frac": round(achieved / bytes_per_sec_peak, 4),
             "traffic": profiled_traffic(kind),
-            "kernel": f"k_bsr_gemv ({kind})", "launches": st["launches"],
+            "kernel": "k_near_gemv" if kind.startswith("near") else f"k_bsr_gemv ({kind})",
+            "launches": st["launches"],
             "avg_launch_ms": round(avg_ms, 4), "avg_bytes_per_launch": avg_bytes}
 
 
@@ -226,6 +227,7 @@ def stored_near_matvec(args, torch, g, w, time_matvecs):
         "matvec_frac_of_hbm_peak": round(total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3),
         "near_gemv_ms": round(near_ms, 3),
         "near_gemv_gbs": round(near_b / (near_ms * 1e-3) / 1e9, 1) if near_ms else None,
+        "near_gemv_roofline": block_gemv_roofline(g, "near_gemv_fp64"),
         "device_memory_gb": round(g.memory_bytes() / 1e9, 1),
     }
     g.store_near(False)
