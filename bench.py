@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--spd-probe", default="",
                     help="n:cycles:shift,... run FP64 V-cycles of the headline shape and report "
                          "the Rayleigh quotient of the final iterate")
+    ap.add_argument("--growth", default="",
+                    help="comma-separated N: iterations to 1e-8 of H2-MG and of plain CG against N")
     ap.add_argument("--spd-probe-oracle", action="store_true",
                     help="also evaluate the Rayleigh quotient with the CPU oracle's matvec")
     ap.add_argument("--n", type=int, default=0, help="override the number of points")
@@ -253,15 +255,22 @@ def c1_latency(args, torch, synth, H2Matrix):
     out = {"workload": f"{w.name}: N={w.n}, {w.kernel} l={w.length_scale} + {w.shift}*I, "
                        f"leaf {w.leaf}, eta {w.eta}, rank {w.rank}, rtol 1e-8",
            "build_and_setup_s": round(time.perf_counter() - t0, 4)}
-    for smoother in ("cg", "bj"):
-        for prec in ("fp64", "fp32"):
-            g.solve(bd, rtol=1e-8, precision=prec, smoother=smoother, raise_on_error=False)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            _, info = g.solve(bd, rtol=1e-8, precision=prec, smoother=smoother, raise_on_error=False)
-            torch.cuda.synchronize()
-            out[f"{smoother}_{prec}"] = {"time_to_1e-8_s": round(time.perf_counter() - t0, 4),
-                                         "cycles": info["cycles"], "converged": info["converged"]}
+    runs = [(m, sm, pr) for sm in ("cg", "bj") for pr in ("fp64", "fp32") for m in ("v",)]
+    runs += [(m, sm, "fp64") for sm in ("cg", "bj") for m in ("w", "f", "cg")]
+    for method, smoother, prec in runs:
+        kw = dict(rtol=1e-8, precision=prec, smoother=smoother, method=method, raise_on_error=False,
+                  max_cycles=20000 if method == "cg" else 500)
+        g.solve(bd, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = g.solve(bd, **kw)
+        torch.cuda.synchronize()
+        key = f"{smoother}_{prec}" if method == "v" else f"{method}-cycle_{smoother}_{prec}"
+        if method == "cg":
+            key = f"plain_{'pcg' if smoother == 'bj' else 'cg'}_fp64"
+        out[key] = {"time_to_1e-8_s": round(time.perf_counter() - t0, 4),
+                    ("iterations" if method == "cg" else "cycles"): info["cycles"],
+                    "converged": info["converged"]}
     g.close()
     if not args.no_cpu:
         from oracle.galerkin import Hierarchy
@@ -276,9 +285,44 @@ def c1_latency(args, torch, synth, H2Matrix):
         out["oracle_cg_fp64"] = {"time_to_1e-8_s": round(t2 - t1, 3), "setup_s": round(t1 - t0, 3),
                                  "cycles": res.cycles, "converged": res.converged,
                                  "threads": int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count())}
-    log(f"C1 {w.name}: " + ", ".join(f"{k} {v['time_to_1e-8_s']} s/{v['cycles']} cycles"
+    log(f"C1 {w.name}: " + ", ".join(f"{k} {v['time_to_1e-8_s']} s/{v.get('cycles', v.get('iterations'))}"
                                       for k, v in out.items() if isinstance(v, dict)))
     return out
+
+
+def growth_scan(args, torch, synth, H2Matrix):
+    """Iterations to 1e-8 against N on the shift-1 Matern problem: H2-MG
+    V-cycles (paper CG smoother and block smoother) next to the comparison
+    solver, CG (and block-Jacobi PCG) on A_H2 alone.  FP64; the near field is
+    stored when it fits, which speeds up every fine-level product alike."""
+    base = synth.workload("matern3d_1m_spd")
+    for n in [int(v) for v in args.growth.split(",")]:
+        w = base.scaled(n)
+        pts = torch.from_numpy(w.make_points()).cuda()
+        b = torch.from_numpy(w.make_rhs()).cuda()
+        g = H2Matrix(pts, w.kernel, w.length_scale, w.shift, w.leaf, w.eta, w.cheb_m)
+        try:
+            g.store_near(True)
+            stored = True
+        except Exception:
+            stored = False
+        g.setup()
+        out = {"growth": w.name, "n": n, "near_stored": stored}
+        for label, kw in (("vcycle_cg_smoother", dict(method="v", smoother="cg")),
+                          ("vcycle_block_smoother", dict(method="v", smoother="bj")),
+                          ("plain_cg", dict(method="cg", smoother="cg", max_cycles=50000)),
+                          ("plain_pcg_block_jacobi", dict(method="cg", smoother="bj", max_cycles=50000))):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = g.solve(b, rtol=1e-8, raise_on_error=False, **kw)
+            torch.cuda.synchronize()
+            out[label] = {"count": info["cycles"], "s": round(time.perf_counter() - t0, 3),
+                          "converged": info["converged"], "rel_residual": info["rel_residual"]}
+            log(f"growth n={n} {label}: {info['cycles']} in {out[label]['s']} s ({info['status']})")
+        print(json.dumps(out), flush=True)
+        g.close()
+        del pts, b
+        torch.cuda.empty_cache()
 
 
 def part_a(args, torch, synth, H2Matrix):
@@ -376,6 +420,9 @@ def main():
         return
     if args.spd_probe:
         spd_probe(args, torch, synth, H2Matrix)
+        return
+    if args.growth:
+        growth_scan(args, torch, synth, H2Matrix)
         return
     c1 = None if args.no_c1 else c1_latency(args, torch, synth, H2Matrix)
     headline = part_a(args, torch, synth, H2Matrix) if args.headline else None

@@ -104,18 +104,34 @@ typedef enum h2mg_smoother {
  * the finest / coarser levels; the solve stops when
  * ||b - A_H2 x||_2 / ||b||_2 < rtol, measured in FP64, or after max_cycles
  * V-cycles (FP64) or refinement steps (mixed forms, one V-cycle each). */
+/* Solver method.  V: Algorithm 1 repeated (Section 3.3).  W and F: the
+ * other cycles named after Algorithm 1, in their textbook recursive forms
+ * (after the first coarse correction of a level, a second one on the
+ * remaining coarse residual by a W-cycle, resp. a V-cycle; skipped when the
+ * coarse level is the directly solved one).  CG: the comparison solver of
+ * the experiments (Section 4), CG on A_H2 alone in FP64 (block-Jacobi PCG
+ * with the block smoother), stopped on the recurrence residual; there
+ * max_cycles counts CG iterations. */
+typedef enum h2mg_method {
+  H2MG_METHOD_V_CYCLE = 0,
+  H2MG_METHOD_W_CYCLE = 1,
+  H2MG_METHOD_F_CYCLE = 2,
+  H2MG_METHOD_CG = 3
+} h2mg_method;
+
 typedef struct h2mg_solve_opts {
   int32_t n_fine;        /* >= 0, paper default 1 */
   int32_t n_coarse;      /* >= 0, paper default 40 */
   double rtol;           /* > 0, e.g. 1e-8 */
-  int32_t max_cycles;    /* >= 0 */
-  int32_t precision;     /* h2mg_precision */
+  int32_t max_cycles;    /* >= 0 (CG iterations for H2MG_METHOD_CG) */
+  int32_t precision;     /* h2mg_precision (FP64 only for H2MG_METHOD_CG) */
   int32_t use_x0;        /* 1: x holds the initial guess; 0: start from 0 */
   int32_t smoother;      /* h2mg_smoother */
+  int32_t method;        /* h2mg_method, default 0 (V-cycles) */
 } h2mg_solve_opts;
 
 typedef struct h2mg_solve_info {
-  int32_t cycles;        /* V-cycles (or refinement steps) performed */
+  int32_t cycles;        /* cycles (refinement steps, CG iterations) performed */
   int32_t converged;     /* 1 if the residual test passed */
   double rel_residual;   /* final ||b - A_H2 x|| / ||b|| in FP64 */
   double solve_seconds;  /* wall time of the solve on the host clock */
@@ -218,8 +234,10 @@ h2mg_status h2mg_restrict(h2mg_h2_t h, int32_t level, const double* r_dev,
 h2mg_status h2mg_prolong(h2mg_h2_t h, int32_t level, const double* e_next_dev,
                          double* e_dev, hipStream_t stream);
 
-/* One V-cycle of Algorithm 1 in FP64: x_out = x0 + e_1 for A_H2 x = b.
- * All vectors device, length n, user order; x_out may alias x0. */
+/* One V-cycle of Algorithm 1 in FP64: x_out = x0 + e_1 for A_H2 x = b
+ * (a W- or F-cycle when opts->method says so; H2MG_METHOD_CG is
+ * INVALID_ARG here).  All vectors device, length n, user order; x_out may
+ * alias x0. */
 h2mg_status h2mg_vcycle(h2mg_h2_t h, const double* x0_dev, const double* b_dev,
                         double* x_out_dev, const h2mg_solve_opts* opts,
                         hipStream_t stream);

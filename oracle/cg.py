@@ -17,6 +17,9 @@ A second smoother, preconditioned CG with a block-Jacobi preconditioner M
 smoother on the leaf diagonal blocks and their coarse analogues; `pcg` is textbook
 PCG: z = M^{-1} s, p = z, gamma = s.z, ..., p = z + (gamma'/gamma) p, and
 `block_jacobi` applies M^{-1} block by block through Cholesky factors.
+
+`cg_solve` is the comparison solver of the experiments: CG (or PCG) run on
+A_H2 itself until the recurrence residual sqrt(s.s) / ||b|| falls below rtol.
 """
 from __future__ import annotations
 
@@ -98,3 +101,37 @@ def block_jacobi(A: np.ndarray, offsets):
             out[s:e] = scipy.linalg.cho_solve(f, v[s:e])
         return out
     return apply
+
+
+def cg_solve(apply, b: np.ndarray, rtol: float = 1e-8, max_iter: int = 10000, precond=None):
+    """CG (PCG when precond is given) on A x = b from x = 0.  Stops when the
+    recurrence residual ||s|| / ||b|| < rtol.  Returns (x, iterations,
+    converged, history of ||s|| / ||b|| before each iteration and at exit)."""
+    nb = float(np.linalg.norm(b))
+    x = np.zeros_like(b)
+    if nb == 0.0:
+        return x, 0, True, [0.0]
+    s = b.copy()
+    z = s if precond is None else precond(s)
+    p = z.copy()
+    gamma = float(s @ z)
+    hist = []
+    for it in range(max_iter + 1):
+        rel = float(np.linalg.norm(s)) / nb
+        hist.append(rel)
+        if rel < rtol:
+            return x, it, True, hist
+        if it == max_iter:
+            break
+        q = apply(p)
+        delta = float(p @ q)
+        if not delta > 0.0:
+            raise NotSPD(f"p^T A p = {delta!r}")
+        alpha = gamma / delta
+        x += alpha * p
+        s -= alpha * q
+        z = s if precond is None else precond(s)
+        gamma_new = float(s @ z)
+        p = z + (gamma_new / gamma) * p
+        gamma = gamma_new
+    return x, max_iter, False, hist

@@ -20,6 +20,17 @@ Readings:
 * smoother "bj": preconditioned CG with M = the diagonal blocks of each
   level's operator (leaf blocks of A_H2 on level 1, one r x r block per
   cluster on coarser levels): a block smoother on the diagonal blocks.
+
+Other cycles (the text after Algorithm 1 names W- and F-cycles without
+defining them; the textbook recursive forms are used).  Written as a
+recursion MG(i, r_i) returning e_i: pre-smooth from zero, restrict the
+residual, coarse correction, prolongate, post-smooth, with the coarsest
+level solved directly.  The coarse correction of level i is
+  V: e_{i+1} = V(i+1, r_{i+1});
+  W: e_{i+1} = W(i+1, r_{i+1}), then e_{i+1} += W(i+1, r_{i+1} - A_{i+1} e_{i+1});
+  F: e_{i+1} = F(i+1, r_{i+1}), then e_{i+1} += V(i+1, r_{i+1} - A_{i+1} e_{i+1});
+the second call is skipped when level i+1 is the coarsest (its solve is
+exact).  The V form is exactly Algorithm 1.
 """
 from __future__ import annotations
 
@@ -90,8 +101,41 @@ def vcycle(H, x0: np.ndarray, b: np.ndarray, n_f: int = 1, n_c: int = 40,
     return x0 + e
 
 
+def mg_cycle(H, x0: np.ndarray, b: np.ndarray, kind: str = "V", n_f: int = 1, n_c: int = 40,
+             factor=None, r1=None, smoother="cg", precs=None) -> np.ndarray:
+    """One V-, W- or F-cycle on the dense hierarchy H (tree order)."""
+    ops, P = H.ops, H.prolong
+    l = len(ops)
+    if factor is None:
+        factor = coarsest_factor(ops[-1])
+    if precs is None:
+        precs = smoothers(H, smoother)
+
+    def iterate(i, rhs, e0, n):
+        if precs is None:
+            return cg(ops[i].__matmul__, rhs, e0, n)
+        return pcg(ops[i].__matmul__, precs[i], rhs, e0, n)
+
+    def mg(i, rhs, kd):
+        if i == l - 1:
+            return scipy.linalg.cho_solve(factor, rhs)
+        n = n_f if i == 0 else n_c
+        e = iterate(i, rhs, None, n)
+        rc = P[i].T @ (rhs - ops[i] @ e)
+        ec = mg(i + 1, rc, kd)
+        if kd != "V" and i + 1 < l - 1:
+            ec = ec + mg(i + 1, rc - ops[i + 1] @ ec, "V" if kd == "F" else "W")
+        e = e + P[i] @ ec
+        return iterate(i, rhs, e, n)
+
+    if kind not in ("V", "W", "F"):
+        raise ValueError(kind)
+    r = b - ops[0] @ x0 if r1 is None else r1
+    return x0 + mg(0, r, kind)
+
+
 def solve(H, b: np.ndarray, rtol: float = 1e-8, max_cycles: int = 500,
-          n_f: int = 1, n_c: int = 40, x0=None, smoother="cg") -> SolveResult:
+          n_f: int = 1, n_c: int = 40, x0=None, smoother="cg", kind="V") -> SolveResult:
     """Repeated V-cycles on A_H2 x = b (b and x in tree order)."""
     A = H.ops[0]
     factor = coarsest_factor(H.ops[-1])
@@ -109,7 +153,10 @@ def solve(H, b: np.ndarray, rtol: float = 1e-8, max_cycles: int = 500,
             return SolveResult(x, cyc, True, hist)
         if cyc == max_cycles:
             break
-        x = vcycle(H, x, b, n_f, n_c, factor, r1=res, precs=precs)
+        if kind == "V":
+            x = vcycle(H, x, b, n_f, n_c, factor, r1=res, precs=precs)
+        else:
+            x = mg_cycle(H, x, b, kind, n_f, n_c, factor, r1=res, precs=precs)
     return SolveResult(x, max_cycles, False, hist)
 
 

@@ -28,7 +28,7 @@ class BuildOpts(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("n_fine", c_int32), ("n_coarse", c_int32), ("rtol", c_double),
                 ("max_cycles", c_int32), ("precision", c_int32), ("use_x0", c_int32),
-                ("smoother", c_int32)]
+                ("smoother", c_int32), ("method", c_int32)]
 
 
 class SolveInfo(ctypes.Structure):

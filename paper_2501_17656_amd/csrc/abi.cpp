@@ -45,7 +45,7 @@ h2mg_status check_stream_err(hipStream_t s) {
 bool valid_solve_opts(const h2mg_solve_opts* o) {
   return o && o->n_fine >= 0 && o->n_coarse >= 0 && o->rtol > 0.0 && std::isfinite(o->rtol) &&
          o->max_cycles >= 0 && o->precision >= 0 && o->precision <= 2 && o->smoother >= 0 &&
-         o->smoother <= 1;
+         o->smoother <= 1 && o->method >= 0 && o->method <= 3;
 }
 
 SolveParams to_params(const h2mg_solve_opts* o) {
@@ -57,6 +57,7 @@ SolveParams to_params(const h2mg_solve_opts* o) {
   sp.precision = o->precision;
   sp.use_x0 = o->use_x0 != 0;
   sp.smoother = o->smoother;
+  sp.method = o->method;
   return sp;
 }
 

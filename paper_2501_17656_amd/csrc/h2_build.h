@@ -31,10 +31,11 @@ struct SolveParams {
   int precision = 0;
   bool use_x0 = false;
   int smoother = 0;      // 0: CG, 1: block-Jacobi preconditioned CG
+  int method = 0;        // 0: V-cycles, 1: W-cycles, 2: F-cycles, 3: CG on A_H2 alone
 };
 // Solve A_H2 x = b; b, x device, user order.  Fills info.
 h2mg_status solve(H2& h, const double* b, double* x, const SolveParams& sp, h2mg_solve_info* info);
-// One FP64 V-cycle from x0 (user order).
+// One FP64 cycle (V, W or F by sp.method) from x0 (user order).
 h2mg_status vcycle_once(H2& h, const double* x0, const double* b, double* x_out, const SolveParams& sp);
 
 }  // namespace h2mg

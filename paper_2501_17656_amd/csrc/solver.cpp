@@ -1,5 +1,9 @@
 // The H2-MG solver: Algorithm 1 (Section 3.3) with CG smoothing, repeated
 // V-cycles, and FP64 iterative refinement around a low-precision V-cycle.
+// Also the W- and F-cycles named after Algorithm 1 (textbook recursive
+// forms: the coarse correction of a level is repeated once on the remaining
+// residual, with a W- or a V-cycle), and the comparison solver of the
+// experiments, CG on A_H2 alone.
 //
 // Every step runs on the device; the host only enqueues kernels and reads
 // the FP64 residual norm (a few hundred partial sums) once per cycle to
@@ -25,23 +29,27 @@ void hip_check(hipError_t e, const char* what) {
 inline int vprec(int p) { return p == P64 ? P64 : P32; }   // vector type of an operator precision
 inline size_t vbytes(int p) { return p == P64 ? 8 : 4; }
 
-// Per-precision V-cycle vectors: r_k and e~_k per level, CG temporaries.
+// Per-precision cycle vectors: r_k and e~_k per level, the first coarse
+// correction of W/F-cycles (ec), CG temporaries.
 struct Work {
-  std::vector<void*> r, et;
+  std::vector<void*> r, et, ec;
   void *s = nullptr, *pv = nullptr, *q = nullptr, *tmp = nullptr, *z = nullptr;
   int smoother = 0;
   double* gpart[2] = {nullptr, nullptr};
   double* dpart = nullptr;
 };
 
-Work make_work(H2& h, int p) {
+Work make_work(H2& h, int p, bool second_corrections = false) {
   Work w;
   const size_t vb = vbytes(p);
   w.r.resize(h.levels + 1);
   w.et.resize(h.levels + 1);
+  w.ec.assign(h.levels + 1, nullptr);
   for (int k = 1; k <= h.levels; ++k) {
     w.r[k] = h.arena.alloc(size_t(h.level_size(k)) * vb);
     w.et[k] = h.arena.alloc(size_t(h.level_size(k)) * vb);
+    if (second_corrections && k >= 2 && k < h.levels)
+      w.ec[k] = h.arena.alloc(size_t(h.level_size(k)) * vb);
   }
   w.s = h.arena.alloc(size_t(h.n) * vb);
   w.pv = h.arena.alloc(size_t(h.n) * vb);
@@ -58,6 +66,7 @@ void release_work(H2& h, Work& w) {
   for (int k = 1; k <= h.levels; ++k) {
     h.arena.release(w.r[k]);
     h.arena.release(w.et[k]);
+    if (w.ec[k]) h.arena.release(w.ec[k]);
   }
   h.arena.release(w.s);
   h.arena.release(w.pv);
@@ -178,27 +187,41 @@ void coarse_solve(H2& h, int p, const void* r, void* e) {
   }
 }
 
-// One V-cycle on the correction equation A e_1 = r_1 (w.r[1] holds r_1,
-// tree order); the result e_1 is left in w.et[1].
-void vcycle(H2& h, int p, Work& w, int n_f, int n_c) {
+enum Cycle { CYCLE_V = 0, CYCLE_W = 1, CYCLE_F = 2 };
+
+// One cycle on level k for A_k e_k = r_k (w.r[k] holds r_k); the result e_k
+// is left in w.et[k].  With kind V this is Algorithm 1 from level k down.
+void mg(H2& h, int p, Work& w, int k, int kind, int n_f, int n_c) {
   const int vp = vprec(p);
   const int l = h.levels;
-  for (int k = 1; k < l; ++k) {
-    const int nk = k == 1 ? n_f : n_c;
-    const int64_t N = h.level_size(k);
-    cg(h, p, k, w, w.r[k], w.et[k], true, nk);
-    // restriction of the residual: r_{k+1} = U_k^T (r_k - A_k e~_k)
-    apply_level(h, p, k, w.et[k], w.tmp);
-    launch_axpby(h, vp, N, 1.0, w.r[k], -1.0, w.tmp);
-    restrict_level(h, p, k, w.tmp, w.r[k + 1]);
+  if (k == l) {
+    coarse_solve(h, p, w.r[l], w.et[l]);
+    return;
   }
-  coarse_solve(h, p, w.r[l], w.et[l]);
-  for (int k = l - 1; k >= 1; --k) {
-    const int nk = k == 1 ? n_f : n_c;
-    prolong_level(h, p, k, w.et[k + 1], w.et[k], w.et[k], 1.0);   // e~_k += U_k e_{k+1}
-    cg(h, p, k, w, w.r[k], w.et[k], false, nk);
+  const int nk = k == 1 ? n_f : n_c;
+  const int64_t N = h.level_size(k);
+  cg(h, p, k, w, w.r[k], w.et[k], true, nk);
+  // restriction of the residual: r_{k+1} = U_k^T (r_k - A_k e~_k)
+  apply_level(h, p, k, w.et[k], w.tmp);
+  launch_axpby(h, vp, N, 1.0, w.r[k], -1.0, w.tmp);
+  restrict_level(h, p, k, w.tmp, w.r[k + 1]);
+  mg(h, p, w, k + 1, kind, n_f, n_c);
+  if (kind != CYCLE_V && k + 1 < l) {
+    // second coarse correction on r_{k+1} - A_{k+1} e_{k+1}
+    const int64_t N1 = h.level_size(k + 1);
+    launch_copy(h, vp, w.et[k + 1], w.ec[k + 1], N1);
+    apply_level(h, p, k + 1, w.et[k + 1], w.tmp);
+    launch_axpby(h, vp, N1, -1.0, w.tmp, 1.0, w.r[k + 1]);
+    mg(h, p, w, k + 1, kind == CYCLE_F ? CYCLE_V : CYCLE_W, n_f, n_c);
+    launch_axpby(h, vp, N1, 1.0, w.ec[k + 1], 1.0, w.et[k + 1]);
   }
+  prolong_level(h, p, k, w.et[k + 1], w.et[k], w.et[k], 1.0);   // e~_k += U_k e_{k+1}
+  cg(h, p, k, w, w.r[k], w.et[k], false, nk);
 }
+
+// One cycle on the correction equation A e_1 = r_1 (w.r[1] holds r_1,
+// tree order); the result e_1 is left in w.et[1].
+void vcycle(H2& h, int p, Work& w, int kind, int n_f, int n_c) { mg(h, p, w, 1, kind, n_f, n_c); }
 
 double host_norm(H2& h, const double* v, int64_t n) {
   const int np = dot_parts(n);
@@ -213,13 +236,84 @@ double host_norm(H2& h, const double* v, int64_t n) {
 }
 
 
+double sum_parts(H2& h, const double* part, int np) {
+  std::vector<double> v(np);
+  hip_check(hipMemcpyAsync(v.data(), part, np * sizeof(double), hipMemcpyDeviceToHost, h.stream),
+            "readback");
+  hip_check(hipStreamSynchronize(h.stream), "sync");
+  double s = 0.0;
+  for (int i = 0; i < np; ++i) s += v[i];
+  return s;
+}
+
+// The comparison solver: CG (block-Jacobi PCG with smoother 1) on A_H2 x = b
+// in FP64, tree order, from x = 0 or the given x.  The stopping test reads
+// the recurrence residual ||s|| / ||b|| (the sum of s.s partials) once per
+// iteration; iterations are counted in `cycles`.
+h2mg_status plain_cg(H2& h, Work& w, const double* bt, double* xt, double nb, const SolveParams& sp,
+                     int* iters, bool* converged) {
+  const int64_t n = h.n;
+  const int np = dot_parts(n);
+  const bool pre = w.smoother == 1;
+  double* s = static_cast<double*>(w.s);
+  double* z = static_cast<double*>(w.z);
+  double* pv = static_cast<double*>(w.pv);
+  double* q = static_cast<double*>(w.q);
+  double* ss = h.dot_part + 2048;
+  // s = b - A x
+  apply_fine(h, P64, xt, s, -1.0, bt, 1.0);
+  int cur = 0;
+  if (pre) {
+    launch_bj_apply(h, P64, 1, s, z);
+    launch_copy(h, P64, z, pv, n);
+    launch_dot(h, P64, n, s, z, w.gpart[cur]);
+    launch_dot(h, P64, n, s, s, ss);
+  } else {
+    launch_copy(h, P64, s, pv, n);
+    launch_dot(h, P64, n, s, s, w.gpart[cur]);
+  }
+  int f[4];
+  for (int it = 0;; ++it) {
+    const double rn = std::sqrt(sum_parts(h, pre ? ss : w.gpart[cur], np));
+    read_flags(h, f);
+    const double rel = rn / nb;
+    h.history.push_back(rel);
+    *iters = it;
+    if (f[0]) return fail(H2MG_ERR_NOT_SPD, "CG met p^T A p <= 0 (operator not SPD)");
+    if (!std::isfinite(rel)) return fail(H2MG_ERR_NUMERIC, "non-finite residual after %d iterations", it);
+    if (rel < sp.rtol) {
+      *converged = true;
+      return H2MG_OK;
+    }
+    if (it >= sp.max_cycles)
+      return fail(H2MG_ERR_NOT_CONVERGED, "CG: no convergence in %d iterations (rel. residual %.3e)",
+                  sp.max_cycles, rel);
+    apply_fine(h, P64, pv, q, 1.0, nullptr, 0.0);
+    launch_dot(h, P64, n, pv, q, w.dpart);
+    if (pre) {
+      launch_cg_update(h, P64, n, xt, pv, s, q, w.gpart[cur], w.dpart, ss);
+      launch_bj_apply(h, P64, 1, s, z);
+      launch_dot(h, P64, n, s, z, w.gpart[1 - cur]);
+      launch_cg_pupdate(h, P64, n, pv, z, w.gpart[cur], w.gpart[1 - cur]);
+    } else {
+      launch_cg_update(h, P64, n, xt, pv, s, q, w.gpart[cur], w.dpart, w.gpart[1 - cur]);
+      launch_cg_pupdate(h, P64, n, pv, s, w.gpart[cur], w.gpart[1 - cur]);
+    }
+    cur = 1 - cur;
+  }
+}
+
 }  // namespace
 
 h2mg_status solve(H2& h, const double* b, double* x, const SolveParams& sp, h2mg_solve_info* info) {
   const auto t0 = std::chrono::steady_clock::now();
   h.history.clear();
   const int p = sp.precision == 0 ? P64 : sp.precision == 1 ? P32 : P16;
-  h2mg_status st = setup_mg(h, p == P64 ? 0 : (1 << p));
+  const bool plain = sp.method == 3;
+  if (plain && p != P64) return fail(H2MG_ERR_INVALID_ARG, "CG on A_H2 alone runs in FP64 only");
+  // plain CG needs the hierarchy only for the block-Jacobi inverses, which
+  // are formed for all levels together
+  h2mg_status st = plain && sp.smoother == 0 ? H2MG_OK : setup_mg(h, p == P64 ? 0 : (1 << p));
   if (st != H2MG_OK) return st;
   if (sp.smoother == 1) {
     try {
@@ -238,10 +332,11 @@ h2mg_status solve(H2& h, const double* b, double* x, const SolveParams& sp, h2mg
   bool converged = false;
   double rel = 0.0;
   try {
-    w64 = make_work(h, P64);
+    const bool second = sp.method == CYCLE_W || sp.method == CYCLE_F;
+    w64 = make_work(h, P64, second && p == P64);
     w64.smoother = sp.smoother;
     if (p != P64) {
-      wlp = make_work(h, p);
+      wlp = make_work(h, p, second);
       wlp.smoother = sp.smoother;
       have_lp = true;
     }
@@ -268,6 +363,12 @@ h2mg_status solve(H2& h, const double* b, double* x, const SolveParams& sp, h2mg
       zero(h, xt, n, P64);
       h.history.push_back(0.0);
       converged = true;
+    } else if (sp.method == 3) {
+      result = plain_cg(h, w64, bt, xt, nb, sp, &cycles, &converged);
+      // report the true FP64 residual of the final iterate
+      apply_fine(h, P64, xt, res, -1.0, bt, 1.0);
+      rel = host_norm(h, res, n) / nb;
+      if (!h.history.empty()) h.history.back() = rel;
     } else {
       for (int cyc = 0;; ++cyc) {
         // res = b - A_H2 x (FP64)
@@ -286,11 +387,11 @@ h2mg_status solve(H2& h, const double* b, double* x, const SolveParams& sp, h2mg
           break;
         }
         if (p == P64) {
-          vcycle(h, P64, w64, sp.n_fine, sp.n_coarse);
+          vcycle(h, P64, w64, sp.method, sp.n_fine, sp.n_coarse);
           launch_axpby(h, P64, n, 1.0, w64.et[1], 1.0, xt);
         } else {
           launch_cast(h, P32, wlp.r[1], P64, res, n);
-          vcycle(h, p, wlp, sp.n_fine, sp.n_coarse);
+          vcycle(h, p, wlp, sp.method, sp.n_fine, sp.n_coarse);
           launch_cast(h, P64, h.vtree, P32, wlp.et[1], n);
           launch_axpby(h, P64, n, 1.0, h.vtree, 1.0, xt);
         }
@@ -319,6 +420,7 @@ h2mg_status solve(H2& h, const double* b, double* x, const SolveParams& sp, h2mg
 }
 
 h2mg_status vcycle_once(H2& h, const double* x0, const double* b, double* x_out, const SolveParams& sp) {
+  if (sp.method > CYCLE_F) return fail(H2MG_ERR_INVALID_ARG, "one cycle needs method V, W or F");
   h2mg_status st = setup_mg(h, 0);
   if (st != H2MG_OK) return st;
   try {
@@ -326,7 +428,7 @@ h2mg_status vcycle_once(H2& h, const double* x0, const double* b, double* x_out,
       st = ensure_block_jacobi(h, P64);
       if (st != H2MG_OK) return st;
     }
-    Work w = make_work(h, P64);
+    Work w = make_work(h, P64, sp.method != CYCLE_V);
     w.smoother = sp.smoother;
     const int64_t n = h.n;
     double* bt = static_cast<double*>(h.arena.alloc(size_t(n) * 8));
@@ -335,7 +437,7 @@ h2mg_status vcycle_once(H2& h, const double* x0, const double* b, double* x_out,
     launch_gather(h, x0, xt);
     hip_check(hipMemsetAsync(h.flags, 0, 4 * sizeof(int), h.stream), "memset");
     apply_fine(h, P64, xt, w.r[1], -1.0, bt, 1.0);   // r_1 = b - A x_0
-    vcycle(h, P64, w, sp.n_fine, sp.n_coarse);
+    vcycle(h, P64, w, sp.method, sp.n_fine, sp.n_coarse);
     launch_axpby(h, P64, n, 1.0, w.et[1], 1.0, xt);  // x* = x_0 + e_1
     launch_scatter(h, xt, x_out);
     int f[4];

@@ -16,6 +16,7 @@ from ._lib import check, lib
 KERNELS = {"exp": 0, "gauss": 1, "matern32": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 SMOOTHERS = {"cg": 0, "bj": 1}
+METHODS = {"v": 0, "w": 1, "f": 2, "cg": 3}
 
 
 def _stream():
@@ -143,25 +144,30 @@ class H2Matrix:
 
     # ------------------------------------------------------------ solves
     @staticmethod
-    def _opts(rtol, n_fine, n_coarse, max_cycles, precision, use_x0, smoother="cg"):
+    def _opts(rtol, n_fine, n_coarse, max_cycles, precision, use_x0, smoother="cg", method="v"):
         return _lib.SolveOpts(int(n_fine), int(n_coarse), float(rtol), int(max_cycles),
-                              PRECISIONS[precision], int(use_x0), SMOOTHERS[smoother])
+                              PRECISIONS[precision], int(use_x0), SMOOTHERS[smoother],
+                              METHODS[method])
 
-    def vcycle(self, x0, b, n_fine: int = 1, n_coarse: int = 40, out=None, smoother: str = "cg"):
+    def vcycle(self, x0, b, n_fine: int = 1, n_coarse: int = 40, out=None, smoother: str = "cg",
+               method: str = "v"):
+        """One cycle (V, W or F) from x0."""
         import torch
         x = torch.empty_like(b) if out is None else out
-        o = self._opts(1e-8, n_fine, n_coarse, 1, "fp64", 1, smoother)
+        o = self._opts(1e-8, n_fine, n_coarse, 1, "fp64", 1, smoother, method)
         check(lib().h2mg_vcycle(self._h, _dev_f64(x0, self.n, "x0"), _dev_f64(b, self.n, "b"),
                                 _dev_f64(x, self.n, "x"), ctypes.byref(o), _stream()))
         return x
 
     def solve(self, b, rtol: float = 1e-8, n_fine: int = 1, n_coarse: int = 40,
               max_cycles: int = 500, precision: str = "fp64", x0=None, raise_on_error: bool = True,
-              smoother: str = "cg"):
-        """Solve A_H2 x = b.  Returns (x, info dict)."""
+              smoother: str = "cg", method: str = "v"):
+        """Solve A_H2 x = b by V-, W- or F-cycles, or by CG alone (method
+        "cg"; max_cycles then counts CG iterations).  Returns (x, info)."""
         import torch
         x = torch.zeros_like(b) if x0 is None else x0.clone()
-        o = self._opts(rtol, n_fine, n_coarse, max_cycles, precision, x0 is not None, smoother)
+        o = self._opts(rtol, n_fine, n_coarse, max_cycles, precision, x0 is not None, smoother,
+                       method)
         info = _lib.SolveInfo()
         st = lib().h2mg_solve(self._h, _dev_f64(b, self.n, "b"), _dev_f64(x, self.n, "x"),
                               ctypes.byref(o), ctypes.byref(info), _stream())

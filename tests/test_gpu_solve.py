@@ -179,3 +179,75 @@ def test_solve_error_paths():
     assert info["converged"] and info["cycles"] == 0
     with pytest.raises(H2MGError):
         g.solve(_dev(b), rtol=-1.0)
+
+
+# ---------------------------------------------------------------- W/F-cycles, plain CG
+@pytest.mark.parametrize("name", ["exp2d_4k", "exp3d_r8"])
+@pytest.mark.parametrize("kind", ["W", "F"])
+def test_w_f_cycle_matches_oracle(name, kind):
+    """One W- or F-cycle with 2 coarse CG steps: iterate by iterate against
+    the oracle's recursive cycle on the dense hierarchy."""
+    from oracle.vcycle import mg_cycle
+    P, o, g = make(name)
+    H = hier(name)
+    n = len(P)
+    b = synth.normal_vector(n, 1)
+    x0 = 0.1 * synth.normal_vector(n, 5)
+    xg = _host(g.vcycle(_dev(x0), _dev(b), n_coarse=2, method=kind.lower()))
+    perm = o.tree.perm
+    xo = np.empty(n)
+    xo[perm] = mg_cycle(H, x0[perm], b[perm], kind, 1, 2)
+    xv = _host(g.vcycle(_dev(x0), _dev(b), n_coarse=2))
+    rel = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+    print(f"[gpu] {name} {kind}-cycle n_c=2 rel diff {rel:.2e} (levels {H.levels})")
+    assert rel <= 1e-10
+    if H.levels > 2:
+        assert np.linalg.norm(xg - xv) > 1e-6 * np.linalg.norm(xv)     # not a V-cycle
+
+
+@pytest.mark.parametrize("kind", ["w", "f"])
+def test_w_f_cycle_solve_reaches_oracle_solution(kind):
+    P, o, g = make("exp2d_4k")
+    H = hier("exp2d_4k")
+    b = synth.normal_vector(len(P), 1)
+    x, info = g.solve(_dev(b), rtol=1e-8, method=kind)
+    xh = _host(x)
+    res = np.linalg.norm(b - o.matvec(xh)) / np.linalg.norm(b)
+    xs = np.empty(len(P))
+    xs[o.tree.perm] = np.linalg.solve(H.ops[0], b[o.tree.perm])
+    err = np.linalg.norm(xh - xs) / np.linalg.norm(xs)
+    print(f"[gpu] {kind}-cycles: {info['cycles']} cycles, oracle residual {res:.2e}, error {err:.2e}")
+    assert info["converged"] and res < 1.5e-8
+    assert err <= np.linalg.cond(H.ops[0]) * 1e-8
+
+
+@pytest.mark.parametrize("smoother", ["cg", "bj"])
+def test_plain_cg_solve_matches_oracle(smoother):
+    """The comparison solver: CG (or block-Jacobi PCG) on A_H2 alone.  The
+    GPU's true residual, recomputed by the oracle, is below 1e-8 and its
+    iteration count is within 10% of the oracle's own CG on the dense A_H2."""
+    from oracle.cg import block_jacobi, cg_solve
+    P, o, g = make("exp2d_4k")
+    H = hier("exp2d_4k")
+    b = synth.normal_vector(len(P), 1)
+    x, info = g.solve(_dev(b), rtol=1e-8, method="cg", max_cycles=5000, smoother=smoother)
+    xh = _host(x)
+    res = np.linalg.norm(b - o.matvec(xh)) / np.linalg.norm(b)
+    perm = o.tree.perm
+    pre = None
+    if smoother == "bj":
+        pre = block_jacobi(H.ops[0], o.tree.offsets[o.L])
+    _, it_o, ok_o, _ = cg_solve(H.ops[0].__matmul__, b[perm], rtol=1e-8, max_iter=5000, precond=pre)
+    print(f"[gpu] plain {smoother}: {info['cycles']} iterations (oracle {it_o}), residual {res:.2e}")
+    assert info["converged"] and ok_o
+    assert res < 2e-8
+    assert abs(info["cycles"] - it_o) <= 0.1 * it_o + 2
+
+
+def test_plain_cg_rejects_low_precision():
+    from paper_2501_17656_amd import H2MGError
+    P, o, g = make("exp2d_4k")
+    with pytest.raises(H2MGError):
+        g.solve(_dev(synth.normal_vector(len(P), 1)), method="cg", precision="fp32")
+    with pytest.raises(H2MGError):
+        g.vcycle(_dev(np.zeros(len(P))), _dev(synth.normal_vector(len(P), 1)), method="cg")

@@ -12,12 +12,12 @@ import scipy.sparse.linalg
 import torch
 
 import synth
-from oracle.cg import NotSPD, block_jacobi, cg, pcg
+from oracle.cg import NotSPD, block_jacobi, cg, cg_solve, pcg
 from oracle.galerkin import Hierarchy, galerkin
 from oracle.h2 import H2
 from oracle.ir import ir_solve, round_bf16, round_fp32
 from oracle.ortho import coarse_basis, qr_pos
-from oracle.vcycle import coarsest_factor, solve, vcycle
+from oracle.vcycle import coarsest_factor, mg_cycle, solve, vcycle
 
 
 @pytest.fixture(scope="module")
@@ -226,3 +226,87 @@ def test_refinement_fixed_point_is_the_fp64_solution(small, prec):
     A = H.ops[0]
     assert res.converged
     assert np.linalg.norm(b - A @ res.x) < 1e-8 * np.linalg.norm(b)
+
+
+# ---------------------------------------------------------------- W/F-cycles, plain CG
+def _truncated(H, nlev):
+    """The first nlev levels of H with the last one solved directly."""
+    T = Hierarchy.__new__(Hierarchy)
+    T.h2, T.ops, T.prolong = H.h2, H.ops[:nlev], H.prolong[:nlev - 1]
+    return T
+
+
+def test_w_and_f_cycles_equal_v_on_two_levels(small):
+    """With one coarse level the coarse correction is an exact solve, so the
+    second coarse call is skipped and all three cycles coincide."""
+    h, H = small
+    T = _truncated(H, 2)
+    b = synth.normal_vector(h.n, 21)
+    v = vcycle(T, np.zeros(h.n), b, 1, 3)
+    for kind in ("V", "W", "F"):
+        np.testing.assert_array_equal(mg_cycle(T, np.zeros(h.n), b, kind, 1, 3), v)
+
+
+def test_coarsest_solves_per_cycle_follow_the_recursion(small, monkeypatch):
+    """Per cycle on l levels the coarsest level is solved once (V), 2^(l-2)
+    times (W) and l-1 times (F); on three levels F and W coincide."""
+    import oracle.vcycle as vc
+    h, H = small
+    l = len(H.ops)
+    calls = []
+    real = vc.scipy.linalg.cho_solve
+    monkeypatch.setattr(vc.scipy.linalg, "cho_solve", lambda f, r: calls.append(1) or real(f, r))
+    b = synth.normal_vector(h.n, 22)
+    for kind, expect in (("V", 1), ("W", 2 ** (l - 2)), ("F", l - 1)):
+        calls.clear()
+        mg_cycle(H, np.zeros(h.n), b, kind, 1, 3)
+        assert len(calls) == expect, kind
+    T = _truncated(H, 3)
+    np.testing.assert_array_equal(mg_cycle(T, np.zeros(h.n), b, "F", 1, 3),
+                                  mg_cycle(T, np.zeros(h.n), b, "W", 1, 3))
+    np.testing.assert_array_equal(mg_cycle(H, np.zeros(h.n), b, "V", 1, 3),
+                                  vcycle(H, np.zeros(h.n), b, 1, 3))
+
+
+@pytest.mark.parametrize("kind", ["W", "F"])
+def test_w_f_cycles_error_monotone_and_converge(small, kind):
+    h, H = small
+    A = H.ops[0]
+    b = synth.normal_vector(h.n, 23)
+    xs = np.linalg.solve(A, b)
+    x = np.zeros(h.n)
+    prev = np.inf
+    for _ in range(4):
+        x = mg_cycle(H, x, b, kind, 1, 10)
+        err = np.sqrt((x - xs) @ A @ (x - xs))
+        assert err <= prev * (1 + 1e-12)
+        prev = err
+    v = mg_cycle(H, np.zeros(h.n), b, "V", 1, 10)
+    assert not np.array_equal(v, mg_cycle(H, np.zeros(h.n), b, kind, 1, 10))
+    res = solve(H, b, rtol=1e-8, n_c=10, kind=kind)
+    assert res.converged and res.history[-1] < 1e-8
+    assert np.linalg.norm(res.x - xs) <= np.linalg.cond(A) * 1e-8 * np.linalg.norm(xs)
+
+
+def test_plain_cg_solve_distinct_eigenvalues_and_scipy():
+    """CG on a matrix with k distinct eigenvalues terminates in k steps; on a
+    general SPD matrix its iterates match scipy's CG."""
+    rng = np.random.default_rng(3)
+    Q, _ = np.linalg.qr(rng.standard_normal((60, 60)))
+    lam = np.repeat([1.0, 2.0, 5.0, 7.0, 11.0], 12)
+    A = (Q * lam) @ Q.T
+    b = rng.standard_normal(60)
+    x, it, ok, hist = cg_solve(A.__matmul__, b, rtol=1e-10, max_iter=50)
+    assert ok and it == 5
+    np.testing.assert_allclose(x, np.linalg.solve(A, b), rtol=1e-9)
+    M = rng.standard_normal((40, 40))
+    A = M @ M.T + 40 * np.eye(40)
+    b = rng.standard_normal(40)
+    x, it, ok, hist = cg_solve(A.__matmul__, b, rtol=1e-12, max_iter=3)
+    xr, _ = scipy.sparse.linalg.cg(A, b, x0=np.zeros(40), rtol=1e-30, atol=0.0, maxiter=3)
+    np.testing.assert_allclose(x, xr, rtol=1e-12)
+    assert not ok and len(hist) == 4
+    # block-Jacobi preconditioning with the whole matrix as one block: one step
+    x, it, ok, _ = cg_solve(A.__matmul__, b, rtol=1e-12, max_iter=5,
+                            precond=block_jacobi(A, [0, 40]))
+    assert ok and it == 1
