@@ -10,6 +10,16 @@ Readings:
 * Matern-3/2: k(r) = (1 + sqrt(3) r / l) exp(-sqrt(3) r / l).
 * Exponential: k(r) = exp(-r / l) (the paper's sigma is l).
 
+Derivative kernels (for the gradient of b^T A^{-1} b; no shift): a kind
+"<base>/dl" is the radial profile dk/dl (derivative in the length scale at
+fixed r) and "<base>/g" is g(r) = k'(r) / r, through which the gradient of
+k(|p_i - p_j|) in p_i is g(r_ij) (p_i - p_j).  g is set to 0 at r = 0 (its
+self term cancels in the gradient; for the exponential kernel g is singular
+there).  Closed forms, with z = sqrt(3) r / l for Matern-3/2:
+  exp:      dk/dl = (r / l^2) exp(-r/l),        g = -exp(-r/l) / (l r)
+  gauss:    dk/dl = (r^2 / l^3) exp(-r^2/2l^2), g = -exp(-r^2/2l^2) / l^2
+  matern32: dk/dl = (z^2 / l) exp(-z),          g = -(3 / l^2) exp(-z)
+
 A kernel is represented here by a callable taking two point arrays
 X (n, dim) and Y (m, dim) and returning the (n, m) matrix of k(x_i, y_j)
 *without* the diagonal shift.  The shift is added by `kernel_matrix` only on
@@ -29,8 +39,11 @@ def distances(X: np.ndarray, Y: np.ndarray) -> np.ndarray:
 
 
 def radial(kind: str, length_scale: float):
-    """The radial profile k(r) of a named kernel."""
+    """The radial profile k(r) of a named kernel ("exp", "gauss",
+    "matern32", or one of those followed by "/dl" or "/g")."""
     ell = float(length_scale)
+    if "/" in kind:
+        return _derivative(kind, ell)
     if kind == "exp":
         return lambda r: np.exp(-r / ell)
     if kind == "gauss":
@@ -38,6 +51,32 @@ def radial(kind: str, length_scale: float):
     if kind == "matern32":
         a = np.sqrt(3.0) / ell
         return lambda r: (1.0 + a * r) * np.exp(-a * r)
+    raise ValueError(f"unknown kernel kind {kind!r}")
+
+
+def _derivative(kind: str, ell: float):
+    base, which = kind.split("/")
+    if which == "dl":
+        if base == "exp":
+            return lambda r: (r / ell ** 2) * np.exp(-r / ell)
+        if base == "gauss":
+            return lambda r: (r * r / ell ** 3) * np.exp(-(r * r) / (2.0 * ell * ell))
+        if base == "matern32":
+            a = np.sqrt(3.0) / ell
+            return lambda r: ((a * r) ** 2 / ell) * np.exp(-a * r)
+    if which == "g":
+        if base == "exp":
+            def g(r):
+                r = np.asarray(r, dtype=np.float64)
+                safe = np.where(r > 0.0, r, 1.0)
+                return np.where(r > 0.0, -np.exp(-safe / ell) / (ell * safe), 0.0)
+            return g
+        if base == "gauss":
+            return lambda r: np.where(np.asarray(r) > 0.0,
+                                      -np.exp(-(r * r) / (2.0 * ell * ell)) / ell ** 2, 0.0)
+        if base == "matern32":
+            a = np.sqrt(3.0) / ell
+            return lambda r: np.where(np.asarray(r) > 0.0, -(3.0 / ell ** 2) * np.exp(-a * r), 0.0)
     raise ValueError(f"unknown kernel kind {kind!r}")
 
 
