@@ -66,6 +66,7 @@ def parse():
     ap.add_argument("--matvec-reps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-c1", action="store_true", help="skip the small-configuration latency run")
+    ap.add_argument("--no-diff", action="store_true", help="skip the gradient run")
     ap.add_argument("--cpu-leaves", type=int, default=48)
     ap.add_argument("--json-out", default="")
     return ap.parse_args()
@@ -325,6 +326,45 @@ def growth_scan(args, torch, synth, H2Matrix):
         torch.cuda.empty_cache()
 
 
+def differentiation(args, torch, synth, H2Matrix):
+    """Gradient of L = b^T A^{-1} b in (l, s, points) on the exponential-
+    kernel workload (N = 2^18): forward H2-MG solve, then the derivative-
+    kernel H2 builds and their 1 + 1 + dim products."""
+    w = synth.workload("exp3d_256k")
+    pts = torch.from_numpy(w.make_points()).cuda()
+    b = torch.from_numpy(w.make_rhs()).cuda()
+    out = {"workload": f"{w.name}: N={w.n}, {w.kernel} l={w.length_scale} + {w.shift}*I, "
+                       f"leaf {w.leaf}, eta {w.eta}, rank {w.rank}, solve rtol 1e-10, block smoother"}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = H2Matrix(pts, w.kernel, w.length_scale, w.shift, w.leaf, w.eta, w.cheb_m)
+    g.setup()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    x, info = g.solve(b, rtol=1e-10, smoother="bj", raise_on_error=False)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out.update({"build_and_setup_s": round(t1 - t0, 3), "solve_s": round(t2 - t1, 3),
+                "solve_cycles": info["cycles"], "solve_status": info["status"]})
+    if info["converged"]:
+        hl, hg = g.derivative("dl"), g.derivative("g")
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        L, dl, ds, gp, _ = g.quadratic_gradient(hl, hg, b, x)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        out.update({"derivative_builds_s": round(t3 - t2, 3), "gradient_products_s": round(t4 - t3, 3),
+                    "loss": L, "dL_dl": dl, "dL_ds": ds,
+                    "grad_points_norm": float(gp.norm()),
+                    "backward_total_s": round(t4 - t2, 3)})
+        hl.close()
+        hg.close()
+    g.close()
+    log(f"differentiation {w.name}: solve {out['solve_s']} s ({out['solve_status']}), "
+        f"backward {out.get('backward_total_s')} s")
+    return out
+
+
 def part_a(args, torch, synth, H2Matrix):
     """The exact headline workload: build, setup, matvec and a few cycles."""
     w = synth.workload(args.headline)
@@ -425,6 +465,7 @@ def main():
         growth_scan(args, torch, synth, H2Matrix)
         return
     c1 = None if args.no_c1 else c1_latency(args, torch, synth, H2Matrix)
+    diff = None if args.no_diff else differentiation(args, torch, synth, H2Matrix)
     headline = part_a(args, torch, synth, H2Matrix) if args.headline else None
     if headline:
         log(f"part A: build {headline['build_s']} s, matvec {headline['matvec_ms']} ms, "
@@ -554,6 +595,7 @@ def main():
         "roofline_fp64_gemv": rec["rl64"],
         "paper_cg_smoother": cg_runs,
         "c1_small_config": c1,
+        "differentiation": diff,
         "headline_shift_1e-3": headline,
     }
     if not args.no_cpu:

@@ -65,10 +65,22 @@ typedef enum h2mg_kernel_kind {
   H2MG_KERNEL_MATERN32 = 2
 } h2mg_kernel_kind;
 
+/* Derivative kernels, for the gradient of L = b^T A^{-1} b (not in the
+ * paper; the gradient follows from its problem statement A x = b with
+ * A = K(p; l) + s I): the profile dk/dl at fixed r, or g(r) = k'(r) / r,
+ * through which grad_{p_i} k(|p_i - p_j|) = g(r_ij) (p_i - p_j).  g is 0 at
+ * r = 0 (its self term cancels in the gradient). */
+typedef enum h2mg_kernel_derivative {
+  H2MG_KERNEL_VALUE = 0,
+  H2MG_KERNEL_D_LENGTH = 1,
+  H2MG_KERNEL_D_RADIAL = 2
+} h2mg_kernel_derivative;
+
 typedef struct h2mg_kernel {
   int32_t kind;          /* h2mg_kernel_kind */
   double length_scale;   /* l > 0 */
   double shift;          /* >= 0, added to the diagonal */
+  int32_t derivative;    /* h2mg_kernel_derivative, 0 for the kernel itself */
 } h2mg_kernel;
 
 /* Cluster tree and bases (Section 3.1).  Binary tree of uniform depth
@@ -196,6 +208,33 @@ h2mg_status h2mg_build(const double* points_dev, int64_t n, int32_t dim,
 h2mg_status h2mg_matvec(h2mg_h2_t h, const double* x_dev, double* y_dev,
                         hipStream_t stream);
 
+/* Build the H2 matrix of a derivative kernel (`which` = H2MG_KERNEL_D_LENGTH
+ * or H2MG_KERNEL_D_RADIAL, shift 0) on the same points, tree, partition and
+ * Chebyshev bases as `h` (same kernel kind and length scale).  *out must be
+ * destroyed with h2mg_destroy.  Errors: INVALID_ARG (bad which, null), OOM,
+ * HIP.  Blocks until the build is complete. */
+h2mg_status h2mg_build_derivative(h2mg_h2_t h, int32_t which, hipStream_t stream,
+                                  h2mg_h2_t* out);
+
+/* Loss L = b^T x and its gradient for x = A^{-1} b (x from h2mg_solve on h):
+ *   dL/dl = -x^T (dA/dl) x,  dL/ds = -x^T x,
+ *   dL/dp_ia = -2 x_i [p_ia (G x)_i - (G (x * p_.a))_i],  dL/db = 2 x,
+ * with dA/dl and G = [g(r_ij)] the H2 matrices h_dl and h_g from
+ * h2mg_build_derivative on h (A symmetric, so the adjoint solve is the
+ * forward solve).  Every gradient output is multiplied by `scale` (the
+ * incoming gradient of an autodiff chain; 1 for the plain gradient).
+ * b_dev, x_dev: device, length n, user order.  grad_points_dev: device,
+ * n x dim row-major, user order, or null to skip the 1 + dim products with
+ * G; grad_b_dev: device, length n, or null.  Host outputs may be null; h_dl
+ * may be null when grad_length is, h_g when grad_points_dev is.  Errors:
+ * INVALID_ARG (null handle or vector, a derivative handle missing, of the
+ * wrong kind or built on other points), HIP. */
+h2mg_status h2mg_quadratic_gradient(h2mg_h2_t h, h2mg_h2_t h_dl, h2mg_h2_t h_g,
+                                    const double* b_dev, const double* x_dev, double scale,
+                                    double* loss, double* grad_length, double* grad_shift,
+                                    double* grad_points_dev, double* grad_b_dev,
+                                    hipStream_t stream);
+
 /* Store the near field (Section 3.1: the dense close leaf blocks D of the
  * matvec y = D x + U_1 y_1).  enable != 0 evaluates every close leaf pair
  * once, as 64 x 64 FP64 tiles between chunks of at most 64 points of a leaf
@@ -253,6 +292,15 @@ h2mg_status h2mg_solve(h2mg_h2_t h, const double* b_dev, double* x_dev,
 /* Relative residual before each cycle of the last solve, then at exit
  * (host array of at least `capacity` doubles; copies min(capacity, len)). */
 h2mg_status h2mg_solve_history(h2mg_h2_t h, double* history_host, int32_t capacity);
+
+/* Cycle graphs.  When enabled, h2mg_solve records the launches of one cycle
+ * (V/W/F-cycle and the update of x, not the FP64 residual and its norm) into
+ * a HIP graph on a private stream the first time and then launches that
+ * graph once per cycle into the caller's stream; the arithmetic is the same
+ * launch for launch, so results are bitwise those of the direct launches.
+ * Ignored while kernel timing is enabled and by H2MG_METHOD_CG.  Off by
+ * default. */
+h2mg_status h2mg_set_graphs(h2mg_h2_t h, int32_t enabled);
 
 /* Kernel timing, for measurement harnesses.  While enabled, every launch of
  * the block GEMV and of the near-field kernel is bracketed by HIP events on

@@ -2,8 +2,10 @@
 
 `H2Matrix` builds the H2 approximation of a kernel matrix from points on the
 GPU, multiplies by it and solves with the H2-MG V-cycle; `Plan` exposes the
-host-side cluster tree and block partition.  Every numerical step runs in
+host-side cluster tree and block partition; `quadratic_loss` is
+L = b^T A^{-1} b as a differentiable torch function.  Every numerical step runs in
 libh2mg.so; this package only marshals arguments.
 """
 from .h2mg import H2Matrix, Plan, KERNELS, PRECISIONS  # noqa: F401
 from ._lib import H2MGError  # noqa: F401
+from .autograd import quadratic_loss  # noqa: F401

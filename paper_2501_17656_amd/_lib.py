@@ -18,7 +18,8 @@ P_int32 = ctypes.POINTER(c_int32)
 
 
 class Kernel(ctypes.Structure):
-    _fields_ = [("kind", c_int32), ("length_scale", c_double), ("shift", c_double)]
+    _fields_ = [("kind", c_int32), ("length_scale", c_double), ("shift", c_double),
+                ("derivative", c_int32)]
 
 
 class BuildOpts(ctypes.Structure):
@@ -69,6 +70,10 @@ SIGNATURES = {
     "h2mg_memory_bytes": (c_int32, [c_void_p, P_int64]),
     "h2mg_set_timing": (c_int32, [c_void_p, c_int32]),
     "h2mg_store_near": (c_int32, [c_void_p, c_int32, c_void_p]),
+    "h2mg_set_graphs": (c_int32, [c_void_p, c_int32]),
+    "h2mg_build_derivative": (c_int32, [c_void_p, c_int32, c_void_p, ctypes.POINTER(c_void_p)]),
+    "h2mg_quadratic_gradient": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double,
+                                          P_double, P_double, P_double, c_void_p, c_void_p, c_void_p]),
     "h2mg_kernel_stats": (c_int32, [c_void_p, c_int32, P_int64, P_double, P_double]),
     "h2mg_destroy": (c_int32, [c_void_p]),
     "h2mg_last_error": (ctypes.c_char_p, []),

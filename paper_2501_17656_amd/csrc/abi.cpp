@@ -285,11 +285,45 @@ h2mg_status h2mg_memory_bytes(h2mg_h2_t hh, int64_t* bytes) {
   });
 }
 
+h2mg_status h2mg_build_derivative(h2mg_h2_t hh, int32_t which, hipStream_t stream, h2mg_h2_t* out) {
+  return guarded([&] {
+    if (!hh || !out) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    hh->h->stream = stream;
+    H2* d = nullptr;
+    h2mg_status st = build_derivative(*hh->h, which, &d);
+    if (st != H2MG_OK) return st;
+    *out = new h2mg_h2_s{d};
+    return H2MG_OK;
+  });
+}
+
+h2mg_status h2mg_quadratic_gradient(h2mg_h2_t hh, h2mg_h2_t hl, h2mg_h2_t hg, const double* b,
+                                    const double* x, double scale, double* loss, double* grad_l,
+                                    double* grad_s, double* grad_p, double* grad_b,
+                                    hipStream_t stream) {
+  return guarded([&] {
+    if (!hh || !b || !x) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    if (!std::isfinite(scale)) return fail(H2MG_ERR_INVALID_ARG, "scale must be finite");
+    hh->h->stream = stream;
+    return quadratic_gradient(*hh->h, hl ? hl->h : nullptr, hg ? hg->h : nullptr, b, x, scale, loss,
+                              grad_l, grad_s, grad_p, grad_b);
+  });
+}
+
 h2mg_status h2mg_store_near(h2mg_h2_t hh, int32_t enable, hipStream_t stream) {
   return guarded([&] {
     if (!hh) return fail(H2MG_ERR_INVALID_ARG, "null handle");
     hh->h->stream = stream;
     return store_near(*hh->h, enable);
+  });
+}
+
+h2mg_status h2mg_set_graphs(h2mg_h2_t hh, int32_t enabled) {
+  return guarded([&] {
+    if (!hh) return fail(H2MG_ERR_INVALID_ARG, "null handle");
+    hh->h->graphs = enabled != 0;
+    return H2MG_OK;
   });
 }
 

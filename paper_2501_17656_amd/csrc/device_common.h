@@ -105,29 +105,46 @@ __device__ inline void load_subtile(const Tb* __restrict__ tile, int lane, Tacc 
 
 // ---------------------------------------------------------------- kernels
 enum { KER_EXP = 0, KER_GAUSS = 1, KER_MATERN32 = 2 };
+// deriv: the kernel itself, its derivative in the length scale at fixed r,
+// or g(r) = k'(r) / r (0 at r = 0, where its self term cancels in the
+// coordinate gradient).
+enum { DER_NONE = 0, DER_LENGTH = 1, DER_RADIAL = 2 };
 
 struct KernelParams {
   int kind;
+  int deriv;
   double inv_l;        // 1 / l
   double inv_2l2;      // 1 / (2 l^2)
   double shift;
 };
 
-// k as a function of the squared distance (no shift).
+// k (or its derivative) as a function of the squared distance (no shift).
+template <typename T>
+__device__ inline T kernel_r2_t(int kind, int deriv, T inv_l, T inv_2l2, T r2) {
+  if (deriv == DER_RADIAL && r2 == T(0)) return T(0);
+  if (kind == KER_GAUSS) {
+    const T e = exp(-r2 * inv_2l2);
+    if (deriv == DER_NONE) return e;
+    return deriv == DER_LENGTH ? r2 * inv_l * inv_l * inv_l * e : -inv_l * inv_l * e;
+  }
+  const T rr = sqrt(r2);
+  if (kind == KER_EXP) {
+    const T e = exp(-rr * inv_l);
+    if (deriv == DER_NONE) return e;
+    return deriv == DER_LENGTH ? rr * inv_l * inv_l * e : -inv_l * e / rr;
+  }
+  const T z = T(1.7320508075688772) * rr * inv_l;
+  const T e = exp(-z);
+  if (deriv == DER_NONE) return (T(1) + z) * e;
+  return deriv == DER_LENGTH ? z * z * inv_l * e : T(-3) * inv_l * inv_l * e;
+}
+
 __device__ inline double kernel_r2(const KernelParams& kp, double r2) {
-  if (kp.kind == KER_GAUSS) return exp(-r2 * kp.inv_2l2);
-  const double rr = sqrt(r2);
-  if (kp.kind == KER_EXP) return exp(-rr * kp.inv_l);
-  const double z = 1.7320508075688772 * rr * kp.inv_l;
-  return (1.0 + z) * exp(-z);
+  return kernel_r2_t<double>(kp.kind, kp.deriv, kp.inv_l, kp.inv_2l2, r2);
 }
 
 __device__ inline float kernel_r2(const KernelParams& kp, float r2) {
-  if (kp.kind == KER_GAUSS) return expf(-r2 * float(kp.inv_2l2));
-  const float rr = sqrtf(r2);
-  if (kp.kind == KER_EXP) return expf(-rr * float(kp.inv_l));
-  const float z = 1.7320508f * rr * float(kp.inv_l);
-  return (1.0f + z) * expf(-z);
+  return kernel_r2_t<float>(kp.kind, kp.deriv, float(kp.inv_l), float(kp.inv_2l2), r2);
 }
 
 // ---------------------------------------------------------------- shuffles

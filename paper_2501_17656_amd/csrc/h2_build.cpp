@@ -41,6 +41,7 @@ Arena::~Arena() {
 
 H2::~H2() {
   for (hipEvent_t e : events) (void)hipEventDestroy(e);
+  if (capture_stream) (void)hipStreamDestroy(capture_stream);
 }
 
 int H2::take_event() {
@@ -162,6 +163,8 @@ h2mg_status build_h2(const double* points_dev, int64_t n, int dim, const h2mg_ke
                      const h2mg_build_opts* opts, hipStream_t stream, H2** out) {
   if (!points_dev || !kernel || !opts || !out) return fail(H2MG_ERR_INVALID_ARG, "null argument");
   if (kernel->kind < 0 || kernel->kind > 2) return fail(H2MG_ERR_INVALID_ARG, "unknown kernel kind %d", kernel->kind);
+  if (kernel->derivative < 0 || kernel->derivative > 2)
+    return fail(H2MG_ERR_INVALID_ARG, "unknown kernel derivative %d", kernel->derivative);
   if (!(kernel->length_scale > 0.0) || !std::isfinite(kernel->length_scale))
     return fail(H2MG_ERR_INVALID_ARG, "length_scale must be finite and > 0");
   if (!(kernel->shift >= 0.0) || !std::isfinite(kernel->shift))
@@ -197,7 +200,10 @@ h2mg_status build_h2(const double* points_dev, int64_t n, int dim, const h2mg_ke
     h.nleaf = 1 << h.L;
     h.leaf_max = P.leaf_max;
     h.ngid = (1 << (h.L + 1)) - 1;
+    h.kernel = *kernel;
+    h.opts = *opts;
     h.kp.kind = kernel->kind;
+    h.kp.deriv = kernel->derivative;
     h.kp.inv_l = 1.0 / kernel->length_scale;
     h.kp.inv_2l2 = 1.0 / (2.0 * kernel->length_scale * kernel->length_scale);
     h.kp.shift = kernel->shift;
@@ -361,6 +367,102 @@ h2mg_status build_h2(const double* points_dev, int64_t n, int dim, const h2mg_ke
     return fail(H2MG_ERR_HIP, "%s", ex.what());
   }
   *out = hp;
+  return H2MG_OK;
+}
+
+h2mg_status build_derivative(H2& h, int which, H2** out) {
+  if (which != 1 && which != 2) return fail(H2MG_ERR_INVALID_ARG, "derivative must be 1 or 2 (got %d)", which);
+  double* user = nullptr;
+  try {
+    user = h.arena.make<double>(size_t(h.n) * h.dim);
+    launch_scatter_rows(h, h.pts, user);
+    hip_check(hipStreamSynchronize(h.stream), "scatter points");
+  } catch (const std::bad_alloc&) {
+    return fail(H2MG_ERR_OOM, "device allocation failed");
+  } catch (const std::exception& ex) {
+    return fail(H2MG_ERR_HIP, "%s", ex.what());
+  }
+  h2mg_kernel k = h.kernel;
+  k.derivative = which;
+  k.shift = 0.0;
+  const h2mg_status st = build_h2(user, h.n, h.dim, &k, &h.opts, h.stream, out);
+  h.arena.release(user);
+  if (st == H2MG_OK && (*out)->plan.perm != h.plan.perm) {
+    delete *out;
+    *out = nullptr;
+    return fail(H2MG_ERR_HIP, "derivative build produced a different tree");
+  }
+  return st;
+}
+
+h2mg_status quadratic_gradient(H2& h, H2* hl, H2* hg, const double* b, const double* x, double scale,
+                               double* loss, double* grad_l, double* grad_s, double* grad_p,
+                               double* grad_b) {
+  auto same_points = [&](const H2* d) {
+    return d->n == h.n && d->dim == h.dim && d->plan.perm == h.plan.perm;
+  };
+  if (grad_l && (!hl || !same_points(hl) || hl->kp.deriv != DER_LENGTH))
+    return fail(H2MG_ERR_INVALID_ARG, "dL/dl needs h_dl, the length-scale derivative on the same points");
+  if (grad_p && (!hg || !same_points(hg) || hg->kp.deriv != DER_RADIAL))
+    return fail(H2MG_ERR_INVALID_ARG, "dL/dp needs h_g, the radial derivative on the same points");
+  const int64_t n = h.n;
+  const int np = dot_parts(n);
+  auto host_sum = [&](const double* part) {
+    std::vector<double> v(np);
+    hip_check(hipMemcpyAsync(v.data(), part, np * sizeof(double), hipMemcpyDeviceToHost, h.stream),
+              "readback");
+    hip_check(hipStreamSynchronize(h.stream), "sync");
+    double acc = 0.0;
+    for (double t : v) acc += t;
+    return acc;
+  };
+  double* u = nullptr;
+  double* w = nullptr;
+  try {
+    // L = b^T x, dL/ds = -x^T x (user order)
+    launch_dot(h, P64, n, b, x, h.dot_part);
+    const double L = host_sum(h.dot_part);
+    launch_dot(h, P64, n, x, x, h.dot_part);
+    const double xx = host_sum(h.dot_part);
+    if (loss) *loss = L;
+    if (grad_s) *grad_s = -scale * xx;
+    // dL/dl = -x^T (dA/dl) x (tree order)
+    if (grad_l) {
+      H2& dl = *hl;
+      dl.stream = h.stream;
+      launch_gather(dl, x, dl.vtree);
+      apply_fine(dl, P64, dl.vtree, dl.vtree2, 1.0, nullptr, 0.0);
+      launch_dot(dl, P64, n, dl.vtree, dl.vtree2, h.dot_part);
+      *grad_l = -scale * host_sum(h.dot_part);
+    }
+    // dL/dp_ia = -2 x_i [p_ia (G x)_i - (G (x * p_.a))_i]
+    if (grad_p) {
+      H2& g = *hg;
+      g.stream = h.stream;
+      u = g.arena.make<double>(n);
+      w = g.arena.make<double>(n);
+      launch_gather(g, x, g.vtree);
+      apply_fine(g, P64, g.vtree, g.vtree2, 1.0, nullptr, 0.0);
+      for (int a = 0; a < h.dim; ++a) {
+        launch_coord_mul(g, a, g.vtree, w);
+        apply_fine(g, P64, w, u, 1.0, nullptr, 0.0);
+        launch_coord_grad(g, a, scale, g.vtree, g.vtree2, u, grad_p);
+      }
+    }
+    if (grad_b) launch_axpby(h, P64, n, 2.0 * scale, x, 0.0, grad_b);
+    hip_check(hipStreamSynchronize(h.stream), "gradient");
+  } catch (const std::bad_alloc&) {
+    if (u) hg->arena.release(u);
+    if (w) hg->arena.release(w);
+    return fail(H2MG_ERR_OOM, "device allocation failed in the gradient");
+  } catch (const std::exception& ex) {
+    (void)hipStreamSynchronize(h.stream);
+    if (u) hg->arena.release(u);
+    if (w) hg->arena.release(w);
+    return fail(H2MG_ERR_HIP, "%s", ex.what());
+  }
+  if (u) hg->arena.release(u);
+  if (w) hg->arena.release(w);
   return H2MG_OK;
 }
 

@@ -11,6 +11,15 @@ h2mg_status setup_mg(H2& h, int precision_mask);
 // tiles) for every later FP64 fine product; enable == 0: release them and
 // go back to evaluating the near field in every product.
 h2mg_status store_near(H2& h, int enable);
+// H2 matrix of dk/dl (which 1) or g = k'(r)/r (which 2) on the points and
+// tree of h (shift 0).
+h2mg_status build_derivative(H2& h, int which, H2** out);
+// L = b^T x and scale * (dL/dl, dL/ds, dL/dp, dL/db) for x = A^{-1} b
+// (user order; null outputs are skipped; hl is needed for dL/dl, hg for
+// dL/dp).
+h2mg_status quadratic_gradient(H2& h, H2* hl, H2* hg, const double* b, const double* x, double scale,
+                               double* loss, double* grad_l, double* grad_s, double* grad_p,
+                               double* grad_b);
 
 // Products in precision p (vectors double for P64, float otherwise).
 // Fine level, tree order: out = alpha * A_H2 x + beta * add (add may be null).

@@ -126,6 +126,8 @@ struct PrecData {                      // operator storage in one precision
 struct H2 {
   Plan plan;
   KernelParams kp{};
+  h2mg_kernel kernel{};                // as given to the build
+  h2mg_build_opts opts{};
   int n = 0, dim = 0, r = 0, m = 0, L = 0, d_top = -1, T = 1;
   int nleaf = 0, leaf_max = 0;
   int ngid = 0;                        // 2^(L+1) - 1
@@ -185,6 +187,11 @@ struct H2 {
   int bj_ld = 0;                       // padded leaf block size of the finest level
   void* bj_fine[3] = {nullptr, nullptr, nullptr};   // nleaf blocks of bj_ld^2
   void* bj_coarse[3] = {nullptr, nullptr, nullptr}; // per gid r^2 (depths d_top+1..L)
+
+  // cycle graphs: with graphs on, the first cycle of a solve is captured
+  // (on a private stream) and every cycle is one graph launch
+  bool graphs = false;
+  hipStream_t capture_stream = nullptr;
 
   // kernel timing
   bool timing = false;
@@ -254,6 +261,7 @@ void launch_fine_reduce(H2& h, int p, const void* yhat, void* out, bool to_user,
 void launch_gather(H2& h, const double* user, double* tree);     // tree[i] = user[perm[i]]
 void launch_scatter(H2& h, const double* tree, double* user);    // user[perm[i]] = tree[i]
 void launch_copy(H2& h, int p, const void* src, void* dst, int64_t n);
+void launch_zero(H2& h, int p, void* dst, int64_t n);
 void launch_cast(H2& h, int pdst, void* dst, int psrc, const void* src, int64_t n);
 // y = a*x + b*y  (vector type of p)
 void launch_axpby(H2& h, int p, int64_t n, double a, const void* x, double b, void* y);
@@ -268,6 +276,12 @@ void launch_cg_pupdate(H2& h, int p, int64_t n, void* pv, const void* s,
                        const double* gamma_old_part, const double* gamma_new_part);
 void launch_chol_solve(H2& h, const double* L, int64_t N, double* x);   // in place
 void launch_check_finite(H2& h, int p, int64_t n, const void* x);      // sets flags[1]
+// Gradient helpers (tree-ordered points h.pts, n x dim).
+void launch_scatter_rows(H2& h, const double* tree, double* user);     // user[perm[i], :] = tree[i, :]
+void launch_coord_mul(H2& h, int a, const double* x, double* w);       // w = x * p[:, a]
+// grad[perm[i], a] = -2 scale x_i (p[i, a] v_i - u_i)
+void launch_coord_grad(H2& h, int a, double scale, const double* x, const double* v, const double* u,
+                       double* grad);
 // z = M^{-1} s on one level (block-Jacobi): level 1 uses the leaf blocks,
 // level k >= 2 the r x r blocks of its depth.
 void launch_bj_apply(H2& h, int p, int k, const void* s, void* z);

@@ -79,6 +79,49 @@ __global__ __launch_bounds__(NT) void k_axpby(int64_t n, double a, const Tv* __r
   if (i < n) y[i] = Tv(a) * x[i] + (b == 0.0 ? Tv(0) : Tv(b) * y[i]);
 }
 
+// y = x and y = 0 as kernels (no memset or memcpy nodes when a cycle is
+// captured into a graph).
+template <typename Tv>
+__global__ __launch_bounds__(NT) void k_copy(int64_t n, const Tv* __restrict__ x, Tv* __restrict__ y) {
+  const int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x;
+  if (i < n) y[i] = x[i];
+}
+
+template <typename Tv>
+__global__ __launch_bounds__(NT) void k_zero(int64_t n, Tv* __restrict__ y) {
+  const int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x;
+  if (i < n) y[i] = Tv(0);
+}
+
+// ---------------------------------------------------------------- gradient helpers
+// user[perm[i]] = tree[i] for rows of dim coordinates.
+__global__ __launch_bounds__(NT) void k_scatter_rows(int64_t n, int dim, const int64_t* __restrict__ perm,
+                                                     const double* __restrict__ tree,
+                                                     double* __restrict__ user) {
+  const int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x;
+  if (i < n)
+    for (int a = 0; a < dim; ++a) user[perm[i] * dim + a] = tree[i * dim + a];
+}
+
+// w_i = x_i * p_{i,a} (tree order).
+__global__ __launch_bounds__(NT) void k_coord_mul(int64_t n, int dim, int a, const double* __restrict__ x,
+                                                  const double* __restrict__ pts, double* __restrict__ w) {
+  const int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x;
+  if (i < n) w[i] = x[i] * pts[i * dim + a];
+}
+
+// grad[perm[i], a] = -2 scale x_i (p_{i,a} v_i - u_i), v = G x, u = G (x * p_.a).
+__global__ __launch_bounds__(NT) void k_coord_grad(int64_t n, int dim, int a, double scale,
+                                                   const int64_t* __restrict__ perm,
+                                                   const double* __restrict__ x,
+                                                   const double* __restrict__ pts,
+                                                   const double* __restrict__ v,
+                                                   const double* __restrict__ u,
+                                                   double* __restrict__ grad) {
+  const int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x;
+  if (i < n) grad[perm[i] * dim + a] = -2.0 * scale * x[i] * (pts[i * dim + a] * v[i] - u[i]);
+}
+
 template <typename Tv>
 __global__ __launch_bounds__(NT) void k_dot(int64_t n, const Tv* __restrict__ x,
                                             const Tv* __restrict__ y, double* __restrict__ part) {
@@ -248,9 +291,23 @@ void launch_scatter(H2& h, const double* tree, double* user) {
 }
 
 void launch_copy(H2& h, int p, const void* src, void* dst, int64_t n) {
-  const size_t bytes = size_t(n) * (p == P64 ? 8 : 4);
-  if (hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, h.stream) != hipSuccess)
-    throw std::runtime_error("hipMemcpyAsync failed");
+  if (n <= 0) return;
+  if (p == P64)
+    hipLaunchKernelGGL(k_copy<double>, dim3(blocks(n)), dim3(NT), 0, h.stream, n,
+                       static_cast<const double*>(src), static_cast<double*>(dst));
+  else
+    hipLaunchKernelGGL(k_copy<float>, dim3(blocks(n)), dim3(NT), 0, h.stream, n,
+                       static_cast<const float*>(src), static_cast<float*>(dst));
+  check_launch("copy");
+}
+
+void launch_zero(H2& h, int p, void* dst, int64_t n) {
+  if (n <= 0) return;
+  if (p == P64)
+    hipLaunchKernelGGL(k_zero<double>, dim3(blocks(n)), dim3(NT), 0, h.stream, n, static_cast<double*>(dst));
+  else
+    hipLaunchKernelGGL(k_zero<float>, dim3(blocks(n)), dim3(NT), 0, h.stream, n, static_cast<float*>(dst));
+  check_launch("zero");
 }
 
 void launch_cast(H2& h, int pdst, void* dst, int psrc, const void* src, int64_t n) {
@@ -352,6 +409,25 @@ void launch_bj_apply(H2& h, int p, int k, const void* s, void* z) {
                        reinterpret_cast<const float*>(base), ld, static_cast<const float*>(s),
                        static_cast<float*>(z));
   check_launch("bj_apply");
+}
+
+void launch_scatter_rows(H2& h, const double* tree, double* user) {
+  hipLaunchKernelGGL(k_scatter_rows, dim3(blocks(h.n)), dim3(NT), 0, h.stream, int64_t(h.n), h.dim,
+                     h.perm, tree, user);
+  check_launch("scatter_rows");
+}
+
+void launch_coord_mul(H2& h, int a, const double* x, double* w) {
+  hipLaunchKernelGGL(k_coord_mul, dim3(blocks(h.n)), dim3(NT), 0, h.stream, int64_t(h.n), h.dim, a, x,
+                     h.pts, w);
+  check_launch("coord_mul");
+}
+
+void launch_coord_grad(H2& h, int a, double scale, const double* x, const double* v, const double* u,
+                       double* grad) {
+  hipLaunchKernelGGL(k_coord_grad, dim3(blocks(h.n)), dim3(NT), 0, h.stream, int64_t(h.n), h.dim, a,
+                     scale, h.perm, x, h.pts, v, u, grad);
+  check_launch("coord_grad");
 }
 
 void launch_check_finite(H2& h, int p, int64_t n, const void* x) {

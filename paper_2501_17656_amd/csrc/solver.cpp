@@ -75,8 +75,40 @@ void release_work(H2& h, Work& w) {
   h.arena.release(w.z);
 }
 
-void zero(H2& h, void* v, int64_t n, int p) {
-  hip_check(hipMemsetAsync(v, 0, size_t(n) * vbytes(p), h.stream), "memset");
+void zero(H2& h, void* v, int64_t n, int p) { launch_zero(h, p, v, n); }
+
+// A captured cycle: instantiated once per solve, launched once per cycle.
+struct CycleGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~CycleGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+// Record the launches of body() into g on the handle's private capture
+// stream (the caller's stream may be the null stream, which cannot be
+// captured), then instantiate it.
+template <typename F>
+void capture(H2& h, CycleGraph& g, F&& body) {
+  hipStream_t user = h.stream;
+  if (!h.capture_stream)
+    hip_check(hipStreamCreateWithFlags(&h.capture_stream, hipStreamNonBlocking), "stream create");
+  h.stream = h.capture_stream;
+  hip_check(hipStreamBeginCapture(h.capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  try {
+    body();
+  } catch (...) {
+    hipGraph_t partial = nullptr;
+    (void)hipStreamEndCapture(h.capture_stream, &partial);
+    if (partial) (void)hipGraphDestroy(partial);
+    h.stream = user;
+    throw;
+  }
+  h.stream = user;
+  hip_check(hipStreamEndCapture(h.capture_stream, &g.graph), "end capture");
+  hip_check(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0), "graph instantiate");
 }
 
 void read_flags(H2& h, int* f) {
@@ -370,6 +402,10 @@ h2mg_status solve(H2& h, const double* b, double* x, const SolveParams& sp, h2mg
       rel = host_norm(h, res, n) / nb;
       if (!h.history.empty()) h.history.back() = rel;
     } else {
+      // event timing records events between launches, so it runs the cycle
+      // launch by launch
+      const bool use_graph = h.graphs && !h.timing;
+      CycleGraph cg_graph;
       for (int cyc = 0;; ++cyc) {
         // res = b - A_H2 x (FP64)
         apply_fine(h, P64, xt, res, -1.0, bt, 1.0);
@@ -386,14 +422,22 @@ h2mg_status solve(H2& h, const double* b, double* x, const SolveParams& sp, h2mg
                         sp.max_cycles, rel);
           break;
         }
-        if (p == P64) {
-          vcycle(h, P64, w64, sp.method, sp.n_fine, sp.n_coarse);
-          launch_axpby(h, P64, n, 1.0, w64.et[1], 1.0, xt);
+        auto body = [&]() {
+          if (p == P64) {
+            vcycle(h, P64, w64, sp.method, sp.n_fine, sp.n_coarse);
+            launch_axpby(h, P64, n, 1.0, w64.et[1], 1.0, xt);
+          } else {
+            launch_cast(h, P32, wlp.r[1], P64, res, n);
+            vcycle(h, p, wlp, sp.method, sp.n_fine, sp.n_coarse);
+            launch_cast(h, P64, h.vtree, P32, wlp.et[1], n);
+            launch_axpby(h, P64, n, 1.0, h.vtree, 1.0, xt);
+          }
+        };
+        if (use_graph) {
+          if (!cg_graph.exec) capture(h, cg_graph, body);
+          hip_check(hipGraphLaunch(cg_graph.exec, h.stream), "graph launch");
         } else {
-          launch_cast(h, P32, wlp.r[1], P64, res, n);
-          vcycle(h, p, wlp, sp.method, sp.n_fine, sp.n_coarse);
-          launch_cast(h, P64, h.vtree, P32, wlp.et[1], n);
-          launch_axpby(h, P64, n, 1.0, h.vtree, 1.0, xt);
+          body();
         }
       }
     }

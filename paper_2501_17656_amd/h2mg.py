@@ -17,6 +17,7 @@ KERNELS = {"exp": 0, "gauss": 1, "matern32": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 SMOOTHERS = {"cg": 0, "bj": 1}
 METHODS = {"v": 0, "w": 1, "f": 2, "cg": 3}
+DERIVATIVES = {"value": 0, "dl": 1, "g": 2}
 
 
 def _stream():
@@ -80,17 +81,48 @@ class H2Matrix:
     """H2 approximation of a kernel matrix, built and applied on the GPU."""
 
     def __init__(self, points, kernel: str = "matern32", length_scale: float = 0.2,
-                 shift: float = 1e-3, leaf: int = 128, eta: float = 0.7, m: int = 4):
+                 shift: float = 1e-3, leaf: int = 128, eta: float = 0.7, m: int = 4,
+                 derivative: str = "value"):
+        if points is None:                 # wrapped handle (see derivative())
+            return
         pts = points if points.is_contiguous() else points.contiguous()
         n, dim = pts.shape
         _dev_f64(pts, name="points")
         self.n, self.dim = int(n), int(dim)
-        ker = _lib.Kernel(KERNELS[kernel], float(length_scale), float(shift))
+        ker = _lib.Kernel(KERNELS[kernel], float(length_scale), float(shift), DERIVATIVES[derivative])
         opts = _lib.BuildOpts(int(leaf), float(eta), int(m))
         h = ctypes.c_void_p()
         check(lib().h2mg_build(ctypes.c_void_p(pts.data_ptr()), self.n, self.dim, ctypes.byref(ker),
                                ctypes.byref(opts), _stream(), ctypes.byref(h)))
         self._h = h
+
+    # ------------------------------------------------------------ derivatives
+    def derivative(self, which: str) -> "H2Matrix":
+        """H2 matrix of dk/dl ("dl") or g = k'(r)/r ("g") on the same points
+        and tree (shift 0)."""
+        h = ctypes.c_void_p()
+        check(lib().h2mg_build_derivative(self._h, DERIVATIVES[which], _stream(), ctypes.byref(h)))
+        d = H2Matrix(None)
+        d.n, d.dim, d._h = self.n, self.dim, h
+        return d
+
+    def quadratic_gradient(self, h_dl, h_g, b, x, scale: float = 1.0, b_grad: bool = False):
+        """L = b^T x and scale * (dL/dl, dL/ds, dL/dp, dL/db) for x = A^{-1} b.
+        dL/dl needs h_dl = derivative("dl"), dL/dp needs h_g = derivative("g");
+        pass None to skip them.  Returns (L, dl or None, ds, grad_points or
+        None, grad_b or None)."""
+        import torch
+        loss, gl, gs = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        gp = (torch.empty((self.n, self.dim), dtype=torch.float64, device=x.device)
+              if h_g is not None else None)
+        gb = torch.empty_like(x) if b_grad else None
+        check(lib().h2mg_quadratic_gradient(
+            self._h, h_dl._h if h_dl is not None else None, h_g._h if h_g is not None else None,
+            _dev_f64(b, self.n, "b"), _dev_f64(x, self.n, "x"), float(scale), ctypes.byref(loss),
+            ctypes.byref(gl) if h_dl is not None else None, ctypes.byref(gs),
+            _dev_f64(gp) if gp is not None else None, _dev_f64(gb) if gb is not None else None,
+            _stream()))
+        return loss.value, (gl.value if h_dl is not None else None), gs.value, gp, gb
 
     # ------------------------------------------------------------ products
     def matvec(self, x, out=None):
@@ -182,6 +214,10 @@ class H2Matrix:
 
     KERNEL_KINDS = {"gemv_fp64": 0, "gemv_fp32": 1, "gemv_bf16": 2, "near_fp64": 3, "near_fp32": 4,
                     "near_gemv_fp64": 5}
+
+    def set_graphs(self, enabled: bool) -> None:
+        """Launch each solver cycle as one captured HIP graph."""
+        check(lib().h2mg_set_graphs(self._h, int(bool(enabled))))
 
     def set_timing(self, enabled: bool) -> None:
         check(lib().h2mg_set_timing(self._h, int(bool(enabled))))
