@@ -254,8 +254,10 @@ def c1_latency(args, torch, synth, H2Matrix):
     g.setup(("fp64", "fp32"))
     torch.cuda.synchronize()
     out = {"workload": f"{w.name}: N={w.n}, {w.kernel} l={w.length_scale} + {w.shift}*I, "
-                       f"leaf {w.leaf}, eta {w.eta}, rank {w.rank}, rtol 1e-8",
+                       f"leaf {w.leaf}, eta {w.eta}, rank {w.rank}, rtol 1e-8; each cycle launched "
+                       f"as one captured HIP graph",
            "build_and_setup_s": round(time.perf_counter() - t0, 4)}
+    g.set_graphs(True)
     runs = [(m, sm, pr) for sm in ("cg", "bj") for pr in ("fp64", "fp32") for m in ("v",)]
     runs += [(m, sm, "fp64") for sm in ("cg", "bj") for m in ("w", "f", "cg")]
     for method, smoother, prec in runs:

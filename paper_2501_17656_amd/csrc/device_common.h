@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace h2mg {
 
 // ---------------------------------------------------------------- bf16
@@ -118,25 +120,55 @@ struct KernelParams {
   double shift;
 };
 
-// k (or its derivative) as a function of the squared distance (no shift).
+// k (or its derivative) as a function of the squared distance (no shift),
+// for a kernel fixed at compile time.
+template <int KIND, int DERIV, typename T>
+__device__ inline T kernel_fixed(T inv_l, T inv_2l2, T r2) {
+  if constexpr (DERIV == DER_RADIAL) {
+    if (r2 == T(0)) return T(0);
+  }
+  if constexpr (KIND == KER_GAUSS) {
+    const T e = exp(-r2 * inv_2l2);
+    if constexpr (DERIV == DER_NONE) return e;
+    else if constexpr (DERIV == DER_LENGTH) return r2 * inv_l * inv_l * inv_l * e;
+    else return -inv_l * inv_l * e;
+  } else if constexpr (KIND == KER_EXP) {
+    const T rr = sqrt(r2);
+    const T e = exp(-rr * inv_l);
+    if constexpr (DERIV == DER_NONE) return e;
+    else if constexpr (DERIV == DER_LENGTH) return rr * inv_l * inv_l * e;
+    else return -inv_l * e / rr;
+  } else {
+    const T rr = sqrt(r2);
+    const T z = T(1.7320508075688772) * rr * inv_l;
+    const T e = exp(-z);
+    if constexpr (DERIV == DER_NONE) return (T(1) + z) * e;
+    else if constexpr (DERIV == DER_LENGTH) return z * z * inv_l * e;
+    else return T(-3) * inv_l * inv_l * e;
+  }
+}
+
+// Call f(integral_constant<KIND>, integral_constant<DERIV>) for a runtime pair.
+template <typename F>
+__host__ __device__ inline void dispatch_kernel(int kind, int deriv, F&& f) {
+  using I = int;
+  auto d = [&](auto kc) {
+    if (deriv == DER_LENGTH) f(kc, std::integral_constant<I, DER_LENGTH>{});
+    else if (deriv == DER_RADIAL) f(kc, std::integral_constant<I, DER_RADIAL>{});
+    else f(kc, std::integral_constant<I, DER_NONE>{});
+  };
+  if (kind == KER_GAUSS) d(std::integral_constant<I, KER_GAUSS>{});
+  else if (kind == KER_EXP) d(std::integral_constant<I, KER_EXP>{});
+  else d(std::integral_constant<I, KER_MATERN32>{});
+}
+
 template <typename T>
 __device__ inline T kernel_r2_t(int kind, int deriv, T inv_l, T inv_2l2, T r2) {
-  if (deriv == DER_RADIAL && r2 == T(0)) return T(0);
-  if (kind == KER_GAUSS) {
-    const T e = exp(-r2 * inv_2l2);
-    if (deriv == DER_NONE) return e;
-    return deriv == DER_LENGTH ? r2 * inv_l * inv_l * inv_l * e : -inv_l * inv_l * e;
-  }
-  const T rr = sqrt(r2);
-  if (kind == KER_EXP) {
-    const T e = exp(-rr * inv_l);
-    if (deriv == DER_NONE) return e;
-    return deriv == DER_LENGTH ? rr * inv_l * inv_l * e : -inv_l * e / rr;
-  }
-  const T z = T(1.7320508075688772) * rr * inv_l;
-  const T e = exp(-z);
-  if (deriv == DER_NONE) return (T(1) + z) * e;
-  return deriv == DER_LENGTH ? z * z * inv_l * e : T(-3) * inv_l * inv_l * e;
+  T v = T(0);
+  dispatch_kernel(kind, deriv, [&](auto kc, auto dc) {
+    v = kernel_fixed<decltype(kc)::value, decltype(dc)::value, T>(inv_l, inv_2l2, r2);
+  });
+  return v;
 }
 
 __device__ inline double kernel_r2(const KernelParams& kp, double r2) {

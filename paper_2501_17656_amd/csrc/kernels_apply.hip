@@ -364,7 +364,7 @@ __global__ __launch_bounds__(256) void k_leaf_up(const int* __restrict__ leaf_of
 // workgroup per task (row leaf s, pairs [p0, p1)), 16 x 16 threads, each
 // thread an 8 x 8 sub-tile of a 128 x 128 tile.  Row sums go to
 // partial[task], column sums of off-diagonal pairs to colpart[pair].
-template <typename Tv, typename Te>
+template <typename Tv, typename Te, int KIND, int DERIV>
 __global__ __launch_bounds__(256) void k_near(const int* __restrict__ tasks,
                                               const int* __restrict__ pair_col,
                                               const int* __restrict__ leaf_off,
@@ -426,7 +426,7 @@ __global__ __launch_bounds__(256) void k_near(const int* __restrict__ tasks,
               const double dx = pi[u][a] - pj[a];
               r2 += dx * dx;
             }
-            Tv k = Tv(kernel_r2(kp, Te(r2)));
+            Tv k = Tv(kernel_fixed<KIND, DERIV, Te>(Te(kp.inv_l), Te(kp.inv_2l2), Te(r2)));
             if (diag && rt + ti + 16 * u == ct + j) k += Tv(kp.shift);
             racc[u] += k * xj;
             cacc += k * xi[u];
@@ -686,15 +686,18 @@ void launch_near(H2& h, int p, const void* xtree) {
   int ev;
   h.time_begin(ev);
   const dim3 g(h.near.ntasks), b(256);
-  if (p == P64)
-    hipLaunchKernelGGL((k_near<double, double>), g, b, 0, h.stream, h.near.task, h.near.pair_col,
-                       h.leaf_off, h.pts, h.dim, static_cast<const double*>(xtree), h.near_partial,
-                       h.near_colpart, h.near.ld, h.kp);
-  else
-    hipLaunchKernelGGL((k_near<float, float>), g, b, 0, h.stream, h.near.task, h.near.pair_col,
-                       h.leaf_off, h.pts, h.dim, static_cast<const float*>(xtree),
-                       reinterpret_cast<float*>(h.near_partial),
-                       reinterpret_cast<float*>(h.near_colpart), h.near.ld, h.kp);
+  dispatch_kernel(h.kp.kind, h.kp.deriv, [&](auto kc, auto dc) {
+    constexpr int K = decltype(kc)::value, D = decltype(dc)::value;
+    if (p == P64)
+      hipLaunchKernelGGL((k_near<double, double, K, D>), g, b, 0, h.stream, h.near.task,
+                         h.near.pair_col, h.leaf_off, h.pts, h.dim, static_cast<const double*>(xtree),
+                         h.near_partial, h.near_colpart, h.near.ld, h.kp);
+    else
+      hipLaunchKernelGGL((k_near<float, float, K, D>), g, b, 0, h.stream, h.near.task,
+                         h.near.pair_col, h.leaf_off, h.pts, h.dim, static_cast<const float*>(xtree),
+                         reinterpret_cast<float*>(h.near_partial),
+                         reinterpret_cast<float*>(h.near_colpart), h.near.ld, h.kp);
+  });
   check_launch("near");
   h.time_end(p == P64 ? KS_NEAR64 : KS_NEAR32, ev, double(h.near_evals));
 }
