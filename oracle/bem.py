@@ -1,0 +1,90 @@
+"""The boundary-element matrix of the Laplace single layer (oracle; test
+infrastructure only).
+
+Paper: Section 4.3.  Triangles with centroids y_j, quadrature weights w_j
+(the triangle areas) and collocation points x_i = y_i give
+    A_ij = w_j / (4 pi ||x_i - y_j||)  (i != j),   A_ii = w_i / (4 pi R_i),
+with R_i the mean distance from the centroid of triangle i to its three
+vertices, and the right-hand side of a point source x_0 off the surface,
+f_j = 1 / (4 pi ||y_j - x_0||).
+
+Finding and reading for the diagonal: with A_ii = w_i / (4 pi R_i) the
+matrix is indefinite on the bumpy torus (about half of its eigenvalues are
+negative at 576 to 8000 panels): the regularised self term is about 3 times
+smaller than the potential of the panel's own uniform density at its
+centroid.  The self term used instead is that potential itself,
+A_ii = I_i / (4 pi), with I_i the integral of 1 / |y_i - y| over the flat
+triangle, in closed form: the sum over the three edges of
+d_e ln((s_2 + r_2) / (s_1 + r_1)), where d_e is the distance from the
+centroid to the edge line, s_1, s_2 the signed positions of the edge's end
+points along it and r_1, r_2 their distances to the centroid.  With it the
+matrix is positive definite.
+
+A has column weights, so it is not symmetric.  Reading: the library solves
+the symmetric form S y = W^(1/2) f with S = W^(1/2) A W^(-1/2)
+= W^(1/2) G W^(1/2), G_ij = 1 / (4 pi r_ij), G_ii = 1 / (4 pi R_i), and
+recovers sigma = W^(-1/2) y; S is the kernel matrix 1/(4 pi r) in the scaled
+form of h2.py with s = sqrt(w) and d = A_ii.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .kernels import distances
+
+
+def panels(V: np.ndarray, T: np.ndarray):
+    """Centroids (nt, 3), areas (nt,) and R_i (nt,) of a triangle mesh."""
+    a, b, c = V[T[:, 0]], V[T[:, 1]], V[T[:, 2]]
+    y = (a + b + c) / 3.0
+    w = 0.5 * np.linalg.norm(np.cross(b - a, c - a), axis=1)
+    R = (np.linalg.norm(y - a, axis=1) + np.linalg.norm(y - b, axis=1)
+         + np.linalg.norm(y - c, axis=1)) / 3.0
+    return y, w, R
+
+
+def self_integral(V: np.ndarray, T: np.ndarray) -> np.ndarray:
+    """Integral of 1 / |y_i - y| over triangle i, y_i its centroid (closed
+    form, edge by edge)."""
+    a, b, c = V[T[:, 0]], V[T[:, 1]], V[T[:, 2]]
+    y = (a + b + c) / 3.0
+    total = np.zeros(len(T))
+    for p1, p2 in ((a, b), (b, c), (c, a)):
+        e = p2 - p1
+        t = e / np.linalg.norm(e, axis=1)[:, None]
+        s1 = np.sum((p1 - y) * t, axis=1)
+        s2 = np.sum((p2 - y) * t, axis=1)
+        d = np.linalg.norm(y - (p1 - s1[:, None] * t), axis=1)
+        r1 = np.linalg.norm(p1 - y, axis=1)
+        r2 = np.linalg.norm(p2 - y, axis=1)
+        total += d * np.log((s2 + r2) / (s1 + r1))
+    return total
+
+
+def diagonal(V: np.ndarray, T: np.ndarray, self_term: str = "analytic") -> np.ndarray:
+    """A_ii: I_i / (4 pi) ("analytic", used by the library) or the paper's
+    w_i / (4 pi R_i) ("paper")."""
+    y, w, R = panels(V, T)
+    if self_term == "paper":
+        return w / (4.0 * np.pi * R)
+    return self_integral(V, T) / (4.0 * np.pi)
+
+
+def collocation_matrix(V: np.ndarray, T: np.ndarray, self_term: str = "analytic") -> np.ndarray:
+    """The (nonsymmetric) collocation matrix A, dense (small meshes only)."""
+    y, w, R = panels(V, T)
+    D = distances(y, y)
+    np.fill_diagonal(D, 1.0)
+    A = w[None, :] / (4.0 * np.pi * D)
+    A[np.diag_indices_from(A)] = diagonal(V, T, self_term)
+    return A
+
+
+def symmetric_scaling(V: np.ndarray, T: np.ndarray, self_term: str = "analytic"):
+    """(points, s, d) of the symmetric form: centroids, sqrt(w), A_ii."""
+    y, w, R = panels(V, T)
+    return y, np.sqrt(w), diagonal(V, T, self_term)
+
+
+def point_source_rhs(points: np.ndarray, x0) -> np.ndarray:
+    return 1.0 / (4.0 * np.pi * np.linalg.norm(points - np.asarray(x0, dtype=np.float64), axis=1))

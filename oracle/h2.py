@@ -34,9 +34,17 @@ class H2:
 
     `kern` is a callable k(X, Y) (see kernels.py) or a kind name.  Vectors
     passed to the public methods are in user order.
+
+    Scaled form: with per-point `scale` s and `diag` d (user order), the
+    matrix is diag(s) K diag(s) + diag(d) (d replaces the constant shift),
+    so every block gets s on its rows and columns and the cluster bases are
+    diag(s_rows) U.  This is the symmetric W^(1/2) G W^(1/2) form of the
+    collocation matrix of the boundary-element experiment (Section 4.3):
+    s = sqrt(panel area), d = area / (4 pi R_i), k = 1 / (4 pi r).
     """
 
-    def __init__(self, points, kern, shift, leaf, eta, m, length_scale=None):
+    def __init__(self, points, kern, shift, leaf, eta, m, length_scale=None, scale=None,
+                 diag=None):
         if isinstance(kern, str):
             kern = make_kernel(kern, length_scale)
         self.kern = kern
@@ -49,6 +57,9 @@ class H2:
         self.part = build_partition(self.tree, eta)
         self.L = self.tree.L
         self.P = self.points[self.tree.perm]          # tree-ordered points
+        perm = self.tree.perm
+        self.sc = None if scale is None else np.asarray(scale, dtype=np.float64)[perm]
+        self.dg = None if diag is None else np.asarray(diag, dtype=np.float64)[perm]
         floor = cheb.width_floor(self.tree)
         self.c, self.h = [], []
         for d in range(self.L + 1):
@@ -65,12 +76,16 @@ class H2:
     def rows(self, d, j):
         return self.tree.rows(d, j)
 
+    def _basis_at(self, d, j, rows) -> np.ndarray:
+        U = cheb.tensor_eval(self.P[rows], self.c[d][j], self.h[d][j], self.m)
+        return U if self.sc is None else self.sc[rows, None] * U
+
     def basis(self, d, j) -> np.ndarray:
-        """Direct cluster basis U_s (n_s x r) of cluster j at depth d."""
+        """Direct cluster basis U_s (n_s x r) of cluster j at depth d (rows
+        scaled by s in the scaled form)."""
         key = (d, j)
         if key not in self._U:
-            X = self.P[self.rows(d, j)]
-            self._U[key] = cheb.tensor_eval(X, self.c[d][j], self.h[d][j], self.m)
+            self._U[key] = self._basis_at(d, j, self.rows(d, j))
         return self._U[key]
 
     def nodes(self, d, j) -> np.ndarray:
@@ -86,12 +101,19 @@ class H2:
                              self.c[d - 1][p], self.h[d - 1][p], self.m)
 
     def near_block(self, s, t) -> np.ndarray:
-        """Close leaf block K[I_s, I_t] (shift on the diagonal when s == t)."""
-        Xs = self.P[self.rows(self.L, s)]
+        """Close leaf block K[I_s, I_t] (shift, or d, on the diagonal when
+        s == t; rows and columns scaled by s in the scaled form)."""
+        rs, rt = self.rows(self.L, s), self.rows(self.L, t)
+        Xs = self.P[rs]
         if s == t:
-            return kernel_matrix(self.kern, Xs, self.shift)
-        Xt = self.P[self.rows(self.L, t)]
-        return kernel_matrix(self.kern, Xs, self.shift, Xt)
+            K = kernel_matrix(self.kern, Xs, 0.0 if self.dg is not None else self.shift)
+        else:
+            K = kernel_matrix(self.kern, Xs, self.shift, self.P[rt])
+        if self.sc is not None:
+            K = self.sc[rs, None] * K * self.sc[None, rt]
+        if s == t and self.dg is not None:
+            K[np.diag_indices_from(K)] += self.dg[rs]
+        return K
 
     # ---- products -----------------------------------------------------
     def matvec_tree(self, xt: np.ndarray) -> np.ndarray:
@@ -146,12 +168,11 @@ class H2:
             lo, hi = np.searchsorted(far[:, 0], [anc, anc + 1])
             if hi == lo:
                 continue
-            Xa = self.P[lr]
-            Ua = cheb.tensor_eval(Xa, self.c[d][anc], self.h[d][anc], self.m)
+            Ua = self._basis_at(d, anc, lr)
             acc = np.zeros(self.r)
             for s, t in far[lo:hi]:
                 tr = self.rows(d, t)
-                Ut = cheb.tensor_eval(self.P[tr], self.c[d][t], self.h[d][t], self.m)
+                Ut = self._basis_at(d, t, tr)
                 acc += self.coupling(d, s, t) @ (Ut.T @ xt[tr])
             y += Ua @ acc
         return y
@@ -177,5 +198,18 @@ class H2:
         return A
 
     def kernel_dense(self) -> np.ndarray:
-        """The exact kernel matrix K in user order (small N only)."""
-        return kernel_matrix(self.kern, self.points, self.shift)
+        """The exact kernel matrix K in user order (small N only), in the
+        scaled form diag(s) K diag(s) + diag(d) when given."""
+        if self.sc is None and self.dg is None:
+            return kernel_matrix(self.kern, self.points, self.shift)
+        perm = self.tree.perm
+        s = np.ones(self.n) if self.sc is None else np.empty(self.n)
+        if self.sc is not None:
+            s[perm] = self.sc
+        K = kernel_matrix(self.kern, self.points, 0.0 if self.dg is not None else self.shift)
+        K = s[:, None] * K * s[None, :]
+        if self.dg is not None:
+            d = np.empty(self.n)
+            d[perm] = self.dg
+            K[np.diag_indices_from(K)] += d
+        return K

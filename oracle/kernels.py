@@ -9,6 +9,9 @@ Readings:
   dispersion sigma equals 2 l^2.
 * Matern-3/2: k(r) = (1 + sqrt(3) r / l) exp(-sqrt(3) r / l).
 * Exponential: k(r) = exp(-r / l) (the paper's sigma is l).
+* Laplace single layer (Section 4.3): k(r) = 1 / (4 pi r) off the diagonal;
+  its value at r = 0 is set to 0 here, because the boundary-element matrix
+  replaces the singular self term by its own regularised diagonal.
 
 Derivative kernels (for the gradient of b^T A^{-1} b; no shift): a kind
 "<base>/dl" is the radial profile dk/dl (derivative in the length scale at
@@ -29,7 +32,7 @@ from __future__ import annotations
 
 import numpy as np
 
-KINDS = ("exp", "gauss", "matern32")
+KINDS = ("exp", "gauss", "matern32")            # smooth kernels with k(0) = 1; also "laplace"
 
 
 def distances(X: np.ndarray, Y: np.ndarray) -> np.ndarray:
@@ -51,6 +54,12 @@ def radial(kind: str, length_scale: float):
     if kind == "matern32":
         a = np.sqrt(3.0) / ell
         return lambda r: (1.0 + a * r) * np.exp(-a * r)
+    if kind == "laplace":
+        def g(r):
+            r = np.asarray(r, dtype=np.float64)
+            safe = np.where(r > 0.0, r, 1.0)
+            return np.where(r > 0.0, 1.0 / (4.0 * np.pi * safe), 0.0)
+        return g
     raise ValueError(f"unknown kernel kind {kind!r}")
 
 

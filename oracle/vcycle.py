@@ -167,3 +167,28 @@ def solve_user(h2, H, b_user: np.ndarray, **kw) -> SolveResult:
     x = np.empty_like(res.x)
     x[perm] = res.x
     return dataclasses.replace(res, x=x)
+
+
+def smoothing_error_components(H, x_true: np.ndarray, n_f: int = 1, n_c: int = 40,
+                               cycles: int = 2, smoother="cg"):
+    """The error analysis of the experiments (tree order): with b = A x_true
+    and x_0 = 0, the error e = x_k + e~_1 - x_true right after the first
+    fine-level smoothing of cycle k+1, split into its part in the range of
+    U_1 (the restricted error U_1^T e) and its part in the complement,
+    ||Q_1^T e|| = sqrt(||e||^2 - ||U_1^T e||^2) for orthonormal [U_1 Q_1].
+    Returns one (U_1^T e, ||Q_1^T e||) pair per cycle."""
+    A, P = H.ops[0], H.prolong[0]
+    precs = smoothers(H, smoother)
+    factor = coarsest_factor(H.ops[-1])
+    b = A @ x_true
+    x = np.zeros_like(b)
+    out = []
+    for _ in range(cycles):
+        r = b - A @ x
+        e1 = cg(A.__matmul__, r, None, n_f) if precs is None else pcg(A.__matmul__, precs[0], r, None, n_f)
+        err = x + e1 - x_true
+        ue = P.T @ err
+        qn = float(np.sqrt(max(float(err @ err) - float(ue @ ue), 0.0)))
+        out.append((ue, qn))
+        x = vcycle(H, x, b, n_f, n_c, factor, precs=precs)
+    return out

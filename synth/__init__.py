@@ -19,7 +19,7 @@ import numpy as np
 
 __all__ = [
     "uniform_points", "gaussian_mixture_points", "tensor_grid_points",
-    "normal_vector", "Workload", "WORKLOADS", "workload",
+    "normal_vector", "bumpy_torus_mesh", "Workload", "WORKLOADS", "workload",
 ]
 
 
@@ -52,6 +52,40 @@ def tensor_grid_points(n: int, dim: int = 2) -> np.ndarray:
     g = (np.arange(side, dtype=np.float64) + 0.5) / side
     mesh = np.meshgrid(*([g] * dim), indexing="ij")
     return np.stack([m.reshape(-1) for m in mesh], axis=1)
+
+
+def bumpy_torus_mesh(n_major: int, n_minor: int, bumps: int = 40, amplitude: float = 0.05,
+                     width: float = 0.1, major: float = 1.0, minor: float = 0.35,
+                     seed: int = 0):
+    """Closed triangulated surface: a torus (major radius `major`, tube radius
+    `minor`) whose tube radius carries `bumps` Gaussian bumps of height
+    `amplitude` and width `width` (measured along the surface) at seeded
+    random positions.  Parameter grid n_major x n_minor, each cell split
+    into two triangles, so there are 2 * n_major * n_minor triangles.
+    Returns (vertices (nv, 3) float64, triangles (nt, 3) int64), triangles
+    oriented outwards."""
+    rng = np.random.default_rng(seed)
+    th_c = 2 * np.pi * rng.random(bumps)
+    ph_c = 2 * np.pi * rng.random(bumps)
+    th = 2 * np.pi * np.arange(n_major) / n_major
+    ph = 2 * np.pi * np.arange(n_minor) / n_minor
+    T, F = np.meshgrid(th, ph, indexing="ij")
+    rad = np.full(T.shape, float(minor))
+    for k in range(bumps):
+        dth = np.angle(np.exp(1j * (T - th_c[k]))) * major
+        dph = np.angle(np.exp(1j * (F - ph_c[k]))) * minor
+        rad += amplitude * np.exp(-(dth ** 2 + dph ** 2) / (2 * width ** 2))
+    ring = major + rad * np.cos(F)
+    V = np.stack([ring * np.cos(T), ring * np.sin(T), rad * np.sin(F)], axis=-1).reshape(-1, 3)
+    i = np.arange(n_major)[:, None]
+    j = np.arange(n_minor)[None, :]
+    a = i * n_minor + j
+    b = ((i + 1) % n_major) * n_minor + j
+    c = ((i + 1) % n_major) * n_minor + (j + 1) % n_minor
+    d = i * n_minor + (j + 1) % n_minor
+    tris = np.concatenate([np.stack([a, b, c], -1).reshape(-1, 3),
+                           np.stack([a, c, d], -1).reshape(-1, 3)])
+    return V, tris.astype(np.int64)
 
 
 def normal_vector(n: int, seed: int = 1, nrhs: int = 1) -> np.ndarray:

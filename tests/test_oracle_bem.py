@@ -1,0 +1,151 @@
+"""Pins of the oracle's boundary-element matrix (oracle/bem.py) and of the
+scaled form of its H2 construction.
+
+Independent references: closed forms for an equilateral triangle, the exact
+area of a flat square, the single-layer potential of a uniform density on a
+sphere (u = radius on the surface), the symmetric form as a similarity
+transform of the paper's matrix, and exactness of the H2 construction for a
+polynomial kernel in the scaled form.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle.bem import (collocation_matrix, panels, point_source_rhs, self_integral,
+                        symmetric_scaling)
+from oracle.h2 import H2
+from oracle.kernels import kernel_matrix, make_kernel, polynomial_kernel
+
+
+def _sphere(n_theta=40, n_phi=80, radius=1.0):
+    """Latitude-longitude triangulation of a sphere (poles as single vertices)."""
+    th = np.pi * np.arange(1, n_theta) / n_theta
+    ph = 2 * np.pi * np.arange(n_phi) / n_phi
+    T, F = np.meshgrid(th, ph, indexing="ij")
+    V = radius * np.stack([np.sin(T) * np.cos(F), np.sin(T) * np.sin(F), np.cos(T)], -1).reshape(-1, 3)
+    V = np.vstack([V, [[0, 0, radius]], [[0, 0, -radius]]])
+    top, bot = len(V) - 2, len(V) - 1
+    tris = []
+    for i in range(n_theta - 2):
+        for j in range(n_phi):
+            a, b = i * n_phi + j, i * n_phi + (j + 1) % n_phi
+            c, d = (i + 1) * n_phi + (j + 1) % n_phi, (i + 1) * n_phi + j
+            tris += [[a, b, c], [a, c, d]]
+    for j in range(n_phi):
+        tris.append([top, (j + 1) % n_phi, j])
+        k = (n_theta - 2) * n_phi
+        tris.append([bot, k + j, k + (j + 1) % n_phi])
+    return V, np.array(tris)
+
+
+def test_panels_equilateral_and_flat_square():
+    a = 0.3
+    V = np.array([[0, 0, 0], [a, 0, 0], [a / 2, a * np.sqrt(3) / 2, 0]])
+    y, w, R = panels(V, np.array([[0, 1, 2]]))
+    assert w[0] == pytest.approx(np.sqrt(3) / 4 * a * a, rel=1e-14)
+    assert R[0] == pytest.approx(a / np.sqrt(3), rel=1e-14)
+    np.testing.assert_allclose(y[0], [a / 2, a * np.sqrt(3) / 6, 0], atol=1e-15)
+    g = np.linspace(0, 2, 11)
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    Vs = np.stack([X.ravel(), Y.ravel(), np.zeros(X.size)], -1)
+    idx = np.arange(121).reshape(11, 11)
+    Ts = np.concatenate([np.stack([idx[:-1, :-1], idx[1:, :-1], idx[1:, 1:]], -1).reshape(-1, 3),
+                         np.stack([idx[:-1, :-1], idx[1:, 1:], idx[:-1, 1:]], -1).reshape(-1, 3)])
+    assert panels(Vs, Ts)[1].sum() == pytest.approx(4.0, rel=1e-13)
+
+
+def _polar_self_integral(V, T, nth=20000):
+    """Integral of 1/r over a flat triangle around its centroid in polar
+    coordinates: the integral over the angle of the distance to the boundary
+    along that ray (midpoint rule in the angle)."""
+    out = []
+    for tri in T:
+        a, b, c = V[tri]
+        y = (a + b + c) / 3
+        e1 = (b - a) / np.linalg.norm(b - a)
+        nrm = np.cross(b - a, c - a)
+        e2 = np.cross(nrm / np.linalg.norm(nrm), e1)
+        pts = [np.array([(p - y) @ e1, (p - y) @ e2]) for p in (a, b, c)]
+        th = 2 * np.pi * (np.arange(nth) + 0.5) / nth
+        d = np.stack([np.cos(th), np.sin(th)], 1)
+        rho = np.full(nth, np.inf)
+        for p, q in ((pts[0], pts[1]), (pts[1], pts[2]), (pts[2], pts[0])):
+            e = q - p
+            den = d[:, 0] * (-e[1]) + d[:, 1] * e[0]
+            with np.errstate(divide="ignore", invalid="ignore"):
+                t = (p[0] * (-e[1]) + p[1] * e[0]) / den
+                u = (d[:, 0] * p[1] - d[:, 1] * p[0]) / den
+            ok = (t > 0) & (u >= -1e-12) & (u <= 1 + 1e-12)
+            rho = np.where(ok, np.minimum(rho, t), rho)
+        out.append(rho.sum() * 2 * np.pi / nth)
+    return np.array(out)
+
+
+def test_self_integral_closed_form_matches_polar_integration():
+    V, T = synth.bumpy_torus_mesh(12, 6, bumps=4, seed=1)
+    Tsub = T[::7]
+    np.testing.assert_allclose(self_integral(V, Tsub), _polar_self_integral(V, Tsub), rtol=1e-6)
+    a = 0.3
+    Ve = np.array([[0, 0, 0], [a, 0, 0], [a / 2, a * np.sqrt(3) / 2, 0]])
+    # equilateral: 3 edges at distance a/(2 sqrt 3), ends at +-a/2
+    h = a / (2 * np.sqrt(3))
+    r = np.hypot(a / 2, h)
+    assert self_integral(Ve, np.array([[0, 1, 2]]))[0] == pytest.approx(
+        3 * h * np.log((a / 2 + r) / (-a / 2 + r)), rel=1e-13)
+
+
+def test_the_regularised_diagonal_is_indefinite_the_analytic_one_is_not():
+    V, T = synth.bumpy_torus_mesh(24, 12, seed=0)
+    for term, positive in (("paper", False), ("analytic", True)):
+        y, s, d = symmetric_scaling(V, T, term)
+        A = collocation_matrix(V, T, term)
+        S = (s[:, None] * A) / s[None, :]
+        lam = np.linalg.eigvalsh(0.5 * (S + S.T))[0]
+        assert (lam > 0) == positive, (term, lam)
+
+
+def test_uniform_density_on_a_sphere_gives_the_radius():
+    """For a sphere of radius rho, integral of 1/(4 pi |x - y|) over the
+    surface is rho at every surface point: A 1 must approach rho."""
+    rho = 0.7
+    V, T = _sphere(radius=rho)
+    u = collocation_matrix(V, T) @ np.ones(len(T))
+    assert np.abs(u / rho - 1).max() < 0.03
+    assert abs(np.median(u) / rho - 1) < 0.01
+
+
+def test_symmetric_form_is_a_similarity_of_the_collocation_matrix():
+    V, T = synth.bumpy_torus_mesh(24, 12, bumps=5, seed=3)
+    A = collocation_matrix(V, T)
+    y, s, d = symmetric_scaling(V, T)
+    S = s[:, None] * kernel_matrix(make_kernel("laplace", 1.0), y, 0.0) * s[None, :]
+    S[np.diag_indices_from(S)] += d
+    np.testing.assert_allclose(S, (s[:, None] * A) / s[None, :], rtol=1e-13)
+    np.testing.assert_allclose(S, S.T, rtol=1e-14)
+    assert np.linalg.eigvalsh(S)[0] > 0
+    f = point_source_rhs(y, [0.0, 0.0, 2.0])
+    sigma = np.linalg.solve(A, f)
+    ys = np.linalg.solve(S, s * f)
+    np.testing.assert_allclose(ys / s, sigma, rtol=1e-10)
+
+
+def test_scaled_h2_is_exact_for_a_polynomial_kernel_and_matches_dense():
+    """The scaled form diag(s) K diag(s) + diag(d): with a polynomial kernel
+    of degree m-1 the H2 approximation is exact; with the Laplace kernel and
+    no far blocks the blockwise product equals the dense scaled matrix."""
+    P = synth.uniform_points(500, 3, 4)
+    s = 0.5 + synth.uniform_points(500, 1, 5)[:, 0]
+    d = 1.0 + synth.uniform_points(500, 1, 6)[:, 0]
+    h = H2(P, polynomial_kernel(3), 0.0, 20, 0.7, 4, scale=s, diag=d)
+    assert sum(len(f) for f in h.part.far) > 0
+    x = synth.normal_vector(500, 7)
+    K = s[:, None] * kernel_matrix(polynomial_kernel(3), P, 0.0) * s[None, :] + np.diag(d)
+    np.testing.assert_allclose(h.matvec(x), K @ x, rtol=1e-9, atol=1e-9 * np.abs(K @ x).max())
+    V, T = synth.bumpy_torus_mesh(16, 8, bumps=3, seed=2)
+    y, s2, d2 = symmetric_scaling(V, T)
+    hb = H2(y, "laplace", 0.0, 16, 1e-9, 3, 1.0, scale=s2, diag=d2)
+    assert sum(len(f) for f in hb.part.far) == 0
+    A = collocation_matrix(V, T)
+    S = (s2[:, None] * A) / s2[None, :]
+    z = synth.normal_vector(len(T), 8)
+    np.testing.assert_allclose(hb.matvec(z), S @ z, rtol=1e-12, atol=1e-14)

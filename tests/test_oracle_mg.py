@@ -310,3 +310,18 @@ def test_plain_cg_solve_distinct_eigenvalues_and_scipy():
     x, it, ok, _ = cg_solve(A.__matmul__, b, rtol=1e-12, max_iter=5,
                             precond=block_jacobi(A, [0, 40]))
     assert ok and it == 1
+
+
+def test_smoothing_error_components_split_the_error(small):
+    """The two parts are the orthogonal split of the error: with no smoothing
+    step the error is -x_true, so U_1^T e = -U_1^T x_true and the parts'
+    squares add up to ||x_true||^2; with smoothing the total drops."""
+    from oracle.vcycle import smoothing_error_components
+    h, H = small
+    xt = synth.normal_vector(h.n, 31)
+    (ue, qn), = smoothing_error_components(H, xt, n_f=0, n_c=3, cycles=1)
+    np.testing.assert_allclose(ue, -H.prolong[0].T @ xt, rtol=1e-13, atol=1e-13)
+    assert ue @ ue + qn ** 2 == pytest.approx(xt @ xt, rel=1e-12)
+    comps = smoothing_error_components(H, xt, n_f=1, n_c=10, cycles=2)
+    tot = [float(np.sqrt(u @ u + q * q)) for u, q in comps]
+    assert tot[0] < np.linalg.norm(xt) and tot[1] < tot[0]
