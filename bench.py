@@ -55,6 +55,10 @@ def parse():
                          "the Rayleigh quotient of the final iterate")
     ap.add_argument("--growth", default="",
                     help="comma-separated N: iterations to 1e-8 of H2-MG and of plain CG against N")
+    ap.add_argument("--sweep", default="",
+                    help="comma-separated smoother:precision:n_f:n_c items on the shift-1 2^20 problem")
+    ap.add_argument("--error-components", action="store_true",
+                    help="the error analysis of the experiments (1D Gaussian, N = 1024)")
     ap.add_argument("--spd-probe-oracle", action="store_true",
                     help="also evaluate the Rayleigh quotient with the CPU oracle's matvec")
     ap.add_argument("--n", type=int, default=0, help="override the number of points")
@@ -367,6 +371,59 @@ def differentiation(args, torch, synth, H2Matrix):
     return out
 
 
+def smoothing_sweep(args, torch, synth, H2Matrix):
+    """Time-to-1e-8 against the smoothing counts (n_f, n_c) on the shift-1
+    Matern problem at 2^20: each item smoother:precision:n_f:n_c."""
+    w = synth.workload("matern3d_1m_spd")
+    pts = torch.from_numpy(w.make_points()).cuda()
+    b = torch.from_numpy(w.make_rhs()).cuda()
+    g = H2Matrix(pts, w.kernel, w.length_scale, w.shift, w.leaf, w.eta, w.cheb_m)
+    g.setup(("fp64", "fp32"))
+    for item in args.sweep.split(","):
+        smoother, prec, nf, nc = item.split(":")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = g.solve(b, rtol=1e-8, precision=prec, smoother=smoother, n_fine=int(nf),
+                          n_coarse=int(nc), raise_on_error=False, max_cycles=300)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out = {"sweep": w.name, "smoother": smoother, "precision": prec, "n_f": int(nf),
+               "n_c": int(nc), "cycles": info["cycles"], "time_s": round(dt, 3),
+               "status": info["status"], "rel_residual": info["rel_residual"]}
+        print(json.dumps(out), flush=True)
+        log(f"sweep {item}: {info['cycles']} cycles, {dt:.2f} s, {info['status']}")
+    g.close()
+
+
+def error_components(args, torch, synth, H2Matrix):
+    """The error analysis of the experiments: 1D Gaussian kernel, N = 1024
+    equally spaced points, sigma = 2 l^2 = 0.01, c = 1e-3; b = A x_true,
+    x_0 = 0; after the first fine-level smoothing of cycles 1 and 2, the
+    error split into U_1^T e (what restriction carries to the coarse levels)
+    and its complement Q_1^T e.  Norms on the host from the library's
+    smoother, level products, restriction and V-cycle."""
+    import math
+    pts = torch.from_numpy(synth.tensor_grid_points(1024, 1)).cuda()
+    x_true = torch.from_numpy(synth.normal_vector(1024, 3)).cuda()
+    for leaf, m in ((32, 8), (16, 6)):
+        g = H2Matrix(pts, "gauss", math.sqrt(0.01 / 2), 1e-3, leaf, 0.7, m)
+        b = g.matvec(x_true)
+        x = torch.zeros_like(b)
+        rows = []
+        for _ in range(2):
+            r = b - g.matvec(x)
+            err = x + g.smooth(1, r, 1) - x_true
+            ue = g.restrict(1, err)
+            ue2 = float((ue @ ue).item())
+            qn = math.sqrt(max(float((err @ err).item()) - ue2, 0.0))
+            rows.append({"U1T_e_norm": math.sqrt(ue2), "U1T_e_max": float(ue.abs().max().item()),
+                         "Q1T_e_norm": qn})
+            x = g.vcycle(x, b)
+        print(json.dumps({"error_components": "gauss1d_1024", "leaf": leaf, "m": m, "levels": g.levels,
+                          "after_first_smoothing": rows}), flush=True)
+        g.close()
+
+
 def part_a(args, torch, synth, H2Matrix):
     """The exact headline workload: build, setup, matvec and a few cycles."""
     w = synth.workload(args.headline)
@@ -465,6 +522,12 @@ def main():
         return
     if args.growth:
         growth_scan(args, torch, synth, H2Matrix)
+        return
+    if args.sweep:
+        smoothing_sweep(args, torch, synth, H2Matrix)
+        return
+    if args.error_components:
+        error_components(args, torch, synth, H2Matrix)
         return
     c1 = None if args.no_c1 else c1_latency(args, torch, synth, H2Matrix)
     diff = None if args.no_diff else differentiation(args, torch, synth, H2Matrix)
