@@ -71,6 +71,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-c1", action="store_true", help="skip the small-configuration latency run")
     ap.add_argument("--no-diff", action="store_true", help="skip the gradient run")
+    ap.add_argument("--no-bem", action="store_true", help="skip the boundary-element run")
+    ap.add_argument("--bem-grid", type=int, nargs=2, default=[1000, 500],
+                    help="torus parameter grid (panels = 2 * a * b)")
     ap.add_argument("--cpu-leaves", type=int, default=48)
     ap.add_argument("--json-out", default="")
     return ap.parse_args()
@@ -408,20 +411,72 @@ def error_components(args, torch, synth, H2Matrix):
     for leaf, m in ((32, 8), (16, 6)):
         g = H2Matrix(pts, "gauss", math.sqrt(0.01 / 2), 1e-3, leaf, 0.7, m)
         b = g.matvec(x_true)
-        x = torch.zeros_like(b)
-        rows = []
-        for _ in range(2):
-            r = b - g.matvec(x)
-            err = x + g.smooth(1, r, 1) - x_true
-            ue = g.restrict(1, err)
-            ue2 = float((ue @ ue).item())
-            qn = math.sqrt(max(float((err @ err).item()) - ue2, 0.0))
-            rows.append({"U1T_e_norm": math.sqrt(ue2), "U1T_e_max": float(ue.abs().max().item()),
-                         "Q1T_e_norm": qn})
-            x = g.vcycle(x, b)
-        print(json.dumps({"error_components": "gauss1d_1024", "leaf": leaf, "m": m, "levels": g.levels,
-                          "after_first_smoothing": rows}), flush=True)
+        for nc in (2, 40):
+            x = torch.zeros_like(b)
+            rows = []
+            for _ in range(3):
+                r = b - g.matvec(x)
+                err = x + g.smooth(1, r, 1) - x_true
+                ue = g.restrict(1, err)
+                ue2 = float((ue @ ue).item())
+                qn = math.sqrt(max(float((err @ err).item()) - ue2, 0.0))
+                rows.append({"U1T_e_norm": math.sqrt(ue2), "U1T_e_max": float(ue.abs().max().item()),
+                             "Q1T_e_norm": qn})
+                x = g.vcycle(x, b, n_coarse=nc)
+            print(json.dumps({"error_components": "gauss1d_1024", "leaf": leaf, "m": m, "n_c": nc,
+                              "levels": g.levels, "after_first_smoothing": rows}), flush=True)
         g.close()
+
+
+def boundary_elements(args, torch, synth, H2Matrix):
+    """Laplace single layer on the bumpy torus (Section 4.3's problem, the
+    symmetric scaled form): panels, H2 build (1/(4 pi r), leaf 128, rank 64),
+    hierarchy, FP64 and FP32-refinement solves with the block smoother for
+    the point-source right-hand side, and the matvec."""
+    from paper_2501_17656_amd import bem_density, bem_panels, bem_point_source_rhs
+    nmaj, nmin = args.bem_grid
+    V, T = synth.bumpy_torus_mesh(nmaj, nmin)
+    Vd = torch.from_numpy(V).cuda()
+    Td = torch.from_numpy(T).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    y, sc, dg = bem_panels(Vd, Td)
+    g = H2Matrix(y, "laplace", 1.0, 0.0, 128, 0.7, 4, scale=sc, diag=dg)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g.setup(("fp64", "fp32"))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    f = bem_point_source_rhs(y, sc, (0.0, 0.0, 1.5))
+    out = {"workload": f"bumpy torus (R 1, r 0.35, 40 bumps of 0.05), {len(T)} panels, Laplace single "
+                       f"layer 1/(4 pi r), closed-form self term, symmetric scaled form, leaf 128, "
+                       f"eta 0.7, rank 64, point source at (0, 0, 1.5), rtol 1e-8, block smoother",
+           "panels_and_build_s": round(t1 - t0, 3), "setup_s": round(t2 - t1, 3),
+           "levels": g.levels, "device_memory_gb": round(g.memory_bytes() / 1e9, 1)}
+    x = torch.empty_like(f)
+    g.matvec(f, out=x)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    for _ in range(3):
+        g.matvec(f, out=x)
+    torch.cuda.synchronize()
+    out["matvec_ms"] = round((time.perf_counter() - t3) / 3 * 1e3, 3)
+    for prec in ("fp64", "fp32"):
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        sol, info = g.solve(f, rtol=1e-8, precision=prec, smoother="bj", raise_on_error=False)
+        torch.cuda.synchronize()
+        out[prec] = {"time_to_1e-8_s": round(time.perf_counter() - t4, 3), "cycles": info["cycles"],
+                     "status": info["status"], "rel_residual": info["rel_residual"]}
+        if info["converged"]:
+            sigma = bem_density(sol, sc)
+            out[prec]["density_norm"] = float(sigma.norm())
+        log(f"boundary elements {len(T)} panels {prec}: {out[prec]['time_to_1e-8_s']} s, "
+            f"{info['cycles']} cycles, {info['status']}")
+    if out["fp64"]["status"] == "OK" and out["fp32"]["status"] == "OK":
+        out["speedup_mixed_vs_fp64"] = round(out["fp64"]["time_to_1e-8_s"] / out["fp32"]["time_to_1e-8_s"], 3)
+    g.close()
+    return out
 
 
 def part_a(args, torch, synth, H2Matrix):
@@ -531,6 +586,7 @@ def main():
         return
     c1 = None if args.no_c1 else c1_latency(args, torch, synth, H2Matrix)
     diff = None if args.no_diff else differentiation(args, torch, synth, H2Matrix)
+    bem = None if args.no_bem else boundary_elements(args, torch, synth, H2Matrix)
     headline = part_a(args, torch, synth, H2Matrix) if args.headline else None
     if headline:
         log(f"part A: build {headline['build_s']} s, matvec {headline['matvec_ms']} ms, "
@@ -661,6 +717,7 @@ def main():
         "paper_cg_smoother": cg_runs,
         "c1_small_config": c1,
         "differentiation": diff,
+        "boundary_elements": bem,
         "headline_shift_1e-3": headline,
     }
     if not args.no_cpu:

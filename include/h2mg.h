@@ -62,7 +62,9 @@ typedef enum h2mg_status {
 typedef enum h2mg_kernel_kind {
   H2MG_KERNEL_EXP = 0,
   H2MG_KERNEL_GAUSS = 1,
-  H2MG_KERNEL_MATERN32 = 2
+  H2MG_KERNEL_MATERN32 = 2,
+  H2MG_KERNEL_LAPLACE = 3      /* 1 / (4 pi r), 0 at r = 0 (Section 4.3); no
+                                  length scale; use with a per-point diagonal */
 } h2mg_kernel_kind;
 
 /* Derivative kernels, for the gradient of L = b^T A^{-1} b (not in the
@@ -202,6 +204,43 @@ h2mg_status h2mg_build(const double* points_dev, int64_t n, int32_t dim,
                        const h2mg_kernel* kernel, const h2mg_build_opts* opts,
                        hipStream_t stream, h2mg_h2_t* out);
 
+/* As h2mg_build, for the scaled form diag(s) K diag(s) + diag(d): scale_dev
+ * (s > 0) and diag_dev (d, replacing the kernel's constant shift) are
+ * device arrays of n doubles in user order, either may be null (s = 1,
+ * d = shift).  s multiplies the rows of the leaf bases before their
+ * orthonormalisation, so the restricted operators of the hierarchy are those
+ * of the scaled matrix.  This is the symmetric W^(1/2) G W^(1/2) form of the
+ * boundary-element matrix of Section 4.3 (see h2mg_bem_panels).  Errors as
+ * h2mg_build, plus INVALID_ARG for s <= 0 or a non-finite s or d. */
+h2mg_status h2mg_build_scaled(const double* points_dev, int64_t n, int32_t dim,
+                              const h2mg_kernel* kernel, const h2mg_build_opts* opts,
+                              const double* scale_dev, const double* diag_dev,
+                              hipStream_t stream, h2mg_h2_t* out);
+
+/* Boundary elements of the Laplace single layer (Section 4.3), for a flat
+ * triangle mesh: vertices_dev (nv x 3 doubles), triangles_dev (nt x 3
+ * int64 vertex indices), both device.  Writes, per triangle i, the centroid
+ * (collocation point) to centroids_dev (nt x 3), s_i = sqrt(area_i) to
+ * scale_dev and the diagonal entry d_i = I_i / (4 pi) to diag_dev, where I_i
+ * is the integral of 1/|y_i - y| over the triangle (closed form).  The
+ * paper's regularised entry area_i / (4 pi R_i) is not used: it leaves the
+ * matrix indefinite on curved surfaces.  With these, h2mg_build_scaled
+ * with H2MG_KERNEL_LAPLACE builds S = W^(1/2) G W^(1/2), and the density
+ * of the paper's system A sigma = f is sigma = W^(-1/2) y for S y =
+ * W^(1/2) f.  Indices are not checked beyond nt > 0 and nv > 0. */
+h2mg_status h2mg_bem_panels(const double* vertices_dev, int64_t nv, const int64_t* triangles_dev,
+                            int64_t nt, double* centroids_dev, double* scale_dev,
+                            double* diag_dev, hipStream_t stream);
+/* rhs_dev[i] = s_i / (4 pi |y_i - x0|): W^(1/2) f for the point source x0
+ * (3 host doubles) of Section 4.3; centroids and scale from h2mg_bem_panels. */
+h2mg_status h2mg_bem_point_source_rhs(const double* centroids_dev, const double* scale_dev,
+                                      int64_t n, const double* x0_host, double* rhs_dev,
+                                      hipStream_t stream);
+/* sigma_dev[i] = y_dev[i] / s_i: the density of the paper's system from the
+ * solution of the symmetric one. */
+h2mg_status h2mg_bem_density(const double* y_dev, const double* scale_dev, int64_t n,
+                             double* sigma_dev, hipStream_t stream);
+
 /* y = A_H2 x (Section 3.1 matvec: upsweep x_i = V_i x_{i-1}, couplings,
  * downsweep y_{i-1} = D_i x_{i-1} + U_i y_i, near field y = D x + U_1 y_1).
  * x_dev, y_dev: device, length n, user order; they must not overlap. */
@@ -272,6 +311,16 @@ h2mg_status h2mg_restrict(h2mg_h2_t h, int32_t level, const double* r_dev,
                           double* r_next_dev, hipStream_t stream);
 h2mg_status h2mg_prolong(h2mg_h2_t h, int32_t level, const double* e_next_dev,
                          double* e_dev, hipStream_t stream);
+
+/* The smoother alone, e = Iter(A_k, r, e0) of Algorithm 1 (Section 3.3):
+ * nsteps of CG (smoother 0) or block-Jacobi PCG (smoother 1) on level
+ * `level` in FP64, from e0 = e_dev on entry when use_e0 != 0, else from 0.
+ * Level 1 vectors in user order (length n), coarser levels in coefficient
+ * order (h2mg_level_size).  Runs h2mg_setup_mg itself when needed.  Errors:
+ * INVALID_ARG (null, level out of range, bad smoother, the block smoother on
+ * the coarsest level), NOT_SPD, OOM, HIP. */
+h2mg_status h2mg_smooth(h2mg_h2_t h, int32_t level, const double* r_dev, double* e_dev,
+                        int32_t nsteps, int32_t smoother, int32_t use_e0, hipStream_t stream);
 
 /* One V-cycle of Algorithm 1 in FP64: x_out = x0 + e_1 for A_H2 x = b
  * (a W- or F-cycle when opts->method says so; H2MG_METHOD_CG is

@@ -153,6 +153,49 @@ h2mg_status h2mg_build(const double* points_dev, int64_t n, int32_t dim, const h
   });
 }
 
+h2mg_status h2mg_build_scaled(const double* points_dev, int64_t n, int32_t dim,
+                              const h2mg_kernel* kernel, const h2mg_build_opts* opts,
+                              const double* scale_dev, const double* diag_dev, hipStream_t stream,
+                              h2mg_h2_t* out) {
+  return guarded([&] {
+    if (!out) return fail(H2MG_ERR_INVALID_ARG, "null output handle");
+    *out = nullptr;
+    H2* h = nullptr;
+    h2mg_status st = build_h2(points_dev, n, dim, kernel, opts, stream, &h, scale_dev, diag_dev);
+    if (st != H2MG_OK) return st;
+    *out = new h2mg_h2_s{h};
+    return H2MG_OK;
+  });
+}
+
+h2mg_status h2mg_bem_panels(const double* V, int64_t nv, const int64_t* T, int64_t nt, double* y,
+                            double* s, double* d, hipStream_t stream) {
+  return guarded([&] {
+    if (!V || !T || !y || !s || !d) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    if (nv < 3 || nt < 1) return fail(H2MG_ERR_INVALID_ARG, "need at least 3 vertices and 1 triangle");
+    launch_bem_panels(stream, nt, V, T, y, s, d);
+    return check_stream_err(stream);
+  });
+}
+
+h2mg_status h2mg_bem_point_source_rhs(const double* y, const double* s, int64_t n, const double* x0,
+                                      double* f, hipStream_t stream) {
+  return guarded([&] {
+    if (!y || !s || !x0 || !f || n < 1) return fail(H2MG_ERR_INVALID_ARG, "null argument or n < 1");
+    launch_bem_rhs(stream, n, y, x0, s, f);
+    return check_stream_err(stream);
+  });
+}
+
+h2mg_status h2mg_bem_density(const double* yv, const double* s, int64_t n, double* sigma,
+                             hipStream_t stream) {
+  return guarded([&] {
+    if (!yv || !s || !sigma || n < 1) return fail(H2MG_ERR_INVALID_ARG, "null argument or n < 1");
+    launch_div(stream, n, yv, s, sigma);
+    return check_stream_err(stream);
+  });
+}
+
 h2mg_status h2mg_matvec(h2mg_h2_t hh, const double* x, double* y, hipStream_t stream) {
   return guarded([&] {
     if (!hh || !x || !y) return fail(H2MG_ERR_INVALID_ARG, "null argument");
@@ -245,6 +288,16 @@ h2mg_status h2mg_prolong(h2mg_h2_t hh, int32_t level, const double* e_next, doub
       prolong_level(h, P64, level, e_next, e, nullptr, 0.0);
     }
     return check_stream_err(stream);
+  });
+}
+
+h2mg_status h2mg_smooth(h2mg_h2_t hh, int32_t level, const double* r, double* e, int32_t nsteps,
+                        int32_t smoother, int32_t use_e0, hipStream_t stream) {
+  return guarded([&] {
+    if (!hh || !r || !e) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    if (nsteps < 0 || smoother < 0 || smoother > 1) return fail(H2MG_ERR_INVALID_ARG, "bad smoother options");
+    hh->h->stream = stream;
+    return smooth_once(*hh->h, level, r, e, nsteps, smoother, use_e0 != 0);
   });
 }
 

@@ -106,7 +106,7 @@ __device__ inline void load_subtile(const Tb* __restrict__ tile, int lane, Tacc 
 }
 
 // ---------------------------------------------------------------- kernels
-enum { KER_EXP = 0, KER_GAUSS = 1, KER_MATERN32 = 2 };
+enum { KER_EXP = 0, KER_GAUSS = 1, KER_MATERN32 = 2, KER_LAPLACE = 3 };
 // deriv: the kernel itself, its derivative in the length scale at fixed r,
 // or g(r) = k'(r) / r (0 at r = 0, where its self term cancels in the
 // coordinate gradient).
@@ -124,6 +124,10 @@ struct KernelParams {
 // for a kernel fixed at compile time.
 template <int KIND, int DERIV, typename T>
 __device__ inline T kernel_fixed(T inv_l, T inv_2l2, T r2) {
+  if constexpr (KIND == KER_LAPLACE) {
+    // 1 / (4 pi r); 0 at r = 0 (the matrix supplies its own diagonal)
+    return r2 == T(0) ? T(0) : T(0.07957747154594767) / sqrt(r2);
+  }
   if constexpr (DERIV == DER_RADIAL) {
     if (r2 == T(0)) return T(0);
   }
@@ -159,6 +163,8 @@ __host__ __device__ inline void dispatch_kernel(int kind, int deriv, F&& f) {
   };
   if (kind == KER_GAUSS) d(std::integral_constant<I, KER_GAUSS>{});
   else if (kind == KER_EXP) d(std::integral_constant<I, KER_EXP>{});
+  else if (kind == KER_LAPLACE)   // no length scale, so no derivative kernels
+    f(std::integral_constant<I, KER_LAPLACE>{}, std::integral_constant<I, DER_NONE>{});
   else d(std::integral_constant<I, KER_MATERN32>{});
 }
 
@@ -177,6 +183,23 @@ __device__ inline double kernel_r2(const KernelParams& kp, double r2) {
 
 __device__ inline float kernel_r2(const KernelParams& kp, float r2) {
   return kernel_r2_t<float>(kp.kind, kp.deriv, float(kp.inv_l), float(kp.inv_2l2), r2);
+}
+
+// Per-point scale s (on rows and columns) and diagonal d of the scaled form
+// diag(s) K diag(s) + diag(d), tree order; null pointers mean s = 1 and
+// d = the constant shift.
+struct PointScale {
+  const double* s;
+  const double* d;
+};
+
+// One entry of the scaled matrix from the kernel value k between tree
+// positions i and j (self: the same point).
+__device__ inline double scaled_entry(double k, int64_t i, int64_t j, bool self, const PointScale& ps,
+                                      double shift) {
+  if (ps.s) k *= ps.s[i] * ps.s[j];
+  if (self) k += ps.d ? ps.d[i] : shift;
+  return k;
 }
 
 // ---------------------------------------------------------------- shuffles

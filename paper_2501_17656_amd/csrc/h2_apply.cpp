@@ -50,7 +50,7 @@ void apply_fine(H2& h, int p, const void* xt, void* out, double alpha, const voi
   // near field and leaf downsweep: y = D x + Q y_L
   if (p == P64 && h.snear.ready) launch_near_stored(h, static_cast<const double*>(xt));
   else launch_near(h, p, xt);
-  launch_fine_reduce(h, p, at_depth(yall, p, h.L, r), out, false, alpha, add, beta);
+  launch_fine_reduce(h, p, at_depth(yall, p, h.L, r), out, false, alpha, add, beta, xt);
 }
 
 void apply_coarse(H2& h, int p, int k, const void* x, void* y) {

@@ -160,11 +160,14 @@ Launch make_launch(H2& h, const std::vector<const View*>& views) {
 }  // namespace
 
 h2mg_status build_h2(const double* points_dev, int64_t n, int dim, const h2mg_kernel* kernel,
-                     const h2mg_build_opts* opts, hipStream_t stream, H2** out) {
+                     const h2mg_build_opts* opts, hipStream_t stream, H2** out,
+                     const double* scale_dev, const double* diag_dev) {
   if (!points_dev || !kernel || !opts || !out) return fail(H2MG_ERR_INVALID_ARG, "null argument");
-  if (kernel->kind < 0 || kernel->kind > 2) return fail(H2MG_ERR_INVALID_ARG, "unknown kernel kind %d", kernel->kind);
+  if (kernel->kind < 0 || kernel->kind > 3) return fail(H2MG_ERR_INVALID_ARG, "unknown kernel kind %d", kernel->kind);
   if (kernel->derivative < 0 || kernel->derivative > 2)
     return fail(H2MG_ERR_INVALID_ARG, "unknown kernel derivative %d", kernel->derivative);
+  if (kernel->kind == KER_LAPLACE && kernel->derivative != 0)
+    return fail(H2MG_ERR_INVALID_ARG, "the Laplace kernel has no derivative kernels");
   if (!(kernel->length_scale > 0.0) || !std::isfinite(kernel->length_scale))
     return fail(H2MG_ERR_INVALID_ARG, "length_scale must be finite and > 0");
   if (!(kernel->shift >= 0.0) || !std::isfinite(kernel->shift))
@@ -173,11 +176,23 @@ h2mg_status build_h2(const double* points_dev, int64_t n, int dim, const h2mg_ke
   if (opts->leaf_size > 256)
     return fail(H2MG_ERR_INVALID_ARG, "leaf_size must be <= 256 (got %d)", opts->leaf_size);
 
-  std::vector<double> pts_h(size_t(n) * dim);
+  std::vector<double> pts_h(size_t(n) * dim), scale_h, diag_h;
   hipError_t e = hipMemcpyAsync(pts_h.data(), points_dev, pts_h.size() * sizeof(double),
                                 hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess && scale_dev) {
+    scale_h.resize(n);
+    e = hipMemcpyAsync(scale_h.data(), scale_dev, n * sizeof(double), hipMemcpyDeviceToHost, stream);
+  }
+  if (e == hipSuccess && diag_dev) {
+    diag_h.resize(n);
+    e = hipMemcpyAsync(diag_h.data(), diag_dev, n * sizeof(double), hipMemcpyDeviceToHost, stream);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return fail(H2MG_ERR_HIP, "copying points to the host: %s", hipGetErrorString(e));
+  for (double v : scale_h)
+    if (!(v > 0.0) || !std::isfinite(v)) return fail(H2MG_ERR_INVALID_ARG, "scale must be finite and > 0");
+  for (double v : diag_h)
+    if (!std::isfinite(v)) return fail(H2MG_ERR_INVALID_ARG, "diag must be finite");
 
   H2* hp = new (std::nothrow) H2();
   if (!hp) return fail(H2MG_ERR_OOM, "host allocation failed");
@@ -214,6 +229,13 @@ h2mg_status build_h2(const double* points_dev, int64_t n, int dim, const h2mg_ke
       for (int a = 0; a < dim; ++a) ptree[i * dim + a] = pts_h[P.perm[i] * dim + a];
     h.pts = upload(h, ptree);
     h.perm = upload(h, P.perm);
+    auto tree_order = [&](const std::vector<double>& v) {
+      std::vector<double> t(v.size());
+      for (int64_t i = 0; i < n; ++i) t[i] = v[P.perm[i]];
+      return t;
+    };
+    if (!scale_h.empty()) h.scale = upload(h, tree_order(scale_h));
+    if (!diag_h.empty()) h.diag = upload(h, tree_order(diag_h));
     std::vector<int> loff(h.nleaf + 1);
     for (int j = 0; j <= h.nleaf; ++j) loff[j] = int(P.offsets[h.L][j]);
     h.leaf_off = upload(h, loff);
@@ -372,6 +394,9 @@ h2mg_status build_h2(const double* points_dev, int64_t n, int dim, const h2mg_ke
 
 h2mg_status build_derivative(H2& h, int which, H2** out) {
   if (which != 1 && which != 2) return fail(H2MG_ERR_INVALID_ARG, "derivative must be 1 or 2 (got %d)", which);
+  if (h.kp.kind == KER_LAPLACE || h.scale || h.diag)
+    return fail(H2MG_ERR_INVALID_ARG, "derivative kernels exist for the exp, Gauss and Matern kernels "
+                                      "without per-point scale or diagonal");
   double* user = nullptr;
   try {
     user = h.arena.make<double>(size_t(h.n) * h.dim);

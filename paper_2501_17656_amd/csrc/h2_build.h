@@ -4,8 +4,11 @@
 
 namespace h2mg {
 
+// scale_dev, diag_dev: optional per-point scale and diagonal (device, user
+// order) of the scaled form diag(s) K diag(s) + diag(d).
 h2mg_status build_h2(const double* points_dev, int64_t n, int dim, const h2mg_kernel* kernel,
-                     const h2mg_build_opts* opts, hipStream_t stream, H2** out);
+                     const h2mg_build_opts* opts, hipStream_t stream, H2** out,
+                     const double* scale_dev = nullptr, const double* diag_dev = nullptr);
 h2mg_status setup_mg(H2& h, int precision_mask);
 // enable != 0: evaluate the close leaf blocks once and store them (FP64
 // tiles) for every later FP64 fine product; enable == 0: release them and
@@ -44,6 +47,10 @@ struct SolveParams {
 };
 // Solve A_H2 x = b; b, x device, user order.  Fills info.
 h2mg_status solve(H2& h, const double* b, double* x, const SolveParams& sp, h2mg_solve_info* info);
+// e = Iter(A_level, r, e0): nsteps of the smoother in FP64 (level 1 in user
+// order, coarser levels in coefficient order); e0 = e on entry when use_e0.
+h2mg_status smooth_once(H2& h, int level, const double* r, double* e, int nsteps, int smoother,
+                        bool use_e0);
 // One FP64 cycle (V, W or F by sp.method) from x0 (user order).
 h2mg_status vcycle_once(H2& h, const double* x0, const double* b, double* x_out, const SolveParams& sp);
 

@@ -141,6 +141,8 @@ struct H2 {
   double* cbox = nullptr;              // per gid: dim centres
   double* hbox = nullptr;              // per gid: dim floored half-widths
   double* nodes1d = nullptr;           // m Chebyshev nodes
+  double* scale = nullptr;             // per point s (tree order), or null: s = 1
+  double* diag = nullptr;              // per point d (tree order), or null: d = shift
   double* R = nullptr;                 // per gid r x r (setup only, freed after)
 
   // stored blocks: S of depth d in [s_first[d], s_first[d] + s_count[d]),
@@ -250,12 +252,24 @@ void launch_near_stored(H2& h, const double* xtree);
 // out = alpha * Q yhat + beta * add (tree order).
 void launch_leaf_down(H2& h, int p, const void* yhat, void* out, double alpha, const void* add,
                       double beta);
-// out[idx] = alpha * (Q yhat + near) + beta * add[idx], idx = tree position or
-// perm[tree position] when to_user.  The near part comes from the stored
+// out[idx] = alpha * (Q yhat + near + diag * xin) + beta * add[idx], idx = tree
+// position or perm[tree position] when to_user (the diag term only with a
+// per-point diagonal and the near field evaluated).  The near part comes from the stored
 // near field (snear.yc) for FP64 when it is ready, else from the on-the-fly
 // partials.
 void launch_fine_reduce(H2& h, int p, const void* yhat, void* out, bool to_user,
-                        double alpha, const void* add, double beta);
+                        double alpha, const void* add, double beta, const void* xin);
+
+// ------------------------------------------------------------ boundary elements
+// Per triangle (vertex rows V, index triples T): centroid y (nt x 3), scale
+// s = sqrt(area), diagonal d = self-potential / (4 pi).
+void launch_bem_panels(hipStream_t st, int64_t nt, const double* V, const int64_t* T, double* y,
+                       double* s, double* d);
+// f_i = s_i / (4 pi |y_i - x0|) (x0: 3 host doubles).
+void launch_bem_rhs(hipStream_t st, int64_t n, const double* y, const double* x0, const double* s,
+                    double* f);
+// out_i = x_i / s_i.
+void launch_div(hipStream_t st, int64_t n, const double* x, const double* s, double* out);
 
 // ------------------------------------------------------------ vector kernels
 void launch_gather(H2& h, const double* user, double* tree);     // tree[i] = user[perm[i]]

@@ -370,7 +370,8 @@ __global__ __launch_bounds__(256) void k_near(const int* __restrict__ tasks,
                                               const int* __restrict__ leaf_off,
                                               const double* __restrict__ pts, int dim,
                                               const Tv* __restrict__ x, Tv* __restrict__ partial,
-                                              Tv* __restrict__ colpart, int ld, KernelParams kp) {
+                                              Tv* __restrict__ colpart, int ld, KernelParams kp,
+                                              const double* __restrict__ scale) {
   constexpr int TILE = 128;
   __shared__ double ps[TILE * 3];
   __shared__ double pt[TILE * 3];
@@ -388,7 +389,8 @@ __global__ __launch_bounds__(256) void k_near(const int* __restrict__ tasks,
       const int i = idx / dim;
       ps[idx] = pts[int64_t(s0 + rt + min(i, nrow - 1)) * dim + idx % dim];
     }
-    for (int i = tid; i < TILE; i += 256) xsl[i] = i < nrow ? x[s0 + rt + i] : zero<Tv>();
+    for (int i = tid; i < TILE; i += 256)
+      xsl[i] = i < nrow ? (scale ? Tv(scale[s0 + rt + i]) * x[s0 + rt + i] : x[s0 + rt + i]) : zero<Tv>();
     __syncthreads();
     double pi[8][3];
     Tv xi[8], racc[8];
@@ -410,7 +412,9 @@ __global__ __launch_bounds__(256) void k_near(const int* __restrict__ tasks,
           const int j = idx / dim;
           pt[idx] = pts[int64_t(t0 + ct + min(j, ncol - 1)) * dim + idx % dim];
         }
-        for (int j = tid; j < TILE; j += 256) xtl[j] = j < ncol ? x[t0 + ct + j] : zero<Tv>();
+        for (int j = tid; j < TILE; j += 256)
+          xtl[j] = j < ncol ? (scale ? Tv(scale[t0 + ct + j]) * x[t0 + ct + j] : x[t0 + ct + j])
+                            : zero<Tv>();
         __syncthreads();
 #pragma unroll 2
         for (int v = 0; v < 8; ++v) {
@@ -440,6 +444,7 @@ __global__ __launch_bounds__(256) void k_near(const int* __restrict__ tasks,
 #pragma unroll
             for (int q = 0; q < 16; ++q) s += red[q][tid];
             if (tid < ncol) {
+              if (scale) s *= Tv(scale[t0 + ct + tid]);
               Tv* dst = colpart + int64_t(p) * ld + ct + tid;
               *dst = rt == 0 ? s : *dst + s;
             }
@@ -460,7 +465,8 @@ __global__ __launch_bounds__(256) void k_near(const int* __restrict__ tasks,
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int i = ti + 16 * u;
-        if (i < nrow) partial[int64_t(task) * ld + rt + i] = racc[u];
+        if (i < nrow)
+          partial[int64_t(task) * ld + rt + i] = scale ? Tv(scale[s0 + rt + i]) * racc[u] : racc[u];
       }
     }
   }
@@ -474,8 +480,9 @@ __global__ __launch_bounds__(256) void k_fine_reduce(
     const int* __restrict__ row_task_ptr, const int* __restrict__ col_ptr,
     const int* __restrict__ col_pair, const Tv* __restrict__ partial,
     const Tv* __restrict__ colpart, int ld, const Tv* __restrict__ near_y,
-    const int* __restrict__ chunk_base, const int64_t* __restrict__ perm, Tv* __restrict__ out,
-    double alpha, const Tv* __restrict__ add, double beta) {
+    const int* __restrict__ chunk_base, const double* __restrict__ dg, const Tv* __restrict__ xin,
+    const int64_t* __restrict__ perm, Tv* __restrict__ out, double alpha, const Tv* __restrict__ add,
+    double beta) {
   __shared__ Tv yh[64];
   const int leaf = blockIdx.x;
   const int s0 = leaf_off[leaf], n = leaf_off[leaf + 1] - s0;
@@ -492,6 +499,7 @@ __global__ __launch_bounds__(256) void k_fine_reduce(
     } else {
       for (int t = t0; t < t1; ++t) v += partial[int64_t(t) * ld + i];
       for (int c = c0; c < c1; ++c) v += colpart[int64_t(col_pair[c]) * ld + i];
+      if (dg) v += Tv(dg[s0 + i]) * xin[s0 + i];
     }
     const int64_t idx = perm ? perm[s0 + i] : int64_t(s0 + i);
     Tv o = Tv(alpha) * v;
@@ -686,17 +694,19 @@ void launch_near(H2& h, int p, const void* xtree) {
   int ev;
   h.time_begin(ev);
   const dim3 g(h.near.ntasks), b(256);
+  KernelParams kp = h.kp;
+  if (h.diag) kp.shift = 0.0;          // the per-point diagonal is added by k_fine_reduce
   dispatch_kernel(h.kp.kind, h.kp.deriv, [&](auto kc, auto dc) {
     constexpr int K = decltype(kc)::value, D = decltype(dc)::value;
     if (p == P64)
       hipLaunchKernelGGL((k_near<double, double, K, D>), g, b, 0, h.stream, h.near.task,
                          h.near.pair_col, h.leaf_off, h.pts, h.dim, static_cast<const double*>(xtree),
-                         h.near_partial, h.near_colpart, h.near.ld, h.kp);
+                         h.near_partial, h.near_colpart, h.near.ld, kp, h.scale);
     else
       hipLaunchKernelGGL((k_near<float, float, K, D>), g, b, 0, h.stream, h.near.task,
                          h.near.pair_col, h.leaf_off, h.pts, h.dim, static_cast<const float*>(xtree),
                          reinterpret_cast<float*>(h.near_partial),
-                         reinterpret_cast<float*>(h.near_colpart), h.near.ld, h.kp);
+                         reinterpret_cast<float*>(h.near_colpart), h.near.ld, kp, h.scale);
   });
   check_launch("near");
   h.time_end(p == P64 ? KS_NEAR64 : KS_NEAR32, ev, double(h.near_evals));
@@ -735,15 +745,17 @@ void launch_near_stored(H2& h, const double* xtree) {
 }
 
 void launch_fine_reduce(H2& h, int p, const void* yhat, void* out, bool to_user, double alpha,
-                        const void* add, double beta) {
+                        const void* add, double beta, const void* xin) {
   const dim3 g(h.nleaf), b(256);
   const int64_t* perm = to_user ? h.perm : nullptr;
+  const bool stored = p == P64 && h.snear.ready;
+  const double* dg = stored ? nullptr : h.diag;     // stored tiles hold the diagonal
   if (p == P64)
     hipLaunchKernelGGL((k_fine_reduce<double, double>), g, b, 0, h.stream, h.leaf_off,
                        static_cast<const double*>(h.prec[P64].Qc), static_cast<const double*>(yhat),
                        h.r, h.near.row_task_ptr, h.near.col_ptr, h.near.col_pair, h.near_partial,
-                       h.near_colpart, h.near.ld, h.snear.ready ? h.snear.yc : nullptr,
-                       h.snear.chunk_base, perm, static_cast<double*>(out), alpha,
+                       h.near_colpart, h.near.ld, stored ? h.snear.yc : nullptr, h.snear.chunk_base, dg,
+                       static_cast<const double*>(xin), perm, static_cast<double*>(out), alpha,
                        static_cast<const double*>(add), beta);
   else if (p == P32)
     hipLaunchKernelGGL((k_fine_reduce<float, float>), g, b, 0, h.stream, h.leaf_off,
@@ -751,16 +763,18 @@ void launch_fine_reduce(H2& h, int p, const void* yhat, void* out, bool to_user,
                        h.r, h.near.row_task_ptr, h.near.col_ptr, h.near.col_pair,
                        reinterpret_cast<const float*>(h.near_partial),
                        reinterpret_cast<const float*>(h.near_colpart), h.near.ld,
-                       static_cast<const float*>(nullptr), h.snear.chunk_base, perm,
-                       static_cast<float*>(out), alpha, static_cast<const float*>(add), beta);
+                       static_cast<const float*>(nullptr), h.snear.chunk_base, dg,
+                       static_cast<const float*>(xin), perm, static_cast<float*>(out), alpha,
+                       static_cast<const float*>(add), beta);
   else
     hipLaunchKernelGGL((k_fine_reduce<bf16, float>), g, b, 0, h.stream, h.leaf_off,
                        static_cast<const bf16*>(h.prec[P16].Qc), static_cast<const float*>(yhat),
                        h.r, h.near.row_task_ptr, h.near.col_ptr, h.near.col_pair,
                        reinterpret_cast<const float*>(h.near_partial),
                        reinterpret_cast<const float*>(h.near_colpart), h.near.ld,
-                       static_cast<const float*>(nullptr), h.snear.chunk_base, perm,
-                       static_cast<float*>(out), alpha, static_cast<const float*>(add), beta);
+                       static_cast<const float*>(nullptr), h.snear.chunk_base, dg,
+                       static_cast<const float*>(xin), perm, static_cast<float*>(out), alpha,
+                       static_cast<const float*>(add), beta);
   check_launch("fine_reduce");
 }
 

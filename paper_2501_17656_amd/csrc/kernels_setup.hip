@@ -164,8 +164,8 @@ __device__ inline double* tile_ptr(double* base, int64_t id, int T) {
 __global__ __launch_bounds__(NT) void k_leaf_basis_qr(
     const double* __restrict__ pts, int dim, const int* __restrict__ leaf_off,
     const double* __restrict__ cbox, const double* __restrict__ hbox,
-    const double* __restrict__ nodes, int m, int r, int gid0, double* __restrict__ Rall,
-    double* __restrict__ Qr, double* __restrict__ Qc) {
+    const double* __restrict__ nodes, int m, int r, int gid0, const double* __restrict__ scale,
+    double* __restrict__ Rall, double* __restrict__ Qr, double* __restrict__ Qc) {
   extern __shared__ double smem[];
   const int leaf = blockIdx.x, tid = threadIdx.x;
   const int s0 = leaf_off[leaf], n = leaf_off[leaf + 1] - s0;
@@ -181,7 +181,8 @@ __global__ __launch_bounds__(NT) void k_leaf_basis_qr(
   const double* h = hbox + size_t(gid) * dim;
   for (int idx = tid; idx < n * r; idx += NT) {
     const int i = idx % n, nu = idx / n;
-    A[size_t(nu) * n + i] = tensor_basis(pts + size_t(s0 + i) * dim, c, h, tn, m, dim, nu);
+    const double u = tensor_basis(pts + size_t(s0 + i) * dim, c, h, tn, m, dim, nu);
+    A[size_t(nu) * n + i] = scale ? scale[s0 + i] * u : u;
   }
   __syncthreads();
   qr_householder(A, n, r, tau, red);
@@ -318,7 +319,7 @@ __global__ __launch_bounds__(NT) void k_coupling(
 __global__ __launch_bounds__(NT) void k_pi_leaf(
     int b0, const int* __restrict__ blk_row, const int* __restrict__ blk_col, int gid0,
     const int* __restrict__ leaf_off, const double* __restrict__ pts, int dim, int r, int T,
-    KernelParams kp, const double* __restrict__ Qr, double* __restrict__ blk) {
+    KernelParams kp, PointScale ps, const double* __restrict__ Qr, double* __restrict__ blk) {
   extern __shared__ double smem[];
   const int tid = threadIdx.x;
   const int b = b0 + blockIdx.x;
@@ -347,8 +348,7 @@ __global__ __launch_bounds__(NT) void k_pi_leaf(
           const double dx = pi[a] - pt[j * dim + a];
           r2 += dx * dx;
         }
-        double k = kernel_r2(kp, r2);
-        if (diag && i == j) k += kp.shift;
+        const double k = scaled_entry(kernel_r2(kp, r2), s0 + i, t0 + j, diag && i == j, ps, kp.shift);
         const double* qrow = Qr + size_t(t0 + j) * r + c0;
 #pragma unroll
         for (int q = 0; q < 32; ++q)
@@ -443,7 +443,8 @@ __global__ __launch_bounds__(NT) void k_assemble_dense(
 }
 
 __global__ __launch_bounds__(NT) void k_assemble_kernel_dense(
-    const double* __restrict__ pts, int dim, int64_t n, KernelParams kp, double* __restrict__ A) {
+    const double* __restrict__ pts, int dim, int64_t n, KernelParams kp, PointScale ps,
+    double* __restrict__ A) {
   const int64_t idx = int64_t(blockIdx.x) * NT + threadIdx.x;
   if (idx >= n * n) return;
   const int64_t i = idx % n, j = idx / n;
@@ -452,9 +453,7 @@ __global__ __launch_bounds__(NT) void k_assemble_kernel_dense(
     const double dx = pts[i * dim + a] - pts[j * dim + a];
     r2 += dx * dx;
   }
-  double k = kernel_r2(kp, r2);
-  if (i == j) k += kp.shift;
-  A[i + j * n] = k;
+  A[i + j * n] = scaled_entry(kernel_r2(kp, r2), i, j, i == j, ps, kp.shift);
 }
 
 // ------------------------------------------------------------ Cholesky (lower, blocked)
@@ -577,8 +576,8 @@ __device__ void gauss_jordan_spd(double* A, int n, double* fk, int* flag) {
 // (entries beyond the leaf size are zero).
 __global__ __launch_bounds__(NT) void k_bj_inv_fine(const int* __restrict__ leaf_off,
                                                     const double* __restrict__ pts, int dim,
-                                                    KernelParams kp, double* __restrict__ out,
-                                                    int ld, int* flag) {
+                                                    KernelParams kp, PointScale ps,
+                                                    double* __restrict__ out, int ld, int* flag) {
   extern __shared__ double smem[];
   const int leaf = blockIdx.x, tid = threadIdx.x;
   const int s0 = leaf_off[leaf], n = leaf_off[leaf + 1] - s0;
@@ -591,7 +590,7 @@ __global__ __launch_bounds__(NT) void k_bj_inv_fine(const int* __restrict__ leaf
       const double dx = pts[int64_t(s0 + i) * dim + a] - pts[int64_t(s0 + j) * dim + a];
       r2 += dx * dx;
     }
-    A[idx] = kernel_r2(kp, r2) + (i == j ? kp.shift : 0.0);
+    A[idx] = scaled_entry(kernel_r2(kp, r2), s0 + i, s0 + j, i == j, ps, kp.shift);
   }
   gauss_jordan_spd(A, n, fk, flag);
   double* o = out + int64_t(leaf) * ld * ld;
@@ -648,7 +647,8 @@ __global__ __launch_bounds__(NT) void k_near_tiles(int64_t nblocks, const int* _
                                                    const int* __restrict__ chunk_start,
                                                    const int* __restrict__ chunk_n,
                                                    const double* __restrict__ pts, int dim,
-                                                   KernelParams kp, double* __restrict__ tiles) {
+                                                   KernelParams kp, PointScale ps,
+                                                   double* __restrict__ tiles) {
   const int64_t blk = (int64_t(blockIdx.x) * NT + threadIdx.x) >> 6;
   if (blk >= nblocks) return;
   const int lane = threadIdx.x & 63;
@@ -678,8 +678,8 @@ __global__ __launch_bounds__(NT) void k_near_tiles(int64_t nblocks, const int* _
         const double dx = pi[u][q] - pj[v0 + w][q];
         r2 += dx * dx;
       }
-      double k = kernel_r2(kp, r2);
-      if (cs == ct && i == j) k += kp.shift;
+      const double k = scaled_entry(kernel_r2(kp, r2), s0 + min(i, ns - 1), t0 + min(j, nt - 1),
+                                    cs == ct && i == j, ps, kp.shift);
       val[w] = (i < ns && j < nt) ? k : 0.0;
     }
     double2 out;
@@ -709,7 +709,7 @@ void launch_leaf_basis_qr(H2& h) {
   const size_t lds = (size_t(h.leaf_max) * h.r + 64 + 64 + 8 + 64) * sizeof(double);
   allow_lds(k_leaf_basis_qr, lds);
   hipLaunchKernelGGL(k_leaf_basis_qr, dim3(h.nleaf), dim3(NT), lds, h.stream, h.pts, h.dim,
-                     h.leaf_off, h.cbox, h.hbox, h.nodes1d, h.m, h.r, h.nleaf - 1, h.R,
+                     h.leaf_off, h.cbox, h.hbox, h.nodes1d, h.m, h.r, h.nleaf - 1, h.scale, h.R,
                      static_cast<double*>(h.prec[P64].Qr), static_cast<double*>(h.prec[P64].Qc));
   check_launch("leaf_basis_qr");
 }
@@ -737,7 +737,7 @@ void launch_near_tiles(H2& h) {
   const int64_t groups = (sn.nblocks + 3) / 4;
   hipLaunchKernelGGL(k_near_tiles, dim3(unsigned(groups)), dim3(NT), 0, h.stream, sn.nblocks,
                      sn.blk_row, sn.blk_col, sn.chunk_start, sn.chunk_n, h.pts, h.dim, h.kp,
-                     sn.tiles);
+                     PointScale{h.scale, h.diag}, sn.tiles);
   check_launch("near_tiles");
 }
 
@@ -747,7 +747,7 @@ void launch_pi_leaf(H2& h) {
   allow_lds(k_pi_leaf, lds);
   hipLaunchKernelGGL(k_pi_leaf, dim3(h.p_count[h.L]), dim3(NT), lds, h.stream, h.p_first[h.L],
                      h.blk_row, h.blk_col, h.nleaf - 1, h.leaf_off, h.pts, h.dim, h.r, h.T, h.kp,
-                     static_cast<const double*>(h.prec[P64].Qr),
+                     PointScale{h.scale, h.diag}, static_cast<const double*>(h.prec[P64].Qr),
                      static_cast<double*>(h.prec[P64].blk));
   check_launch("pi_leaf");
 }
@@ -779,7 +779,7 @@ void launch_assemble_dense(H2& h, double* A, int64_t lda) {
 void launch_assemble_kernel_dense(H2& h, double* A, int64_t lda) {
   const int64_t nn = int64_t(h.n) * h.n;
   hipLaunchKernelGGL(k_assemble_kernel_dense, dim3((nn + NT - 1) / NT), dim3(NT), 0, h.stream,
-                     h.pts, h.dim, int64_t(h.n), h.kp, A);
+                     h.pts, h.dim, int64_t(h.n), h.kp, PointScale{h.scale, h.diag}, A);
   (void)lda;
   check_launch("assemble_kernel_dense");
 }
@@ -804,7 +804,7 @@ void launch_bj_inverse_fine(H2& h, double* out, int ld) {
   const size_t lds = (size_t(n) * n + n) * sizeof(double);
   allow_lds(k_bj_inv_fine, lds);
   hipLaunchKernelGGL(k_bj_inv_fine, dim3(h.nleaf), dim3(NT), lds, h.stream, h.leaf_off, h.pts,
-                     h.dim, h.kp, out, ld, h.flags);
+                     h.dim, h.kp, PointScale{h.scale, h.diag}, out, ld, h.flags);
   check_launch("bj_inv_fine");
 }
 

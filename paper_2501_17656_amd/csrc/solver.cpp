@@ -11,6 +11,7 @@
 // partial sums (kernels_solve.hip).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <stdexcept>
@@ -461,6 +462,45 @@ h2mg_status solve(H2& h, const double* b, double* x, const SolveParams& sp, h2mg
     info->history_len = int(h.history.size());
   }
   return result;
+}
+
+h2mg_status smooth_once(H2& h, int level, const double* r, double* e, int nsteps, int smoother,
+                        bool use_e0) {
+  h2mg_status st = setup_mg(h, 0);
+  if (st != H2MG_OK) return st;
+  if (level < 1 || level > h.levels)
+    return fail(H2MG_ERR_INVALID_ARG, "level %d out of range 1..%d", level, h.levels);
+  if (smoother == 1 && level == h.levels && level > 1)
+    return fail(H2MG_ERR_INVALID_ARG, "the block smoother has no blocks on the coarsest level");
+  try {
+    if (smoother == 1) {
+      st = ensure_block_jacobi(h, P64);
+      if (st != H2MG_OK) return st;
+    }
+    Work w = make_work(h, P64);
+    w.smoother = smoother;
+    const int64_t N = h.level_size(level);
+    if (level == 1) {
+      launch_gather(h, r, static_cast<double*>(w.r[1]));
+      if (use_e0) launch_gather(h, e, static_cast<double*>(w.et[1]));
+    } else {
+      launch_copy(h, P64, r, w.r[level], N);
+      if (use_e0) launch_copy(h, P64, e, w.et[level], N);
+    }
+    hip_check(hipMemsetAsync(h.flags, 0, 4 * sizeof(int), h.stream), "memset");
+    cg(h, P64, level, w, w.r[level], w.et[level], !use_e0, nsteps);
+    if (level == 1) launch_scatter(h, static_cast<const double*>(w.et[1]), e);
+    else launch_copy(h, P64, w.et[level], e, N);
+    int f[4];
+    read_flags(h, f);
+    release_work(h, w);
+    if (f[0]) return fail(H2MG_ERR_NOT_SPD, "CG met p^T A p <= 0 (operator not SPD)");
+  } catch (const std::bad_alloc&) {
+    return fail(H2MG_ERR_OOM, "device allocation failed in the smoother");
+  } catch (const std::exception& ex) {
+    return fail(H2MG_ERR_HIP, "%s", ex.what());
+  }
+  return H2MG_OK;
 }
 
 h2mg_status vcycle_once(H2& h, const double* x0, const double* b, double* x_out, const SolveParams& sp) {

@@ -13,7 +13,7 @@ import numpy as np
 from . import _lib
 from ._lib import check, lib
 
-KERNELS = {"exp": 0, "gauss": 1, "matern32": 2}
+KERNELS = {"exp": 0, "gauss": 1, "matern32": 2, "laplace": 3}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 SMOOTHERS = {"cg": 0, "bj": 1}
 METHODS = {"v": 0, "w": 1, "f": 2, "cg": 3}
@@ -82,7 +82,9 @@ class H2Matrix:
 
     def __init__(self, points, kernel: str = "matern32", length_scale: float = 0.2,
                  shift: float = 1e-3, leaf: int = 128, eta: float = 0.7, m: int = 4,
-                 derivative: str = "value"):
+                 derivative: str = "value", scale=None, diag=None):
+        """scale, diag: optional per-point s and d (float64 device tensors,
+        user order) of the scaled form diag(s) K diag(s) + diag(d)."""
         if points is None:                 # wrapped handle (see derivative())
             return
         pts = points if points.is_contiguous() else points.contiguous()
@@ -92,8 +94,14 @@ class H2Matrix:
         ker = _lib.Kernel(KERNELS[kernel], float(length_scale), float(shift), DERIVATIVES[derivative])
         opts = _lib.BuildOpts(int(leaf), float(eta), int(m))
         h = ctypes.c_void_p()
-        check(lib().h2mg_build(ctypes.c_void_p(pts.data_ptr()), self.n, self.dim, ctypes.byref(ker),
-                               ctypes.byref(opts), _stream(), ctypes.byref(h)))
+        if scale is None and diag is None:
+            check(lib().h2mg_build(ctypes.c_void_p(pts.data_ptr()), self.n, self.dim, ctypes.byref(ker),
+                                   ctypes.byref(opts), _stream(), ctypes.byref(h)))
+        else:
+            check(lib().h2mg_build_scaled(
+                ctypes.c_void_p(pts.data_ptr()), self.n, self.dim, ctypes.byref(ker), ctypes.byref(opts),
+                _dev_f64(scale, self.n, "scale") if scale is not None else None,
+                _dev_f64(diag, self.n, "diag") if diag is not None else None, _stream(), ctypes.byref(h)))
         self._h = h
 
     # ------------------------------------------------------------ derivatives
@@ -174,6 +182,15 @@ class H2Matrix:
                                  _dev_f64(out), _stream()))
         return out
 
+    def smooth(self, level: int, r, nsteps: int, e0=None, smoother: str = "cg"):
+        """e = Iter(A_level, r, e0): nsteps of the smoother in FP64."""
+        import torch
+        nk = self.level_size(level)
+        e = torch.zeros_like(r) if e0 is None else e0.clone()
+        check(lib().h2mg_smooth(self._h, level, _dev_f64(r, nk, "r"), _dev_f64(e, nk, "e"), int(nsteps),
+                                SMOOTHERS[smoother], int(e0 is not None), _stream()))
+        return e
+
     # ------------------------------------------------------------ solves
     @staticmethod
     def _opts(rtol, n_fine, n_coarse, max_cycles, precision, use_x0, smoother="cg", method="v"):
@@ -243,3 +260,41 @@ class H2Matrix:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- boundary elements
+def bem_panels(vertices, triangles):
+    """Centroids (nt x 3), scale sqrt(area) and diagonal I_i / (4 pi) of a
+    triangle mesh (device float64 vertices nv x 3, int64 triangles nt x 3)."""
+    import torch
+    nt = int(triangles.shape[0])
+    if triangles.dtype != torch.int64 or not triangles.is_cuda or not triangles.is_contiguous():
+        raise TypeError("triangles must be a contiguous int64 tensor on the GPU")
+    y = torch.empty((nt, 3), dtype=torch.float64, device=vertices.device)
+    s = torch.empty(nt, dtype=torch.float64, device=vertices.device)
+    d = torch.empty(nt, dtype=torch.float64, device=vertices.device)
+    check(lib().h2mg_bem_panels(_dev_f64(vertices), int(vertices.shape[0]),
+                                ctypes.c_void_p(triangles.data_ptr()), nt, _dev_f64(y), _dev_f64(s),
+                                _dev_f64(d), _stream()))
+    return y, s, d
+
+
+def bem_point_source_rhs(centroids, scale, x0):
+    """W^(1/2) f for the point source x0 (three floats)."""
+    import torch
+    n = int(scale.numel())
+    f = torch.empty(n, dtype=torch.float64, device=scale.device)
+    x = (ctypes.c_double * 3)(*[float(v) for v in x0])
+    check(lib().h2mg_bem_point_source_rhs(_dev_f64(centroids), _dev_f64(scale, n, "scale"), n, x,
+                                          _dev_f64(f), _stream()))
+    return f
+
+
+def bem_density(y, scale):
+    """sigma = y / s."""
+    import torch
+    n = int(scale.numel())
+    out = torch.empty_like(y)
+    check(lib().h2mg_bem_density(_dev_f64(y, n, "y"), _dev_f64(scale, n, "scale"), n, _dev_f64(out),
+                                 _stream()))
+    return out

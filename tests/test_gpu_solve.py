@@ -251,3 +251,64 @@ def test_plain_cg_rejects_low_precision():
         g.solve(_dev(synth.normal_vector(len(P), 1)), method="cg", precision="fp32")
     with pytest.raises(H2MGError):
         g.vcycle(_dev(np.zeros(len(P))), _dev(synth.normal_vector(len(P), 1)), method="cg")
+
+
+# ---------------------------------------------------------------- the smoother alone
+@pytest.mark.parametrize("smoother", ["cg", "bj"])
+@pytest.mark.parametrize("level", [1, 2, 3])
+def test_smoother_matches_oracle(level, smoother):
+    """h2mg_smooth: n steps of CG / block-Jacobi PCG on one level, from zero
+    and from a given e0, against the oracle's cg / pcg on the dense level
+    operator."""
+    from oracle.cg import cg, pcg
+    from oracle.vcycle import smoothers
+    P, o, g = make("exp2d_4k")
+    H = hier("exp2d_4k")
+    A = H.ops[level - 1]
+    nk = A.shape[0]
+    r = synth.normal_vector(nk, 40 + level)
+    e0 = 0.1 * synth.normal_vector(nk, 50 + level)
+    perm = o.tree.perm
+    precs = smoothers(H, smoother)
+
+    def oracle(rt, e0t, n):
+        if precs is None:
+            return cg(A.__matmul__, rt, e0t, n)
+        return pcg(A.__matmul__, precs[level - 1], rt, e0t, n)
+    for n, with_e0 in ((3, False), (5, True)):
+        if level == 1:       # user order on the GPU, tree order in the oracle
+            eo = np.empty(nk)
+            eo[perm] = oracle(r[perm], e0[perm] if with_e0 else None, n)
+        else:
+            eo = oracle(r, e0 if with_e0 else None, n)
+        eg = _host(g.smooth(level, _dev(r), n, e0=_dev(e0) if with_e0 else None, smoother=smoother))
+        rel = np.linalg.norm(eg - eo) / np.linalg.norm(eo)
+        print(f"[gpu] level {level} {smoother} {n} steps (e0 {with_e0}): rel diff {rel:.2e}")
+        assert rel <= 1e-11
+
+
+def test_smoothing_error_components_match_oracle():
+    """The error analysis of the experiments, computed with the C ABI
+    (smoother, level apply, restriction, one V-cycle per step) against the
+    oracle's, with 2 coarse CG steps so that iterates are comparable."""
+    import torch
+    from oracle.vcycle import smoothing_error_components
+    P, o, g = make("exp2d_4k")
+    H = hier("exp2d_4k")
+    n = len(P)
+    perm = o.tree.perm
+    x_true = synth.normal_vector(n, 60)
+    comps = smoothing_error_components(H, x_true[perm], n_f=1, n_c=2, cycles=2)
+    xt = _dev(x_true)
+    b = g.matvec(xt)
+    x = torch.zeros_like(b)
+    for k, (ue_o, qn_o) in enumerate(comps):
+        r = b - g.matvec(x)
+        err = x + g.smooth(1, r, 1) - xt
+        ue = _host(g.restrict(1, err))
+        qn = float(np.sqrt(max(float((err @ err).item()) - float(ue @ ue), 0.0)))
+        print(f"[gpu] cycle {k + 1}: |U^T e| {np.linalg.norm(ue):.6e} (oracle {np.linalg.norm(ue_o):.6e}), "
+              f"|Q^T e| {qn:.6e} (oracle {qn_o:.6e})")
+        assert np.linalg.norm(ue - ue_o) <= 1e-9 * np.linalg.norm(ue_o)
+        assert qn == pytest.approx(qn_o, rel=1e-6)
+        x = g.vcycle(x, b, n_coarse=2)
