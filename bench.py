@@ -199,6 +199,43 @@ def spd_probe(args, torch, synth, H2Matrix):
         torch.cuda.empty_cache()
 
 
+def block_product(args, torch, g, w, single_ms):
+    """Y = A_H2 X for a block of 16 vectors (matrix-core tile products; each
+    stored tile streamed twice, once per pass): time per block product, the
+    equivalent time per vector, and the matrix-core rate of the near-field
+    tile passes (2 * 64 * 64 * 16 flops per tile and pass)."""
+    X = torch.from_numpy(synth_block(w, 16)).cuda()
+    try:
+        Y = g.matvec_multi(X)
+    except Exception as ex:
+        return {"error": str(ex)}
+    torch.cuda.synchronize()
+    g.set_timing(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.matvec_reps):
+        g.matvec_multi(X, out=Y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.matvec_reps
+    st = g.kernel_stats("near_gemm16_fp64")
+    near_ms = st["ms"] / max(st["launches"], 1)
+    tile_bytes = st["work"] / max(st["launches"], 1)          # both passes
+    flops = tile_bytes / 8.0 * 2.0 * 16.0                     # 2 flops per stored word and column
+    g.set_timing(False)
+    return {"ms": round(ms, 3), "ms_per_vector": round(ms / 16, 3),
+            "speedup_vs_16_single_products": round(16 * single_ms / ms, 2),
+            "near_tile_passes_ms": round(near_ms, 3),
+            "near_tile_passes_gbs": round(tile_bytes / (near_ms * 1e-3) / 1e9, 1),
+            "near_mfma_tflops": round(flops / (near_ms * 1e-3) / 1e12, 2),
+            "near_mfma_frac_of_fp64_peak": round(flops / (near_ms * 1e-3) / 1e12 / 78.6, 3)}
+
+
+def synth_block(w, nrhs):
+    import synth
+    return synth.normal_vector(w.n, w.x_seed, nrhs=nrhs)
+
+
 def stored_near_matvec(args, torch, g, w, time_matvecs):
     """The fine H2 matvec with the close leaf blocks stored as FP64 tiles:
     time per product, algorithmic bytes (near tiles + couplings + the two
@@ -240,6 +277,7 @@ def stored_near_matvec(args, torch, g, w, time_matvecs):
         "near_gemv_roofline": block_gemv_roofline(g, "near_gemv_fp64"),
         "device_memory_gb": round(g.memory_bytes() / 1e9, 1),
     }
+    out["block_of_16"] = block_product(args, torch, g, w, ms)
     g.store_near(False)
     torch.cuda.synchronize()
     log(f"stored-near matvec: {out['matvec_ms']} ms, {out['matvec_gbs']} GB/s "

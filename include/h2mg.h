@@ -287,6 +287,21 @@ h2mg_status h2mg_quadratic_gradient(h2mg_h2_t h, h2mg_h2_t h_dl, h2mg_h2_t h_g,
  * Blocks until the tiles are complete. */
 h2mg_status h2mg_store_near(h2mg_h2_t h, int32_t enable, hipStream_t stream);
 
+/* Y = A_H2 X for a block of 1 <= nrhs <= 16 vectors (the Section 3.1 matvec
+ * applied column by column, computed for all columns at once): x_dev and
+ * y_dev are device, row-major n x ldx and n x ldy (entry (i, k) of user row
+ * i at i * ld + k), ld >= nrhs.  FP64.  The r x r and near-field tile
+ * products run 16 columns at a time on the matrix cores; each stored tile is
+ * read twice per product (once for its block row, once for its block
+ * column, transposed), so the product streams twice the bytes of a single
+ * matvec for up to 16 of them.  Requires rank 64 and h2mg_store_near.
+ * Results equal 16 single products up to rounding order.  Errors:
+ * INVALID_ARG (null, nrhs or ld out of range, rank != 64), STATE (near field
+ * not stored), OOM (about 1 GB of block buffers per 2^20 points, plus 8 KB
+ * per tile task, allocated on first use and kept), HIP. */
+h2mg_status h2mg_matvec_multi(h2mg_h2_t h, int32_t nrhs, const double* x_dev, int32_t ldx,
+                              double* y_dev, int32_t ldy, hipStream_t stream);
+
 /* Build the H2-MG hierarchy (Section 3.3): restricted operators
  * A_k = U_{k-1}^T A_{k-1} V_{k-1}^T for every level, i.e. the projected close
  * blocks of eq. a2_str at every depth, the dense coarsest operator A_l and
@@ -360,7 +375,8 @@ h2mg_status h2mg_set_graphs(h2mg_h2_t h, int32_t enabled);
  * they streamed (stored block words x element size); for kind 3/4 (near
  * field evaluated in FP64/FP32) the summed kernel evaluations instead of
  * bytes; for kind 5 (block GEMV over the stored FP64 near-field tiles) the
- * bytes of the tiles it streamed. */
+ * bytes of the tiles it streamed; for kind 6 (both passes of the 16-vector
+ * tile product over the near-field tiles) twice those bytes. */
 h2mg_status h2mg_set_timing(h2mg_h2_t h, int32_t enabled);
 h2mg_status h2mg_kernel_stats(h2mg_h2_t h, int32_t kind, int64_t* launches, double* total_ms,
                               double* total_work);

@@ -71,6 +71,7 @@ SIGNATURES = {
     "h2mg_set_timing": (c_int32, [c_void_p, c_int32]),
     "h2mg_store_near": (c_int32, [c_void_p, c_int32, c_void_p]),
     "h2mg_set_graphs": (c_int32, [c_void_p, c_int32]),
+    "h2mg_matvec_multi": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_int32, c_void_p]),
     "h2mg_build_scaled": (c_int32, [c_void_p, c_int64, c_int32, ctypes.POINTER(Kernel), ctypes.POINTER(BuildOpts),
                                     c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_void_p)]),
     "h2mg_bem_panels": (c_int32, [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),

@@ -18,8 +18,9 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libh2mg.so")
 
-HIP_SOURCES = ["kernels_setup.hip", "kernels_apply.hip", "kernels_solve.hip", "kernels_bem.hip"]
-CPP_SOURCES = ["plan.cpp", "h2_build.cpp", "h2_apply.cpp", "solver.cpp", "abi.cpp"]
+HIP_SOURCES = ["kernels_setup.hip", "kernels_apply.hip", "kernels_solve.hip", "kernels_bem.hip",
+               "kernels_multi.hip"]
+CPP_SOURCES = ["plan.cpp", "h2_build.cpp", "h2_apply.cpp", "multi.cpp", "solver.cpp", "abi.cpp"]
 ARCH = os.environ.get("H2MG_ARCH", "gfx950")
 
 

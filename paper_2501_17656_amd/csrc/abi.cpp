@@ -364,6 +364,17 @@ h2mg_status h2mg_quadratic_gradient(h2mg_h2_t hh, h2mg_h2_t hl, h2mg_h2_t hg, co
   });
 }
 
+h2mg_status h2mg_matvec_multi(h2mg_h2_t hh, int32_t nrhs, const double* x, int32_t ldx, double* y,
+                              int32_t ldy, hipStream_t stream) {
+  return guarded([&] {
+    if (!hh || !x || !y) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    hh->h->stream = stream;
+    h2mg_status st = matvec_multi(*hh->h, nrhs, x, ldx, y, ldy);
+    if (st != H2MG_OK) return st;
+    return check_stream_err(stream);
+  });
+}
+
 h2mg_status h2mg_store_near(h2mg_h2_t hh, int32_t enable, hipStream_t stream) {
   return guarded([&] {
     if (!hh) return fail(H2MG_ERR_INVALID_ARG, "null handle");

@@ -493,7 +493,13 @@ h2mg_status quadratic_gradient(H2& h, H2* hl, H2* hg, const double* b, const dou
 
 namespace {
 
+void release_multi(H2& h) {
+  for (void* p : h.multi.owned) h.arena.release(p);
+  h.multi = MultiWork();
+}
+
 void release_stored_near(H2& h) {
+  release_multi(h);                    // its near-field task lists refer to the tiles
   for (void* p : h.snear.owned) h.arena.release(p);
   h.snear = StoredNear();
 }
@@ -573,6 +579,8 @@ h2mg_status store_near(H2& h, int enable) {
     sn.nslot = cptr[sn.nchunk];
     sn.ntasks = int(task.size() / 3);
 
+    sn.brow_h = brow;
+    sn.bcol_h = bcol;
     sn.chunk_base = own(upload(h, cbase));
     sn.chunk_start = own(upload(h, cstart));
     sn.chunk_n = own(upload(h, cn));

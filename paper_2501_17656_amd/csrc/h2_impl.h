@@ -24,6 +24,7 @@ const char* last_error_cstr();
 void clear_error();
 
 enum Prec { P64 = 0, P32 = 1, P16 = 2 };   // FP64, FP32, BF16 operator storage
+constexpr int MULTI_NR = 16;               // columns of a multi-vector block
 inline size_t elem_bytes(int p) { return p == P64 ? 8 : p == P32 ? 4 : 2; }
 
 // Device allocation owned by a handle.
@@ -60,7 +61,8 @@ struct Launch {
 enum KStatKind {
   KS_GEMV64 = 0, KS_GEMV32 = 1, KS_GEMV16 = 2, KS_NEAR64 = 3, KS_NEAR32 = 4,
   KS_NEARST64 = 5,                     // block GEMV over the stored near-field tiles
-  KS_COUNT = 6
+  KS_NEAR16 = 6,                       // both passes of the 16-vector product over the near tiles
+  KS_COUNT = 7
 };
 struct KStat {
   int64_t launches = 0;
@@ -112,7 +114,36 @@ struct StoredNear {
   double* colpart = nullptr;           // nslot * 64
   double* xc = nullptr;                // nchunk * 64 (padded input; null when identity)
   double* yc = nullptr;                // nchunk * 64 (near-field product)
+  std::vector<int> brow_h, bcol_h;     // host copies of blk_row / blk_col
   std::vector<void*> owned;            // device allocations of this structure
+};
+
+// Buffers and task lists of products with a block of MULTI_NR vectors
+// (built on first use).  Row-pass tasks are the single-vector tasks;
+// column-pass tasks are runs of at most 16 off-diagonal tiles of one block
+// column, over `order` (tile ids by column).
+struct MultiWork {
+  bool ready = false;
+  double* x = nullptr;                 // n x NR, tree order
+  double* y = nullptr;
+  double* xall = nullptr;              // ngid * r x NR
+  double* yall = nullptr;
+  double* partial = nullptr;           // max tasks x 64 x NR
+  int64_t partial_tasks = 0;
+  // couplings (all depths)
+  int* rtp = nullptr;                  // ngid + 1: row-pass tasks of each gid
+  int* ctp = nullptr;                  // ngid + 1: column-pass tasks of each gid
+  int* ctask = nullptr;
+  int* corder = nullptr;
+  int nctask = 0;
+  // stored near field
+  int* near_ctp = nullptr;             // nchunk + 1
+  int* near_ctask = nullptr;
+  int* near_corder = nullptr;
+  int near_nctask = 0;
+  double* xc = nullptr;                // nchunk * 64 x NR (null when the chunk order is the tree order)
+  double* yc = nullptr;
+  std::vector<void*> owned;
 };
 
 struct PrecData {                      // operator storage in one precision
@@ -158,6 +189,7 @@ struct H2 {
   std::vector<View> sview, pview;
   NearField near;
   StoredNear snear;
+  MultiWork multi;
   PrecData prec[3];
 
   // launches: fine apply (S of all depths), coarse apply at depth d
@@ -259,6 +291,19 @@ void launch_leaf_down(H2& h, int p, const void* yhat, void* out, double alpha, c
 // partials.
 void launch_fine_reduce(H2& h, int p, const void* yhat, void* out, bool to_user,
                         double alpha, const void* add, double beta, const void* xin);
+
+// ------------------------------------------------------------ blocks of 16 vectors (FP64, r = 64)
+void launch_gemm16(H2& h, bool rows, const int* tasks, int ntasks, const double* tiles,
+                   const int* order, const int* other, const double* x, double* partial);
+void launch_reduce16(H2& h, int nrows, const int* rtp, const int* ctp, int cbase, const double* partial,
+                     double* out);
+void launch_gather16(H2& h, int nrhs, const double* user, int ldu, double* tree);
+void launch_scatter16(H2& h, int nrhs, const double* tree, double* user, int ldu);
+void launch_leaf_up16(H2& h, const double* x, double* xhat);
+void launch_transfer_up16(H2& h, int d, const double* xchild, double* xpar);
+void launch_transfer_down16(H2& h, int d, const double* ypar, double* ychild, const double* addend);
+void launch_fine_reduce16(H2& h, const double* yhat, const double* near_y, double* y);
+void launch_near_pad16(H2& h, const double* x, double* xc);
 
 // ------------------------------------------------------------ boundary elements
 // Per triangle (vertex rows V, index triples T): centroid y (nt x 3), scale

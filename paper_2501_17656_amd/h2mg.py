@@ -139,6 +139,18 @@ class H2Matrix:
         check(lib().h2mg_matvec(self._h, _dev_f64(x, self.n, "x"), _dev_f64(y, self.n, "y"), _stream()))
         return y
 
+    def matvec_multi(self, X, out=None):
+        """Y = A_H2 X for X of shape (n, nrhs), nrhs <= 16 (FP64; needs rank
+        64 and store_near())."""
+        import torch
+        if X.dim() != 2 or X.shape[0] != self.n:
+            raise ValueError("X must have shape (n, nrhs)")
+        Y = torch.empty_like(X) if out is None else out
+        nrhs = int(X.shape[1])
+        check(lib().h2mg_matvec_multi(self._h, nrhs, _dev_f64(X, name="X"), nrhs, _dev_f64(Y, name="Y"),
+                                      nrhs, _stream()))
+        return Y
+
     def store_near(self, enable: bool = True) -> None:
         """Store the close leaf blocks as FP64 tiles (enable) or release them;
         FP64 fine-level products then stream the tiles."""
@@ -230,7 +242,7 @@ class H2Matrix:
         return x, out
 
     KERNEL_KINDS = {"gemv_fp64": 0, "gemv_fp32": 1, "gemv_bf16": 2, "near_fp64": 3, "near_fp32": 4,
-                    "near_gemv_fp64": 5}
+                    "near_gemv_fp64": 5, "near_gemm16_fp64": 6}
 
     def set_graphs(self, enabled: bool) -> None:
         """Launch each solver cycle as one captured HIP graph."""
