@@ -292,15 +292,52 @@ h2mg_status h2mg_store_near(h2mg_h2_t h, int32_t enable, hipStream_t stream);
  * y_dev are device, row-major n x ldx and n x ldy (entry (i, k) of user row
  * i at i * ld + k), ld >= nrhs.  FP64.  The r x r and near-field tile
  * products run 16 columns at a time on the matrix cores; each stored tile is
- * read twice per product (once for its block row, once for its block
- * column, transposed), so the product streams twice the bytes of a single
- * matvec for up to 16 of them.  Requires rank 64 and h2mg_store_near.
- * Results equal 16 single products up to rounding order.  Errors:
- * INVALID_ARG (null, nrhs or ld out of range, rank != 64), STATE (near field
- * not stored), OOM (about 1 GB of block buffers per 2^20 points, plus 8 KB
- * per tile task, allocated on first use and kept), HIP. */
+ * read at most twice per product (once for its block row, once for its
+ * block column, transposed), so the product streams at most twice the bytes
+ * of a single matvec for up to 16 of them.  Requires 9 <= r <= 64 and
+ * h2mg_store_near.  Results equal 16 single products up to rounding order.
+ * Errors: INVALID_ARG (null, nrhs or ld out of range, rank out of range),
+ * STATE (near field not stored), OOM (about 1 GB of block buffers per 2^20
+ * points, plus 8 KB per tile task, allocated on first use and kept), HIP. */
 h2mg_status h2mg_matvec_multi(h2mg_h2_t h, int32_t nrhs, const double* x_dev, int32_t ldx,
                               double* y_dev, int32_t ldy, hipStream_t stream);
+
+/* Solve A_H2 X = B for a block of 1 <= nrhs <= 16 right-hand sides: every
+ * step of the cycles of h2mg_solve (Algorithm 1, Section 3.3: smoother,
+ * restriction, prolongation, coarse Cholesky solve; FP64, or FP64 iterative
+ * refinement around an FP32 or BF16 cycle) applied to all columns at once,
+ * with the CG scalars of the smoother and the stopping test kept per column
+ * (cycles run until every column's FP64 relative residual is below rtol).
+ * b_dev, x_dev: device, row-major n x ldb and n x ldx, user order.  Stored
+ * tiles are multiplied 16 columns at a time on the matrix cores; the
+ * low-precision forms use an FP32 copy of the stored near field (made on
+ * first use and kept; BF16 rounding of the close blocks, which hold the
+ * diagonal, can make the operator indefinite).  opts->method: V, W or F cycles.  info:
+ * cycles run, converged (all columns), the largest column residual, time.
+ * col_residuals: host, nrhs entries (final relative residual of each column),
+ * or null.  Requires 9 <= r <= 64 and h2mg_store_near; runs h2mg_setup_mg
+ * itself when needed.  Errors: as h2mg_solve, plus STATE (near field not
+ * stored) and INVALID_ARG (nrhs, ld or rank out of range, method CG). */
+h2mg_status h2mg_solve_multi(h2mg_h2_t h, int32_t nrhs, const double* b_dev, int32_t ldb,
+                             double* x_dev, int32_t ldx, const h2mg_solve_opts* opts,
+                             h2mg_solve_info* info, double* col_residuals, hipStream_t stream);
+
+/* Independent problems solved together (many right-hand sides of many
+ * problems of uneven size): problem i is h2mg_solve_multi on handle hs[i]
+ * with nrhs[i] columns b_dev[i] / x_dev[i] (leading dimensions ldb[i],
+ * ldx[i]), all with the same opts.  The problems are spread over nstreams
+ * streams of their own (0: 4), and each problem's next cycle is enqueued as
+ * soon as its own residual has been read, so small and large problems keep
+ * the device busy together; with h2mg_set_graphs on a handle its cycles are
+ * graph launches.  Every stream first waits for the work already enqueued
+ * on `stream`; the call returns when every problem has finished.  Handles
+ * must be distinct.  infos: host array of nprob entries, or null.  Returns
+ * the status of the first failing problem (the others still run to their
+ * end); errors as h2mg_solve_multi. */
+h2mg_status h2mg_solve_batch(int32_t nprob, const h2mg_h2_t* hs, const int32_t* nrhs,
+                             const double* const* b_dev, const int32_t* ldb, double* const* x_dev,
+                             const int32_t* ldx, const h2mg_solve_opts* opts,
+                             h2mg_solve_info* infos, int32_t nstreams, hipStream_t stream);
 
 /* Build the H2-MG hierarchy (Section 3.3): restricted operators
  * A_k = U_{k-1}^T A_{k-1} V_{k-1}^T for every level, i.e. the projected close
@@ -375,8 +412,9 @@ h2mg_status h2mg_set_graphs(h2mg_h2_t h, int32_t enabled);
  * they streamed (stored block words x element size); for kind 3/4 (near
  * field evaluated in FP64/FP32) the summed kernel evaluations instead of
  * bytes; for kind 5 (block GEMV over the stored FP64 near-field tiles) the
- * bytes of the tiles it streamed; for kind 6 (both passes of the 16-vector
- * tile product over the near-field tiles) twice those bytes. */
+ * bytes of the tiles it streamed; for kind 6 (both passes of the FP64
+ * 16-column tile product over the near-field tiles) the bytes of the tiles
+ * read by the two passes. */
 h2mg_status h2mg_set_timing(h2mg_h2_t h, int32_t enabled);
 h2mg_status h2mg_kernel_stats(h2mg_h2_t h, int32_t kind, int64_t* launches, double* total_ms,
                               double* total_work);

@@ -72,6 +72,11 @@ SIGNATURES = {
     "h2mg_store_near": (c_int32, [c_void_p, c_int32, c_void_p]),
     "h2mg_set_graphs": (c_int32, [c_void_p, c_int32]),
     "h2mg_matvec_multi": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_int32, c_void_p]),
+    "h2mg_solve_multi": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_int32,
+                                   ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), P_double, c_void_p]),
+    "h2mg_solve_batch": (c_int32, [c_int32, ctypes.POINTER(c_void_p), P_int32, ctypes.POINTER(c_void_p), P_int32,
+                                   ctypes.POINTER(c_void_p), P_int32, ctypes.POINTER(SolveOpts),
+                                   ctypes.POINTER(SolveInfo), c_int32, c_void_p]),
     "h2mg_build_scaled": (c_int32, [c_void_p, c_int64, c_int32, ctypes.POINTER(Kernel), ctypes.POINTER(BuildOpts),
                                     c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_void_p)]),
     "h2mg_bem_panels": (c_int32, [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),
@@ -113,7 +118,13 @@ def lib():
     return _lib
 
 
-def check(status: int) -> None:
+def last_error() -> str:
+    msg = lib().h2mg_last_error()
+    return msg.decode() if msg else ""
+
+
+def check(status: int, message: str = None) -> None:
+    """Raise H2MGError for a failed call (message: the error text read right
+    after that call, when other calls have been made since)."""
     if status != 0:
-        msg = lib().h2mg_last_error()
-        raise H2MGError(status, msg.decode() if msg else "")
+        raise H2MGError(status, last_error() if message is None else message)

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <vector>
 #include <cstring>
 #include <new>
 #include <stdexcept>
@@ -372,6 +373,35 @@ h2mg_status h2mg_matvec_multi(h2mg_h2_t hh, int32_t nrhs, const double* x, int32
     h2mg_status st = matvec_multi(*hh->h, nrhs, x, ldx, y, ldy);
     if (st != H2MG_OK) return st;
     return check_stream_err(stream);
+  });
+}
+
+h2mg_status h2mg_solve_multi(h2mg_h2_t hh, int32_t nrhs, const double* b, int32_t ldb, double* x,
+                             int32_t ldx, const h2mg_solve_opts* opts, h2mg_solve_info* info,
+                             double* col_residuals, hipStream_t stream) {
+  return guarded([&] {
+    if (!hh || !b || !x) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    if (!valid_solve_opts(opts)) return fail(H2MG_ERR_INVALID_ARG, "invalid solve options");
+    hh->h->stream = stream;
+    return solve_multi(*hh->h, nrhs, b, ldb, x, ldx, to_params(opts), info, col_residuals);
+  });
+}
+
+h2mg_status h2mg_solve_batch(int32_t nprob, const h2mg_h2_t* hs, const int32_t* nrhs,
+                             const double* const* b, const int32_t* ldb, double* const* x,
+                             const int32_t* ldx, const h2mg_solve_opts* opts, h2mg_solve_info* infos,
+                             int32_t nstreams, hipStream_t stream) {
+  return guarded([&] {
+    if (nprob < 1 || !hs || !nrhs || !b || !ldb || !x || !ldx)
+      return fail(H2MG_ERR_INVALID_ARG, "null argument or empty batch");
+    if (!valid_solve_opts(opts)) return fail(H2MG_ERR_INVALID_ARG, "invalid solve options");
+    if (nstreams < 0) return fail(H2MG_ERR_INVALID_ARG, "nstreams must be >= 0");
+    std::vector<H2*> hv(nprob);
+    for (int i = 0; i < nprob; ++i) {
+      if (!hs[i]) return fail(H2MG_ERR_INVALID_ARG, "null handle in problem %d", i);
+      hv[i] = hs[i]->h;
+    }
+    return solve_batch(nprob, hv.data(), nrhs, b, ldb, x, ldx, to_params(opts), infos, nstreams, stream);
   });
 }
 

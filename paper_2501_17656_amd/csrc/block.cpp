@@ -1,0 +1,686 @@
+// Products and H2-MG cycles on blocks of up to 16 right-hand sides: the
+// matvec of Section 3.1 and the cycle of Algorithm 1 (Section 3.3) applied to
+// every column at once, so that each stored tile is streamed once per pass
+// for all 16 columns (kernels_block.hip), and independent problems (one
+// handle each) solved together on several streams.  Columns never mix: every
+// CG scalar of the smoother Iter and every stopping test is per column.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <memory>
+#include <new>
+#include <stdexcept>
+#include <vector>
+
+#include "graph.h"
+#include "h2_build.h"
+
+namespace h2mg {
+
+namespace {
+
+constexpr int NR = MULTI_NR;
+constexpr int RUN = 8;                 // tiles per tile-product task
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+inline size_t vbytes(int p) { return p == P64 ? 8 : 4; }
+inline int vprec(int p) { return p == P64 ? P64 : P32; }
+
+void* alloc_owned(H2& h, size_t bytes) {
+  void* d = h.arena.alloc(std::max<size_t>(bytes, 8));
+  h.blk16.owned.push_back(d);
+  return d;
+}
+
+template <typename T>
+T* upload_owned(H2& h, const std::vector<T>& v) {
+  T* d = static_cast<T*>(alloc_owned(h, v.size() * sizeof(T)));
+  if (!v.empty())
+    hip_check(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, h.stream), "upload");
+  return d;
+}
+
+// Task set over the tiles `ids` (rows[b], cols[b]: block row and column of
+// tile b; rows and columns index 0 .. nrows_total - 1).  Row-pass tasks cover
+// every tile, column-pass tasks the off-diagonal ones; tiles keep their id
+// order within a row or column, and a row's (column's) tasks are
+// consecutive.
+TileSet make_set(H2& h, const std::vector<int>& ids, const std::vector<int>& rows, const std::vector<int>& cols,
+                 int nrows_total, int row0, int nrows, const int* brow, const int* bcol) {
+  TileSet ts;
+  ts.brow = brow;
+  ts.bcol = bcol;
+  ts.row0 = row0;
+  ts.nrows = nrows;
+  ts.ntiles = int64_t(ids.size());
+  auto build = [&](bool by_col, std::vector<int>& order, std::vector<int>& tasks, std::vector<int>& ptr) {
+    std::vector<std::pair<int, int>> kb;
+    for (int b : ids) {
+      if (by_col && rows[b] == cols[b]) continue;
+      kb.emplace_back(by_col ? cols[b] : rows[b], b);
+    }
+    std::stable_sort(kb.begin(), kb.end(), [](const auto& u, const auto& v) { return u.first < v.first; });
+    order.resize(kb.size());
+    for (size_t i = 0; i < kb.size(); ++i) order[i] = kb[i].second;
+    ptr.assign(size_t(nrows_total) + 1, 0);
+    for (size_t i = 0; i < kb.size();) {
+      size_t e = i;
+      while (e < kb.size() && kb[e].first == kb[i].first) ++e;
+      for (size_t c = i; c < e; c += RUN) {
+        tasks.push_back(kb[i].first);
+        tasks.push_back(int(c));
+        tasks.push_back(int(std::min(e, c + RUN)));
+        ptr[size_t(kb[i].first) + 1]++;
+      }
+      i = e;
+    }
+    for (int r = 0; r < nrows_total; ++r) ptr[r + 1] += ptr[r];
+    return int64_t(kb.size());
+  };
+  std::vector<int> ro, rt, rp, co, ct, cp;
+  build(false, ro, rt, rp);
+  ts.nctiles = build(true, co, ct, cp);
+  ts.nrt = int(rt.size() / 3);
+  ts.nct = int(ct.size() / 3);
+  ts.rorder = upload_owned(h, ro);
+  ts.rtask = upload_owned(h, rt);
+  ts.rtp = upload_owned(h, rp);
+  ts.corder = upload_owned(h, co);
+  ts.ctask = upload_owned(h, ct);
+  ts.ctp = upload_owned(h, cp);
+  return ts;
+}
+
+void ensure_partial(H2& h, int64_t elems) {
+  BlockWork& w = h.blk16;
+  if (elems <= w.partial_elems) return;
+  if (w.partial) {
+    hip_check(hipStreamSynchronize(h.stream), "sync");
+    h.arena.release(w.partial);
+    w.owned.erase(std::find(w.owned.begin(), w.owned.end(), w.partial));
+  }
+  w.partial = alloc_owned(h, size_t(elems) * sizeof(double));
+  w.partial_elems = elems;
+}
+
+// Task sets and buffers: couplings (at build), near-field tiles (once they
+// are stored), restricted operators of every depth (once the hierarchy is).
+void ensure_block(H2& h) {
+  BlockWork& w = h.blk16;
+  const int r = h.r;
+  if (!w.ready) {
+    if (h.T < 2) throw std::invalid_argument("blocks of vectors need a rank of 9 to 64");
+    if (h.d_top >= 0) {
+      std::vector<int> ids;
+      for (int d = h.d_top; d <= h.L; ++d)
+        for (int b = h.s_first[d]; b < h.s_first[d] + h.s_count[d]; ++b) ids.push_back(b);
+      const int row0 = (1 << h.d_top) - 1;
+      w.fine = make_set(h, ids, h.blk_row_h, h.blk_col_h, h.ngid, row0, h.ngid - row0, h.blk_row, h.blk_col);
+      w.xall = alloc_owned(h, size_t(h.ngid) * r * NR * sizeof(double));
+      w.yall = alloc_owned(h, size_t(h.ngid) * r * NR * sizeof(double));
+      ensure_partial(h, int64_t(w.fine.nrt + w.fine.nct) * r * NR);
+    }
+    w.bx = static_cast<double*>(alloc_owned(h, size_t(h.n) * NR * sizeof(double)));
+    w.by = static_cast<double*>(alloc_owned(h, size_t(h.n) * NR * sizeof(double)));
+    w.ready = true;
+  }
+  const StoredNear& sn = h.snear;
+  if (sn.ready && !w.near_ready) {
+    std::vector<int> ids(sn.brow_h.size());
+    for (size_t b = 0; b < ids.size(); ++b) ids[b] = int(b);
+    w.near = make_set(h, ids, sn.brow_h, sn.bcol_h, sn.nchunk, 0, sn.nchunk, sn.blk_row, sn.blk_col);
+    const size_t nv = size_t(sn.nchunk) * 64 * NR;
+    if (!sn.identity) {
+      w.xc64 = static_cast<double*>(alloc_owned(h, nv * sizeof(double)));
+      w.xc32 = static_cast<float*>(alloc_owned(h, nv * sizeof(float)));
+      hip_check(hipMemsetAsync(w.xc64, 0, nv * sizeof(double), h.stream), "memset");
+      hip_check(hipMemsetAsync(w.xc32, 0, nv * sizeof(float), h.stream), "memset");
+    }
+    w.yc = alloc_owned(h, nv * sizeof(double));
+    ensure_partial(h, int64_t(w.near.nrt + w.near.nct) * 64 * NR);
+    w.near_ready = true;
+  }
+  if (h.mg_built && !w.coarse_ready && h.d_top >= 0) {
+    w.coarse.assign(size_t(h.L) + 1, TileSet());
+    const int row0 = (1 << h.d_top) - 1;
+    for (int d = h.d_top; d <= h.L; ++d) {
+      std::vector<int> ids;
+      for (int q = h.d_top; q <= d; ++q)
+        for (int b = h.s_first[q]; b < h.s_first[q] + h.s_count[q]; ++b) ids.push_back(b);
+      for (int b = h.p_first[d]; b < h.p_first[d] + h.p_count[d]; ++b) ids.push_back(b);
+      w.coarse[d] = make_set(h, ids, h.blk_row_h, h.blk_col_h, h.ngid, row0, (2 << d) - 1 - row0, h.blk_row,
+                             h.blk_col);
+      ensure_partial(h, int64_t(w.coarse[d].nrt + w.coarse[d].nct) * r * NR);
+    }
+    w.coarse_ready = true;
+  }
+  hip_check(hipStreamSynchronize(h.stream), "block setup");
+}
+
+// FP32 copy of the near-field tiles for low-precision cycles.  The BF16
+// form keeps its near field in FP32 as well: the close blocks hold the
+// diagonal, and BF16 rounding of them (2^-9 relative) can exceed the
+// smallest eigenvalue (the shift) and make the operator indefinite.
+void ensure_near_lp(H2& h, int p) {
+  BlockWork& w = h.blk16;
+  if (p == P64 || w.near_lp[P32]) return;
+  w.near_lp[P32] = alloc_owned(h, size_t(h.snear.nblocks) * 4096 * sizeof(float));
+  launch_cast_near_tiles(h, P32, w.near_lp[P32]);
+  hip_check(hipStreamSynchronize(h.stream), "near tile copy");
+}
+
+// Coefficients of depth d inside a gid-indexed block buffer.
+inline void* at_depth(void* base, int p, int d, int r) {
+  return static_cast<char*>(base) + size_t((1 << d) - 1) * r * NR * vbytes(p);
+}
+
+// ------------------------------------------------------------ products
+// Fine level, tree order: out = alpha * A_H2 X + beta * add.
+void apply_fine16(H2& h, int p, const void* X, void* out, double alpha, const void* add, double beta) {
+  BlockWork& w = h.blk16;
+  const int r = h.r;
+  const void* yhat = nullptr;
+  if (h.d_top >= 0) {
+    launch_leaf_up16(h, p, X, at_depth(w.xall, p, h.L, r));
+    for (int d = h.L - 1; d >= h.d_top; --d)
+      launch_transfer_up16(h, p, d, at_depth(w.xall, p, d + 1, r), at_depth(w.xall, p, d, r));
+    launch_tgemm(h, p, h.T, w.fine, h.prec[p].blk, r, w.xall, w.partial);
+    launch_reduce16(h, p, w.fine, r, w.partial, w.yall);
+    for (int d = h.d_top + 1; d <= h.L; ++d)
+      launch_transfer_down16(h, p, d - 1, at_depth(w.yall, p, d - 1, r), at_depth(w.yall, p, d, r),
+                             at_depth(w.yall, p, d, r));
+    yhat = at_depth(w.yall, p, h.L, r);
+  }
+  const StoredNear& sn = h.snear;
+  const void* xc = X;
+  if (!sn.identity) {
+    void* buf = p == P64 ? static_cast<void*>(w.xc64) : static_cast<void*>(w.xc32);
+    launch_near_pad16(h, p, X, buf);
+    xc = buf;
+  }
+  int ev;
+  if (p == P64) h.time_begin(ev);
+  launch_tgemm(h, p == P64 ? P64 : P32, 8, w.near, p == P64 ? static_cast<const void*>(sn.tiles) : w.near_lp[P32],
+               64, xc, w.partial);
+  if (p == P64) h.time_end(KS_NEAR16, ev, double(w.near.ntiles + w.near.nctiles) * 4096.0 * sizeof(double));
+  launch_reduce16(h, p, w.near, 64, w.partial, w.yc);
+  launch_leaf_down16(h, p, yhat, w.yc, out, alpha, add, beta);
+}
+
+// Level k >= 2 (depth d = L - k + 2), coefficient order: Y = A_k X.
+void apply_coarse16(H2& h, int p, int k, const void* X, void* Y) {
+  BlockWork& w = h.blk16;
+  const int r = h.r, d = h.level_depth(k);
+  launch_copy(h, vprec(p), X, at_depth(w.xall, p, d, r), int64_t(1 << d) * r * NR);
+  for (int q = d - 1; q >= h.d_top; --q)
+    launch_transfer_up16(h, p, q, at_depth(w.xall, p, q + 1, r), at_depth(w.xall, p, q, r));
+  launch_tgemm(h, p, h.T, w.coarse[d], h.prec[p].blk, r, w.xall, w.partial);
+  launch_reduce16(h, p, w.coarse[d], r, w.partial, w.yall);
+  for (int q = h.d_top + 1; q <= d; ++q)
+    launch_transfer_down16(h, p, q - 1, at_depth(w.yall, p, q - 1, r), q == d ? Y : at_depth(w.yall, p, q, r),
+                           at_depth(w.yall, p, q, r));
+  if (d == h.d_top) launch_copy(h, vprec(p), at_depth(w.yall, p, d, r), Y, int64_t(1 << d) * r * NR);
+}
+
+void apply16(H2& h, int p, int k, const void* X, void* Y) {
+  if (k == 1) apply_fine16(h, p, X, Y, 1.0, nullptr, 0.0);
+  else apply_coarse16(h, p, k, X, Y);
+}
+
+// ------------------------------------------------------------ cycle
+struct Work16 {
+  int p = P64;
+  int smoother = 0;
+  std::vector<void*> r, et, ec;
+  void *s = nullptr, *pv = nullptr, *q = nullptr, *tmp = nullptr, *z = nullptr;
+  double* part = nullptr;              // 4 slots of 256 x NR partial sums
+  double* coarse64 = nullptr;          // Nl x NR, FP64 coarse solve of a low-precision cycle
+  std::vector<void*> owned;
+  double* gpart(int i) const { return part + size_t(i) * 256 * NR; }
+  double* dpart() const { return part + size_t(2) * 256 * NR; }
+  double* scratch() const { return part + size_t(3) * 256 * NR; }
+};
+
+void make_work16(H2& h, Work16& w, int p, bool second) {
+  auto take = [&](size_t bytes) {
+    void* d = h.arena.alloc(std::max<size_t>(bytes, 8));
+    w.owned.push_back(d);
+    return d;
+  };
+  const size_t vb = vbytes(p) * NR;
+  w.p = p;
+  w.r.assign(size_t(h.levels) + 1, nullptr);
+  w.et.assign(size_t(h.levels) + 1, nullptr);
+  w.ec.assign(size_t(h.levels) + 1, nullptr);
+  for (int k = 1; k <= h.levels; ++k) {
+    w.r[k] = take(size_t(h.level_size(k)) * vb);
+    w.et[k] = take(size_t(h.level_size(k)) * vb);
+    if (second && k >= 2 && k < h.levels) w.ec[k] = take(size_t(h.level_size(k)) * vb);
+  }
+  w.s = take(size_t(h.n) * vb);
+  w.pv = take(size_t(h.n) * vb);
+  w.q = take(size_t(h.n) * vb);
+  w.tmp = take(size_t(h.n) * NR * sizeof(double));
+  w.z = take(size_t(h.n) * vb);
+  w.part = static_cast<double*>(take(size_t(4) * 256 * NR * sizeof(double)));
+  if (p != P64) w.coarse64 = static_cast<double*>(take(size_t(h.Nl) * NR * sizeof(double)));
+}
+
+void release_work16(H2& h, Work16& w) {
+  for (void* d : w.owned) h.arena.release(d);
+  w.owned.clear();
+}
+
+// e = Iter(A_k, rhs, e0) on every column: nsteps of CG, or of block-Jacobi
+// PCG when w.smoother == 1; e holds e0 on entry unless e0_zero.
+void cg16(H2& h, Work16& w, int k, const void* rhs, void* e, bool e0_zero, int nsteps) {
+  const int p = w.p, vp = vprec(p);
+  const int64_t N = h.level_size(k), nf = N * NR;
+  const bool pre = w.smoother == 1;
+  if (e0_zero) launch_zero(h, vp, e, nf);
+  if (nsteps <= 0) return;
+  if (e0_zero) {
+    launch_copy(h, vp, rhs, w.s, nf);
+  } else {
+    apply16(h, p, k, e, w.q);
+    launch_copy(h, vp, rhs, w.s, nf);
+    launch_axpby(h, vp, nf, -1.0, w.q, 1.0, w.s);
+  }
+  int cur = 0;
+  if (pre) {
+    launch_bj_apply16(h, p, k, w.s, w.z);
+    launch_copy(h, vp, w.z, w.pv, nf);
+    launch_dot16(h, vp, N, w.s, w.z, w.gpart(cur));
+  } else {
+    launch_copy(h, vp, w.s, w.pv, nf);
+    launch_dot16(h, vp, N, w.s, w.s, w.gpart(cur));
+  }
+  for (int it = 0; it < nsteps; ++it) {
+    apply16(h, p, k, w.pv, w.q);
+    launch_dot16(h, vp, N, w.pv, w.q, w.dpart());
+    if (pre) {
+      launch_cg_update16(h, vp, N, e, w.pv, w.s, w.q, w.gpart(cur), w.dpart(), w.scratch());
+      launch_bj_apply16(h, p, k, w.s, w.z);
+      launch_dot16(h, vp, N, w.s, w.z, w.gpart(1 - cur));
+      if (it + 1 < nsteps) launch_cg_pupdate16(h, vp, N, w.pv, w.z, w.gpart(cur), w.gpart(1 - cur));
+    } else {
+      launch_cg_update16(h, vp, N, e, w.pv, w.s, w.q, w.gpart(cur), w.dpart(), w.gpart(1 - cur));
+      if (it + 1 < nsteps) launch_cg_pupdate16(h, vp, N, w.pv, w.s, w.gpart(cur), w.gpart(1 - cur));
+    }
+    cur = 1 - cur;
+  }
+}
+
+// Direct solve on the coarsest level with the FP64 Cholesky factor.
+void coarse_solve16(H2& h, Work16& w, const void* r, void* e) {
+  const int64_t nf = h.Nl * NR;
+  if (w.p == P64) {
+    launch_copy(h, P64, r, e, nf);
+    launch_chol_solve16(h, h.chol, h.Nl, static_cast<double*>(e));
+  } else {
+    launch_cast(h, P64, w.coarse64, P32, r, nf);
+    launch_chol_solve16(h, h.chol, h.Nl, w.coarse64);
+    launch_cast(h, P32, e, P64, w.coarse64, nf);
+  }
+}
+
+enum Cycle { CYCLE_V = 0, CYCLE_W = 1, CYCLE_F = 2 };
+
+// One cycle on level k for A_k E_k = R_k (w.r[k]); the result in w.et[k].
+void mg16(H2& h, Work16& w, int k, int kind, int n_f, int n_c) {
+  const int p = w.p, vp = vprec(p), l = h.levels;
+  if (k == l) {
+    coarse_solve16(h, w, w.r[l], w.et[l]);
+    return;
+  }
+  const int nk = k == 1 ? n_f : n_c;
+  const int64_t nf = h.level_size(k) * NR;
+  cg16(h, w, k, w.r[k], w.et[k], true, nk);
+  // R_{k+1} = U_k^T (R_k - A_k E~_k)
+  apply16(h, p, k, w.et[k], w.tmp);
+  launch_axpby(h, vp, nf, 1.0, w.r[k], -1.0, w.tmp);
+  if (k == 1) launch_leaf_up16(h, p, w.tmp, w.r[k + 1]);
+  else launch_transfer_up16(h, p, h.level_depth(k) - 1, w.tmp, w.r[k + 1]);
+  mg16(h, w, k + 1, kind, n_f, n_c);
+  if (kind != CYCLE_V && k + 1 < l) {
+    const int64_t nf1 = h.level_size(k + 1) * NR;
+    launch_copy(h, vp, w.et[k + 1], w.ec[k + 1], nf1);
+    apply16(h, p, k + 1, w.et[k + 1], w.tmp);
+    launch_axpby(h, vp, nf1, -1.0, w.tmp, 1.0, w.r[k + 1]);
+    mg16(h, w, k + 1, kind == CYCLE_F ? CYCLE_V : CYCLE_W, n_f, n_c);
+    launch_axpby(h, vp, nf1, 1.0, w.ec[k + 1], 1.0, w.et[k + 1]);
+  }
+  // E~_k += U_k E_{k+1}
+  if (k == 1) launch_leaf_down16(h, p, w.et[k + 1], nullptr, w.et[k], 1.0, w.et[k], 1.0);
+  else launch_transfer_down16(h, p, h.level_depth(k) - 1, w.et[k + 1], w.et[k], w.et[k]);
+  cg16(h, w, k, w.r[k], w.et[k], false, nk);
+}
+
+// ------------------------------------------------------------ solve driver
+// One problem's solve as separate steps, so that several problems can be
+// interleaved on several streams.
+struct BlockSolve {
+  H2* h = nullptr;
+  SolveParams sp;
+  int p = P64, nrhs = 0, np = 0;
+  double* xuser = nullptr;
+  int ldx = 0;
+  Work16 w64, wlp;
+  double* bt = nullptr;
+  double* xt = nullptr;
+  double* npart = nullptr;
+  double* host = nullptr;              // pinned: np x NR partial sums, then 4 flag ints
+  hipEvent_t ev = nullptr;
+  std::vector<double> nb, rel;
+  CycleGraph graph;
+  int cycles = 0;
+  bool converged = false, done = false;
+  h2mg_status status = H2MG_OK;
+  std::chrono::steady_clock::time_point t0;
+
+  ~BlockSolve() { release(); }
+  void release() {
+    if (!h) return;
+    graph.reset();
+    release_work16(*h, w64);
+    release_work16(*h, wlp);
+    for (double* d : {bt, xt, npart})
+      if (d) h->arena.release(d);
+    bt = xt = npart = nullptr;
+    if (host) (void)hipHostFree(host);
+    host = nullptr;
+    if (ev) (void)hipEventDestroy(ev);
+    ev = nullptr;
+    h = nullptr;
+  }
+
+  void read_async() {
+    H2& H = *h;
+    hip_check(hipMemcpyAsync(host, npart, size_t(np) * NR * sizeof(double), hipMemcpyDeviceToHost, H.stream),
+              "norm readback");
+    hip_check(hipMemcpyAsync(host + size_t(np) * NR, H.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, H.stream),
+              "flag readback");
+    hip_check(hipEventRecord(ev, H.stream), "event");
+  }
+  const int* flags() const { return reinterpret_cast<const int*>(host + size_t(np) * NR); }
+  double column_sum(int k) const {
+    double s = 0.0;
+    for (int b = 0; b < np; ++b) s += host[size_t(b) * NR + k];
+    return s;
+  }
+
+  h2mg_status begin(H2& H, int nrhs_, const double* b, int ldb, double* x, int ldx_, const SolveParams& sp_) {
+    t0 = std::chrono::steady_clock::now();
+    sp = sp_;
+    nrhs = nrhs_;
+    xuser = x;
+    ldx = ldx_;
+    p = sp.precision == 0 ? P64 : sp.precision == 1 ? P32 : P16;
+    H.history.clear();
+    h2mg_status st = setup_mg(H, p == P64 ? 0 : (1 << p));
+    if (st != H2MG_OK) return st;
+    if (sp.smoother == 1) {
+      st = ensure_block_jacobi(H, p);
+      if (st != H2MG_OK) return st;
+    }
+    ensure_block(H);
+    ensure_near_lp(H, p);
+    h = &H;
+    const bool second = sp.method == CYCLE_W || sp.method == CYCLE_F;
+    make_work16(H, w64, P64, second && p == P64);
+    w64.smoother = sp.smoother;
+    if (p != P64) {
+      make_work16(H, wlp, p, second);
+      wlp.smoother = sp.smoother;
+    }
+    const int64_t n = H.n;
+    np = parts16(n);
+    bt = static_cast<double*>(H.arena.alloc(size_t(n) * NR * sizeof(double)));
+    xt = static_cast<double*>(H.arena.alloc(size_t(n) * NR * sizeof(double)));
+    npart = static_cast<double*>(H.arena.alloc(size_t(np) * NR * sizeof(double)));
+    hip_check(hipHostMalloc(reinterpret_cast<void**>(&host), size_t(np) * NR * sizeof(double) + 4 * sizeof(int),
+                            hipHostMallocDefault),
+              "pinned alloc");
+    hip_check(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event create");
+    launch_gather16(H, nrhs, b, ldb, bt);
+    if (sp.use_x0) launch_gather16(H, nrhs, x, ldx, xt);
+    else launch_zero(H, P64, xt, n * NR);
+    hip_check(hipMemsetAsync(H.flags, 0, 4 * sizeof(int), H.stream), "memset");
+    launch_check_finite(H, P64, n * NR, bt);
+    launch_dot16(H, P64, n, bt, bt, npart);
+    read_async();
+    hip_check(hipEventSynchronize(ev), "sync");
+    if (flags()[1]) return fail(H2MG_ERR_INVALID_ARG, "B contains a non-finite value");
+    nb.assign(NR, 0.0);
+    rel.assign(NR, 0.0);
+    bool any = false;
+    for (int k = 0; k < nrhs; ++k) {
+      nb[k] = std::sqrt(column_sum(k));
+      any = any || nb[k] > 0.0;
+    }
+    if (!any) {
+      H.history.push_back(0.0);
+      converged = true;
+      done = true;
+    }
+    return H2MG_OK;
+  }
+
+  // R = B - A_H2 X (FP64), its column norms and the flags, read back
+  // asynchronously (complete once `ev` has fired).
+  void enqueue_residual() {
+    apply_fine16(*h, P64, xt, w64.r[1], -1.0, bt, 1.0);
+    launch_dot16(*h, P64, h->n, w64.r[1], w64.r[1], npart);
+    read_async();
+  }
+
+  void check() {
+    double mx = 0.0;
+    for (int k = 0; k < nrhs; ++k) {
+      rel[k] = nb[k] > 0.0 ? std::sqrt(column_sum(k)) / nb[k] : 0.0;
+      if (!(rel[k] <= mx)) mx = rel[k];
+    }
+    h->history.push_back(mx);
+    if (flags()[0]) {
+      status = fail(H2MG_ERR_NOT_SPD, "CG met p^T A p <= 0 (operator not SPD)");
+      done = true;
+    } else if (!std::isfinite(mx)) {
+      status = fail(H2MG_ERR_NUMERIC, "non-finite residual after %d cycles", cycles);
+      done = true;
+    } else if (mx < sp.rtol) {
+      converged = true;
+      done = true;
+    } else if (cycles >= sp.max_cycles) {
+      status = fail(H2MG_ERR_NOT_CONVERGED, "no convergence in %d cycles (rel. residual %.3e)", sp.max_cycles, mx);
+      done = true;
+    }
+  }
+
+  void enqueue_cycle() {
+    H2& H = *h;
+    const int64_t nf = int64_t(H.n) * NR;
+    auto body = [&]() {
+      if (p == P64) {
+        mg16(H, w64, 1, sp.method, sp.n_fine, sp.n_coarse);
+        launch_axpby(H, P64, nf, 1.0, w64.et[1], 1.0, xt);
+      } else {
+        launch_cast(H, P32, wlp.r[1], P64, w64.r[1], nf);
+        mg16(H, wlp, 1, sp.method, sp.n_fine, sp.n_coarse);
+        launch_cast(H, P64, w64.tmp, P32, wlp.et[1], nf);
+        launch_axpby(H, P64, nf, 1.0, w64.tmp, 1.0, xt);
+      }
+    };
+    if (H.graphs && !H.timing) {
+      if (!graph.exec) capture(H, graph, body);
+      hip_check(hipGraphLaunch(graph.exec, H.stream), "graph launch");
+    } else {
+      body();
+    }
+    ++cycles;
+  }
+
+  void finish(h2mg_solve_info* info, double* col_rel) {
+    H2& H = *h;
+    if (xuser) launch_scatter16(H, nrhs, xt, xuser, ldx);
+    hip_check(hipStreamSynchronize(H.stream), "solve");
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) {
+      info->cycles = cycles;
+      info->converged = converged ? 1 : 0;
+      info->rel_residual = H.history.empty() ? 0.0 : H.history.back();
+      info->solve_seconds = secs;
+      info->history_len = int(H.history.size());
+    }
+    if (col_rel)
+      for (int k = 0; k < nrhs; ++k) col_rel[k] = rel[k];
+    release();
+  }
+};
+
+h2mg_status check_block_args(const H2& h, int nrhs, int ldb, int ldx, const SolveParams& sp) {
+  if (nrhs < 1 || nrhs > NR) return fail(H2MG_ERR_INVALID_ARG, "nrhs must be 1..%d (got %d)", NR, nrhs);
+  if (ldb < nrhs || ldx < nrhs) return fail(H2MG_ERR_INVALID_ARG, "leading dimensions must be >= nrhs");
+  if (h.T < 2) return fail(H2MG_ERR_INVALID_ARG, "blocks of vectors need a rank of 9 to 64 (got %d)", h.r);
+  if (!h.snear.ready) return fail(H2MG_ERR_STATE, "blocks of vectors need h2mg_store_near first");
+  if (sp.method > CYCLE_F) return fail(H2MG_ERR_INVALID_ARG, "blocks of vectors are solved by V-, W- or F-cycles");
+  return H2MG_OK;
+}
+
+}  // namespace
+
+h2mg_status matvec_multi(H2& h, int nrhs, const double* x, int ldx, double* y, int ldy) {
+  if (nrhs < 1 || nrhs > NR) return fail(H2MG_ERR_INVALID_ARG, "nrhs must be 1..%d (got %d)", NR, nrhs);
+  if (ldx < nrhs || ldy < nrhs) return fail(H2MG_ERR_INVALID_ARG, "leading dimensions must be >= nrhs");
+  if (h.T < 2) return fail(H2MG_ERR_INVALID_ARG, "products with vector blocks need a rank of 9 to 64 (got %d)", h.r);
+  if (!h.snear.ready) return fail(H2MG_ERR_STATE, "products with vector blocks need h2mg_store_near first");
+  try {
+    ensure_block(h);
+    BlockWork& w = h.blk16;
+    launch_gather16(h, nrhs, x, ldx, w.bx);
+    apply_fine16(h, P64, w.bx, w.by, 1.0, nullptr, 0.0);
+    launch_scatter16(h, nrhs, w.by, y, ldy);
+  } catch (const std::bad_alloc&) {
+    return fail(H2MG_ERR_OOM, "device allocation failed for the vector-block product");
+  } catch (const std::exception& ex) {
+    return fail(H2MG_ERR_HIP, "%s", ex.what());
+  }
+  return H2MG_OK;
+}
+
+h2mg_status solve_multi(H2& h, int nrhs, const double* b, int ldb, double* x, int ldx, const SolveParams& sp,
+                        h2mg_solve_info* info, double* col_rel) {
+  h2mg_status st = check_block_args(h, nrhs, ldb, ldx, sp);
+  if (st != H2MG_OK) return st;
+  try {
+    BlockSolve bs;
+    st = bs.begin(h, nrhs, b, ldb, x, ldx, sp);
+    if (st != H2MG_OK) return st;
+    while (!bs.done) {
+      bs.enqueue_residual();
+      hip_check(hipEventSynchronize(bs.ev), "sync");
+      bs.check();
+      if (!bs.done) bs.enqueue_cycle();
+    }
+    st = bs.status;
+    bs.finish(info, col_rel);
+  } catch (const std::bad_alloc&) {
+    return fail(H2MG_ERR_OOM, "device allocation failed in the block solve");
+  } catch (const std::exception& ex) {
+    return fail(H2MG_ERR_HIP, "%s", ex.what());
+  }
+  return st;
+}
+
+h2mg_status solve_batch(int nprob, H2* const* hs, const int* nrhs, const double* const* b, const int* ldb,
+                        double* const* x, const int* ldx, const SolveParams& sp, h2mg_solve_info* infos,
+                        int nstreams, hipStream_t user) {
+  if (nprob < 1) return fail(H2MG_ERR_INVALID_ARG, "a batch needs at least one problem");
+  for (int i = 0; i < nprob; ++i) {
+    if (!hs[i] || !b[i] || !x[i]) return fail(H2MG_ERR_INVALID_ARG, "null argument in problem %d", i);
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return fail(H2MG_ERR_INVALID_ARG, "problems %d and %d share a handle", j, i);
+    h2mg_status st = check_block_args(*hs[i], nrhs[i], ldb[i], ldx[i], sp);
+    if (st != H2MG_OK) return st;
+  }
+  const int ns = std::max(1, std::min(nstreams > 0 ? nstreams : 4, nprob));
+  std::vector<hipStream_t> streams(ns, nullptr);
+  std::vector<hipStream_t> saved(nprob);
+  for (int i = 0; i < nprob; ++i) saved[i] = hs[i]->stream;
+  hipEvent_t start = nullptr;
+  std::vector<h2mg_status> result(nprob, H2MG_OK);
+  std::vector<std::string> message(nprob);
+  std::vector<std::unique_ptr<BlockSolve>> bs(nprob);
+  auto record = [&](int i, h2mg_status st) {
+    if (st != H2MG_OK && result[i] == H2MG_OK) {
+      result[i] = st;
+      message[i] = last_error_cstr();
+    }
+  };
+  auto cleanup = [&]() {
+    for (auto& s : bs) s.reset();
+    for (int i = 0; i < nprob; ++i) hs[i]->stream = saved[i];
+    for (hipStream_t s : streams)
+      if (s) (void)hipStreamDestroy(s);
+    if (start) (void)hipEventDestroy(start);
+  };
+  h2mg_status err = H2MG_OK;
+  try {
+    hip_check(hipEventCreateWithFlags(&start, hipEventDisableTiming), "event create");
+    hip_check(hipEventRecord(start, user), "event");
+    for (int s = 0; s < ns; ++s) {
+      hip_check(hipStreamCreateWithFlags(&streams[s], hipStreamNonBlocking), "stream create");
+      hip_check(hipStreamWaitEvent(streams[s], start, 0), "stream wait");
+    }
+    for (int i = 0; i < nprob; ++i) hs[i]->stream = streams[i % ns];
+    for (int i = 0; i < nprob; ++i) {
+      bs[i].reset(new BlockSolve);
+      const h2mg_status st = bs[i]->begin(*hs[i], nrhs[i], b[i], ldb[i], x[i], ldx[i], sp);
+      record(i, st);
+      if (st != H2MG_OK) bs[i].reset();
+      else if (!bs[i]->done) bs[i]->enqueue_residual();
+    }
+    // Round robin: each problem's residual norms are read as soon as its own
+    // stream has produced them, while the other streams keep running.
+    for (bool active = true; active;) {
+      active = false;
+      for (int i = 0; i < nprob; ++i) {
+        if (!bs[i]) continue;
+        if (!bs[i]->done) {
+          hip_check(hipEventSynchronize(bs[i]->ev), "sync");
+          bs[i]->check();
+          record(i, bs[i]->status);
+        }
+        if (bs[i]->done) {
+          bs[i]->finish(infos ? infos + i : nullptr, nullptr);
+          bs[i].reset();
+          continue;
+        }
+        bs[i]->enqueue_cycle();
+        bs[i]->enqueue_residual();
+        active = true;
+      }
+    }
+  } catch (const std::bad_alloc&) {
+    err = H2MG_ERR_OOM;
+  } catch (const std::exception& ex) {
+    err = H2MG_ERR_HIP;
+    message[0] = ex.what();
+  }
+  if (err != H2MG_OK) {
+    (void)hipDeviceSynchronize();
+    cleanup();
+    return err == H2MG_ERR_OOM ? fail(err, "device allocation failed in the batched solve")
+                               : fail(err, "%s", message[0].c_str());
+  }
+  cleanup();
+  for (int i = 0; i < nprob; ++i)
+    if (result[i] != H2MG_OK) return fail(result[i], "problem %d: %s", i, message[i].c_str());
+  return H2MG_OK;
+}
+
+}  // namespace h2mg

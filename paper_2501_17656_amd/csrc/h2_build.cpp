@@ -493,13 +493,14 @@ h2mg_status quadratic_gradient(H2& h, H2* hl, H2* hg, const double* b, const dou
 
 namespace {
 
-void release_multi(H2& h) {
-  for (void* p : h.multi.owned) h.arena.release(p);
-  h.multi = MultiWork();
+// Buffers of the 16-column products and cycles (rebuilt on next use).
+void release_block_work(H2& h) {
+  for (void* p : h.blk16.owned) h.arena.release(p);
+  h.blk16 = BlockWork();
 }
 
 void release_stored_near(H2& h) {
-  release_multi(h);                    // its near-field task lists refer to the tiles
+  release_block_work(h);               // its near-field task lists refer to the tiles
   for (void* p : h.snear.owned) h.arena.release(p);
   h.snear = StoredNear();
 }

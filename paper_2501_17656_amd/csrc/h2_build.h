@@ -15,7 +15,7 @@ h2mg_status setup_mg(H2& h, int precision_mask);
 // go back to evaluating the near field in every product.
 h2mg_status store_near(H2& h, int enable);
 // y = A_H2 x for a block of nrhs <= 16 vectors (device, user order, row-major
-// n x ld), FP64; needs r = 64 and the stored near field.
+// n x ld), FP64; needs 9 <= r <= 64 and the stored near field.
 h2mg_status matvec_multi(H2& h, int nrhs, const double* x, int ldx, double* y, int ldy);
 // H2 matrix of dk/dl (which 1) or g = k'(r)/r (which 2) on the points and
 // tree of h (shift 0).
@@ -56,5 +56,21 @@ h2mg_status smooth_once(H2& h, int level, const double* r, double* e, int nsteps
                         bool use_e0);
 // One FP64 cycle (V, W or F by sp.method) from x0 (user order).
 h2mg_status vcycle_once(H2& h, const double* x0, const double* b, double* x_out, const SolveParams& sp);
+// Inverse diagonal blocks of the block-Jacobi smoother (FP64, plus FP32
+// copies when p != P64).
+h2mg_status ensure_block_jacobi(H2& h, int p);
+
+// Blocks of up to 16 right-hand sides (device, user order, row-major n x ld).
+// Solve A_H2 X = B column by column, all columns per cycle; col_rel (host,
+// nrhs entries, may be null) receives each column's final relative residual.
+h2mg_status solve_multi(H2& h, int nrhs, const double* b, int ldb, double* x, int ldx,
+                        const SolveParams& sp, h2mg_solve_info* info, double* col_rel);
+// Independent problems solved together: problem i on handle hs[i] (distinct
+// handles), with its cycles on one of nstreams streams; every stream first
+// waits for the work enqueued so far on `user`.  Returns the first failing
+// problem's status (the others still run to their end).
+h2mg_status solve_batch(int nprob, H2* const* hs, const int* nrhs, const double* const* b, const int* ldb,
+                        double* const* x, const int* ldx, const SolveParams& sp, h2mg_solve_info* infos,
+                        int nstreams, hipStream_t user);
 
 }  // namespace h2mg

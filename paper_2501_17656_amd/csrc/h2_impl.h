@@ -118,31 +118,47 @@ struct StoredNear {
   std::vector<void*> owned;            // device allocations of this structure
 };
 
-// Buffers and task lists of products with a block of MULTI_NR vectors
-// (built on first use).  Row-pass tasks are the single-vector tasks;
-// column-pass tasks are runs of at most 16 off-diagonal tiles of one block
-// column, over `order` (tile ids by column).
-struct MultiWork {
-  bool ready = false;
-  double* x = nullptr;                 // n x NR, tree order
-  double* y = nullptr;
-  double* xall = nullptr;              // ngid * r x NR
-  double* yall = nullptr;
-  double* partial = nullptr;           // max tasks x 64 x NR
-  int64_t partial_tasks = 0;
-  // couplings (all depths)
-  int* rtp = nullptr;                  // ngid + 1: row-pass tasks of each gid
-  int* ctp = nullptr;                  // ngid + 1: column-pass tasks of each gid
+// One set of stored tiles multiplied at once with a block of MULTI_NR
+// vectors: row-pass tasks (block row, i0, i1) over `rorder` (tile ids by
+// block row), column-pass tasks (block column, i0, i1) over `corder` (the
+// off-diagonal tile ids by block column), at most `run` tiles per task, and
+// per-row task ranges for the reduce.  Rows are gids for coupling and
+// projected close tiles, chunks for near-field tiles.
+struct TileSet {
+  int nrt = 0, nct = 0;                // row-pass and column-pass tasks
+  int* rtask = nullptr;                // device: 3 ints per task
+  int* rorder = nullptr;
   int* ctask = nullptr;
   int* corder = nullptr;
-  int nctask = 0;
-  // stored near field
-  int* near_ctp = nullptr;             // nchunk + 1
-  int* near_ctask = nullptr;
-  int* near_corder = nullptr;
-  int near_nctask = 0;
-  double* xc = nullptr;                // nchunk * 64 x NR (null when the chunk order is the tree order)
-  double* yc = nullptr;
+  int* rtp = nullptr;                  // device: rows + 1 row-pass task offsets
+  int* ctp = nullptr;                  // device: rows + 1 column-pass task offsets
+  const int* brow = nullptr;           // device: block row / column of every tile
+  const int* bcol = nullptr;
+  int row0 = 0, nrows = 0;             // rows the reduce writes
+  int64_t ntiles = 0;                  // tiles in the set (each read by the row pass)
+  int64_t nctiles = 0;                 // off-diagonal tiles (read again by the column pass)
+};
+
+// Buffers and task sets of the products and cycles on blocks of MULTI_NR
+// vectors (built on first use).
+struct BlockWork {
+  bool ready = false;
+  bool coarse_ready = false;
+  bool near_ready = false;
+  int run = 8;                         // tiles per task
+  TileSet fine;                        // couplings S of every depth
+  std::vector<TileSet> coarse;         // by depth d: S of depths d_top..d and Pi of depth d
+  TileSet near;                        // stored near-field tiles
+  void* partial = nullptr;             // max tasks x rows x NR (sized for FP64)
+  int64_t partial_elems = 0;
+  void* xall = nullptr;                // ngid * r x NR (FP64 size; reused by FP32)
+  void* yall = nullptr;
+  double* xc64 = nullptr;              // nchunk * 64 x NR (null when the chunk order is the tree order)
+  float* xc32 = nullptr;
+  void* yc = nullptr;                  // nchunk * 64 x NR
+  void* near_lp[3] = {nullptr, nullptr, nullptr};   // FP32 copy of the near tiles (slot P32)
+  double* bx = nullptr;                // n x NR staging blocks of the product entry point
+  double* by = nullptr;
   std::vector<void*> owned;
 };
 
@@ -189,7 +205,7 @@ struct H2 {
   std::vector<View> sview, pview;
   NearField near;
   StoredNear snear;
-  MultiWork multi;
+  BlockWork blk16;
   PrecData prec[3];
 
   // launches: fine apply (S of all depths), coarse apply at depth d
@@ -258,6 +274,7 @@ void launch_assemble_kernel_dense(H2& h, double* A, int64_t lda);  // no far blo
 void launch_potrf(H2& h, double* A, int64_t N);   // blocked Cholesky, sets flags[0]
 void launch_cast_precision(H2& h, int p);         // FP64 -> FP32 / BF16 copies
 void launch_near_tiles(H2& h);                    // stored near-field tiles (FP64)
+void launch_cast_near_tiles(H2& h, int p, void* dst);   // FP32 / BF16 copies of them
 // Inverses of the block-Jacobi blocks: leaf blocks K_ss + shift (FP64) and the
 // projected diagonal blocks of depths d_top+1..L (FP64); sets flags[0] on a
 // non-positive pivot.
@@ -292,18 +309,31 @@ void launch_leaf_down(H2& h, int p, const void* yhat, void* out, double alpha, c
 void launch_fine_reduce(H2& h, int p, const void* yhat, void* out, bool to_user,
                         double alpha, const void* add, double beta, const void* xin);
 
-// ------------------------------------------------------------ blocks of 16 vectors (FP64, r = 64)
-void launch_gemm16(H2& h, bool rows, const int* tasks, int ntasks, const double* tiles,
-                   const int* order, const int* other, const double* x, double* partial);
-void launch_reduce16(H2& h, int nrows, const int* rtp, const int* ctp, int cbase, const double* partial,
-                     double* out);
+// ------------------------------------------------------------ blocks of 16 vectors
+// Vectors of precision p: double for P64, float otherwise; tiles of the
+// operator precision.  Row-major blocks (entry (i, k) at i * 16 + k).
+int parts16(int64_t nrows);            // partial sums of a per-column dot
+// tp: precision of the tiles (FP64 tiles with FP64 vectors, FP32 or BF16
+// tiles with FP32 vectors).
+void launch_tgemm(H2& h, int tp, int T, const TileSet& ts, const void* tiles, int rr, const void* x,
+                  void* partial);
+void launch_reduce16(H2& h, int p, const TileSet& ts, int rr, const void* partial, void* out);
 void launch_gather16(H2& h, int nrhs, const double* user, int ldu, double* tree);
 void launch_scatter16(H2& h, int nrhs, const double* tree, double* user, int ldu);
-void launch_leaf_up16(H2& h, const double* x, double* xhat);
-void launch_transfer_up16(H2& h, int d, const double* xchild, double* xpar);
-void launch_transfer_down16(H2& h, int d, const double* ypar, double* ychild, const double* addend);
-void launch_fine_reduce16(H2& h, const double* yhat, const double* near_y, double* y);
-void launch_near_pad16(H2& h, const double* x, double* xc);
+void launch_leaf_up16(H2& h, int p, const void* x, void* xhat);
+// out = alpha * (Q yhat + near) + beta * add (tree order; yhat, near may be null)
+void launch_leaf_down16(H2& h, int p, const void* yhat, const void* near_y, void* out, double alpha,
+                        const void* add, double beta);
+void launch_transfer_up16(H2& h, int p, int d, const void* xchild, void* xpar);
+void launch_transfer_down16(H2& h, int p, int d, const void* ypar, void* ychild, const void* addend);
+void launch_near_pad16(H2& h, int p, const void* x, void* xc);
+void launch_dot16(H2& h, int p, int64_t nrows, const void* x, const void* y, double* part);
+void launch_cg_update16(H2& h, int p, int64_t nrows, void* e, const void* pv, void* s, const void* q,
+                        const double* gpart, const double* dpart, double* gnew);
+void launch_cg_pupdate16(H2& h, int p, int64_t nrows, void* pv, const void* s, const double* gold,
+                         const double* gnew);
+void launch_bj_apply16(H2& h, int p, int k, const void* s, void* z);
+void launch_chol_solve16(H2& h, const double* L, int64_t N, double* x);   // in place, FP64
 
 // ------------------------------------------------------------ boundary elements
 // Per triangle (vertex rows V, index triples T): centroid y (nt x 3), scale

@@ -17,6 +17,7 @@
 #include <stdexcept>
 #include <vector>
 
+#include "graph.h"
 #include "h2_build.h"
 
 namespace h2mg {
@@ -78,40 +79,6 @@ void release_work(H2& h, Work& w) {
 
 void zero(H2& h, void* v, int64_t n, int p) { launch_zero(h, p, v, n); }
 
-// A captured cycle: instantiated once per solve, launched once per cycle.
-struct CycleGraph {
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  ~CycleGraph() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-  }
-};
-
-// Record the launches of body() into g on the handle's private capture
-// stream (the caller's stream may be the null stream, which cannot be
-// captured), then instantiate it.
-template <typename F>
-void capture(H2& h, CycleGraph& g, F&& body) {
-  hipStream_t user = h.stream;
-  if (!h.capture_stream)
-    hip_check(hipStreamCreateWithFlags(&h.capture_stream, hipStreamNonBlocking), "stream create");
-  h.stream = h.capture_stream;
-  hip_check(hipStreamBeginCapture(h.capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
-  try {
-    body();
-  } catch (...) {
-    hipGraph_t partial = nullptr;
-    (void)hipStreamEndCapture(h.capture_stream, &partial);
-    if (partial) (void)hipGraphDestroy(partial);
-    h.stream = user;
-    throw;
-  }
-  h.stream = user;
-  hip_check(hipStreamEndCapture(h.capture_stream, &g.graph), "end capture");
-  hip_check(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0), "graph instantiate");
-}
-
 void read_flags(H2& h, int* f) {
   hip_check(hipMemcpyAsync(f, h.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, h.stream), "flags");
   hip_check(hipStreamSynchronize(h.stream), "sync");
@@ -157,54 +124,6 @@ void cg(H2& h, int p, int k, Work& w, const void* rhs, void* e, bool e0_zero, in
     }
     cur = 1 - cur;
   }
-}
-
-// Inverse diagonal blocks for the block-Jacobi smoother (built once per
-// handle; FP32 copies for the low-precision forms).
-h2mg_status ensure_block_jacobi(H2& h, int p) {
-  if (!h.bj_built[P64]) {
-    if (h.leaf_max > 128)
-      return fail(H2MG_ERR_INVALID_ARG,
-                  "the block smoother needs leaves of at most 128 points (largest has %d)",
-                  h.leaf_max);
-    h.bj_ld = h.leaf_max;
-    double* fine = h.arena.make<double>(size_t(h.nleaf) * h.bj_ld * h.bj_ld);
-    double* coarse = h.arena.make<double>(size_t(h.ngid) * h.r * h.r);
-    hip_check(hipMemsetAsync(h.flags, 0, 4 * sizeof(int), h.stream), "memset");
-    launch_bj_inverse_fine(h, fine, h.bj_ld);
-    for (int d = h.d_top + 1; d <= h.L && h.d_top >= 0; ++d) {
-      std::vector<int> diag;
-      for (int b = h.p_first[d]; b < h.p_first[d] + h.p_count[d]; ++b)
-        if (h.blk_row_h[b] == h.blk_col_h[b]) diag.push_back(b);
-      if (int(diag.size()) != (1 << d)) return fail(H2MG_ERR_STATE, "missing diagonal block at depth %d", d);
-      int* dd = h.arena.make<int>(diag.size());
-      hip_check(hipMemcpyAsync(dd, diag.data(), diag.size() * sizeof(int), hipMemcpyHostToDevice, h.stream),
-                "upload");
-      launch_bj_inverse_coarse(h, d, dd, coarse);
-      hip_check(hipStreamSynchronize(h.stream), "bj");
-      h.arena.release(dd);
-    }
-    int f[4];
-    read_flags(h, f);
-    if (f[0]) {
-      h.arena.release(fine);
-      h.arena.release(coarse);
-      return fail(H2MG_ERR_NOT_SPD, "a diagonal block of the block smoother is not positive definite");
-    }
-    h.bj_fine[P64] = fine;
-    h.bj_coarse[P64] = coarse;
-    h.bj_built[P64] = true;
-  }
-  if (p != P64 && !h.bj_built[P32]) {
-    const int64_t nf = int64_t(h.nleaf) * h.bj_ld * h.bj_ld, nc = int64_t(h.ngid) * h.r * h.r;
-    h.bj_fine[P32] = h.arena.alloc(size_t(nf) * 4);
-    h.bj_coarse[P32] = h.arena.alloc(size_t(nc) * 4);
-    launch_cast(h, P32, h.bj_fine[P32], P64, h.bj_fine[P64], nf);
-    launch_cast(h, P32, h.bj_coarse[P32], P64, h.bj_coarse[P64], nc);
-    hip_check(hipStreamSynchronize(h.stream), "bj cast");
-    h.bj_built[P32] = true;
-  }
-  return H2MG_OK;
 }
 
 // Direct solve on the coarsest level (FP64 Cholesky factor): e = A_l^{-1} r.
@@ -337,6 +256,54 @@ h2mg_status plain_cg(H2& h, Work& w, const double* bt, double* xt, double nb, co
 }
 
 }  // namespace
+
+// Inverse diagonal blocks for the block-Jacobi smoother (built once per
+// handle; FP32 copies for the low-precision forms).
+h2mg_status ensure_block_jacobi(H2& h, int p) {
+  if (!h.bj_built[P64]) {
+    if (h.leaf_max > 128)
+      return fail(H2MG_ERR_INVALID_ARG,
+                  "the block smoother needs leaves of at most 128 points (largest has %d)",
+                  h.leaf_max);
+    h.bj_ld = h.leaf_max;
+    double* fine = h.arena.make<double>(size_t(h.nleaf) * h.bj_ld * h.bj_ld);
+    double* coarse = h.arena.make<double>(size_t(h.ngid) * h.r * h.r);
+    hip_check(hipMemsetAsync(h.flags, 0, 4 * sizeof(int), h.stream), "memset");
+    launch_bj_inverse_fine(h, fine, h.bj_ld);
+    for (int d = h.d_top + 1; d <= h.L && h.d_top >= 0; ++d) {
+      std::vector<int> diag;
+      for (int b = h.p_first[d]; b < h.p_first[d] + h.p_count[d]; ++b)
+        if (h.blk_row_h[b] == h.blk_col_h[b]) diag.push_back(b);
+      if (int(diag.size()) != (1 << d)) return fail(H2MG_ERR_STATE, "missing diagonal block at depth %d", d);
+      int* dd = h.arena.make<int>(diag.size());
+      hip_check(hipMemcpyAsync(dd, diag.data(), diag.size() * sizeof(int), hipMemcpyHostToDevice, h.stream),
+                "upload");
+      launch_bj_inverse_coarse(h, d, dd, coarse);
+      hip_check(hipStreamSynchronize(h.stream), "bj");
+      h.arena.release(dd);
+    }
+    int f[4];
+    read_flags(h, f);
+    if (f[0]) {
+      h.arena.release(fine);
+      h.arena.release(coarse);
+      return fail(H2MG_ERR_NOT_SPD, "a diagonal block of the block smoother is not positive definite");
+    }
+    h.bj_fine[P64] = fine;
+    h.bj_coarse[P64] = coarse;
+    h.bj_built[P64] = true;
+  }
+  if (p != P64 && !h.bj_built[P32]) {
+    const int64_t nf = int64_t(h.nleaf) * h.bj_ld * h.bj_ld, nc = int64_t(h.ngid) * h.r * h.r;
+    h.bj_fine[P32] = h.arena.alloc(size_t(nf) * 4);
+    h.bj_coarse[P32] = h.arena.alloc(size_t(nc) * 4);
+    launch_cast(h, P32, h.bj_fine[P32], P64, h.bj_fine[P64], nf);
+    launch_cast(h, P32, h.bj_coarse[P32], P64, h.bj_coarse[P64], nc);
+    hip_check(hipStreamSynchronize(h.stream), "bj cast");
+    h.bj_built[P32] = true;
+  }
+  return H2MG_OK;
+}
 
 h2mg_status solve(H2& h, const double* b, double* x, const SolveParams& sp, h2mg_solve_info* info) {
   const auto t0 = std::chrono::steady_clock::now();

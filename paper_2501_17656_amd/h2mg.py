@@ -36,6 +36,15 @@ def _dev_f64(t, n=None, name="tensor"):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _info_dict(h, info, st, message=""):
+    hist = (ctypes.c_double * max(info.history_len, 1))()
+    lib().h2mg_solve_history(h._h, hist, info.history_len)
+    return {"cycles": info.cycles, "converged": bool(info.converged),
+            "rel_residual": info.rel_residual, "solve_seconds": info.solve_seconds,
+            "history": list(hist)[:info.history_len], "status": _lib.STATUS.get(st, st),
+            "message": message}
+
+
 class Plan:
     """Host-side cluster tree and block partition of a point set."""
 
@@ -140,8 +149,8 @@ class H2Matrix:
         return y
 
     def matvec_multi(self, X, out=None):
-        """Y = A_H2 X for X of shape (n, nrhs), nrhs <= 16 (FP64; needs rank
-        64 and store_near())."""
+        """Y = A_H2 X for X of shape (n, nrhs), nrhs <= 16 (FP64; needs a rank
+        of 9 to 64 and store_near())."""
         import torch
         if X.dim() != 2 or X.shape[0] != self.n:
             raise ValueError("X must have shape (n, nrhs)")
@@ -232,14 +241,35 @@ class H2Matrix:
         info = _lib.SolveInfo()
         st = lib().h2mg_solve(self._h, _dev_f64(b, self.n, "b"), _dev_f64(x, self.n, "x"),
                               ctypes.byref(o), ctypes.byref(info), _stream())
-        hist = (ctypes.c_double * max(info.history_len, 1))()
-        lib().h2mg_solve_history(self._h, hist, info.history_len)
-        out = {"cycles": info.cycles, "converged": bool(info.converged),
-               "rel_residual": info.rel_residual, "solve_seconds": info.solve_seconds,
-               "history": list(hist)[:info.history_len], "status": _lib.STATUS.get(st, st)}
+        msg = _lib.last_error() if st != 0 else ""
+        out = _info_dict(self, info, st, msg)
         if st != 0 and raise_on_error:
-            check(st)
+            check(st, msg)
         return x, out
+
+    def solve_multi(self, B, rtol: float = 1e-8, n_fine: int = 1, n_coarse: int = 40,
+                    max_cycles: int = 500, precision: str = "fp64", X0=None, raise_on_error: bool = True,
+                    smoother: str = "cg", method: str = "v"):
+        """Solve A_H2 X = B for B of shape (n, nrhs), nrhs <= 16, all columns
+        per cycle (needs a rank of 9 to 64 and store_near()).  Returns
+        (X, info); info["column_residuals"] holds each column's final
+        relative residual."""
+        import torch
+        if B.dim() != 2 or B.shape[0] != self.n:
+            raise ValueError("B must have shape (n, nrhs)")
+        nrhs = int(B.shape[1])
+        X = torch.zeros_like(B) if X0 is None else X0.clone()
+        o = self._opts(rtol, n_fine, n_coarse, max_cycles, precision, X0 is not None, smoother, method)
+        info = _lib.SolveInfo()
+        cr = (ctypes.c_double * nrhs)()
+        st = lib().h2mg_solve_multi(self._h, nrhs, _dev_f64(B, name="B"), nrhs, _dev_f64(X, name="X"), nrhs,
+                                    ctypes.byref(o), ctypes.byref(info), cr, _stream())
+        msg = _lib.last_error() if st != 0 else ""
+        out = _info_dict(self, info, st, msg)
+        out["column_residuals"] = list(cr)
+        if st != 0 and raise_on_error:
+            check(st, msg)
+        return X, out
 
     KERNEL_KINDS = {"gemv_fp64": 0, "gemv_fp32": 1, "gemv_bf16": 2, "near_fp64": 3, "near_fp32": 4,
                     "near_gemv_fp64": 5, "near_gemm16_fp64": 6}
@@ -272,6 +302,38 @@ class H2Matrix:
             self.close()
         except Exception:
             pass
+
+
+def solve_batch(problems, rtol: float = 1e-8, n_fine: int = 1, n_coarse: int = 40, max_cycles: int = 500,
+                precision: str = "fp64", smoother: str = "cg", method: str = "v", nstreams: int = 0,
+                raise_on_error: bool = True):
+    """Solve independent problems together: `problems` is a list of
+    (H2Matrix, B) with B of shape (n_i, nrhs_i), nrhs_i <= 16 (distinct
+    matrices).  Returns (list of X, list of info dicts)."""
+    import torch
+    k = len(problems)
+    hs = (ctypes.c_void_p * k)()
+    nr = (ctypes.c_int32 * k)()
+    bp = (ctypes.c_void_p * k)()
+    xp = (ctypes.c_void_p * k)()
+    xs = []
+    for i, (g, B) in enumerate(problems):
+        if B.dim() != 2 or B.shape[0] != g.n:
+            raise ValueError(f"problem {i}: B must have shape (n, nrhs)")
+        X = torch.zeros_like(B)
+        xs.append(X)
+        hs[i] = g._h
+        nr[i] = int(B.shape[1])
+        bp[i] = _dev_f64(B, name="B").value
+        xp[i] = _dev_f64(X, name="X").value
+    o = H2Matrix._opts(rtol, n_fine, n_coarse, max_cycles, precision, 0, smoother, method)
+    infos = (_lib.SolveInfo * k)()
+    st = lib().h2mg_solve_batch(k, hs, nr, bp, nr, xp, nr, ctypes.byref(o), infos, int(nstreams), _stream())
+    msg = _lib.last_error() if st != 0 else ""
+    out = [_info_dict(g, infos[i], st, msg) for i, (g, _) in enumerate(problems)]
+    if st != 0 and raise_on_error:
+        check(st, msg)
+    return xs, out
 
 
 # ---------------------------------------------------------------- boundary elements

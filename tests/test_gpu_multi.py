@@ -5,7 +5,9 @@ Each column of the block product must equal the single product of that
 column up to rounding order (1e-13 relative) and the oracle to 1e-12 (the
 matvec bar).  Shapes: rank 64 in 3D with leaves of 64 and 128 points (chunk
 order equal to the tree order) and with ragged leaves of 78-79 points (two
-chunks per leaf, the second partial); 1, 5 and 16 columns; no far blocks.
+chunks per leaf, the second partial); rank 27 (32 x 32 padded tiles) and
+rank 16 / rank 9 in 2D (16 x 16 tiles, the latter padded); 1, 5 and 16
+columns; no far blocks.
 """
 import numpy as np
 import pytest
@@ -18,10 +20,13 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 SHAPES = {
-    # name: (n, kernel, length, shift, leaf, eta)
-    "matern3d_leaf64": (16384, "matern32", 0.2, 1e-2, 64, 0.7),
-    "exp3d_leaf128_ragged": (10000, "exp", 0.15, 1e-2, 128, 0.7),
-    "matern3d_no_far": (2048, "matern32", 0.2, 1e-2, 64, 1e-9),
+    # name: (n, dim, kernel, length, shift, leaf, eta, m)
+    "matern3d_leaf64": (16384, 3, "matern32", 0.2, 1e-2, 64, 0.7, 4),
+    "exp3d_leaf128_ragged": (10000, 3, "exp", 0.15, 1e-2, 128, 0.7, 4),
+    "matern3d_no_far": (2048, 3, "matern32", 0.2, 1e-2, 64, 1e-9, 4),
+    "gauss3d_r27": (6000, 3, "gauss", 0.1, 1e-2, 64, 0.7, 3),
+    "exp2d_r16": (4096, 2, "exp", 0.1, 1e-2, 64, 0.7, 4),
+    "exp2d_r9_ragged": (1200, 2, "exp", 0.1, 1e-2, 32, 0.7, 3),
 }
 
 
@@ -37,12 +42,12 @@ def _host(t):
 @pytest.mark.parametrize("name", list(SHAPES))
 def test_block_product_matches_single_products_and_oracle(name):
     from paper_2501_17656_amd import H2Matrix
-    n, ker, ell, shift, leaf, eta = SHAPES[name]
-    P = synth.uniform_points(n, 3, 21)
-    print(f"[gpu] build {name} n={n} leaf={leaf} rank 64", flush=True)
-    g = H2Matrix(_dev(P), ker, ell, shift, leaf, eta, 4)
+    n, dim, ker, ell, shift, leaf, eta, m = SHAPES[name]
+    P = synth.uniform_points(n, dim, 21)
+    print(f"[gpu] build {name} n={n} leaf={leaf} rank {m ** dim}", flush=True)
+    g = H2Matrix(_dev(P), ker, ell, shift, leaf, eta, m)
     g.store_near(True)
-    o = OracleH2(P, ker, shift, leaf, eta, 4, ell)
+    o = OracleH2(P, ker, shift, leaf, eta, m, ell)
     X = synth.normal_vector(n, 22, nrhs=16)
     for nrhs in (1, 5, 16):
         Xk = np.ascontiguousarray(X[:, :nrhs])
@@ -64,7 +69,7 @@ def test_block_product_matches_single_products_and_oracle(name):
 def test_block_product_argument_errors():
     from paper_2501_17656_amd import H2Matrix, H2MGError
     P = synth.uniform_points(4096, 2, 3)
-    g = H2Matrix(_dev(P), "exp", 0.1, 1e-2, 64, 0.7, 4)            # rank 16
+    g = H2Matrix(_dev(P), "exp", 0.1, 1e-2, 64, 0.7, 2)            # rank 4: tiles too small
     g.store_near(True)
     with pytest.raises(H2MGError):
         g.matvec_multi(_dev(np.zeros((4096, 4))))
