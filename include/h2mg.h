@@ -294,11 +294,14 @@ h2mg_status h2mg_store_near(h2mg_h2_t h, int32_t enable, hipStream_t stream);
  * products run 16 columns at a time on the matrix cores; each stored tile is
  * read at most twice per product (once for its block row, once for its
  * block column, transposed), so the product streams at most twice the bytes
- * of a single matvec for up to 16 of them.  Requires 9 <= r <= 64 and
- * h2mg_store_near.  Results equal 16 single products up to rounding order.
- * Errors: INVALID_ARG (null, nrhs or ld out of range, rank out of range),
- * STATE (near field not stored), OOM (about 1 GB of block buffers per 2^20
- * points, plus 8 KB per tile task, allocated on first use and kept), HIP. */
+ * of a single matvec for up to 16 of them.  The near-field tiles are the
+ * stored ones after h2mg_store_near, else they are evaluated from the points
+ * inside the product (64 x 64 tiles between chunks of at most 64 points of a
+ * leaf; no near-field storage).  Requires 9 <= r <= 64.  Results equal 16
+ * single products up to rounding order.  Errors: INVALID_ARG (null, nrhs or
+ * ld out of range, rank out of range), OOM (about 1 GB of block buffers per
+ * 2^20 points, plus 8 KB per tile task, allocated on first use and kept),
+ * HIP. */
 h2mg_status h2mg_matvec_multi(h2mg_h2_t h, int32_t nrhs, const double* x_dev, int32_t ldx,
                               double* y_dev, int32_t ldy, hipStream_t stream);
 
@@ -309,15 +312,17 @@ h2mg_status h2mg_matvec_multi(h2mg_h2_t h, int32_t nrhs, const double* x_dev, in
  * with the CG scalars of the smoother and the stopping test kept per column
  * (cycles run until every column's FP64 relative residual is below rtol).
  * b_dev, x_dev: device, row-major n x ldb and n x ldx, user order.  Stored
- * tiles are multiplied 16 columns at a time on the matrix cores; the
- * low-precision forms use an FP32 copy of the stored near field (made on
- * first use and kept; BF16 rounding of the close blocks, which hold the
- * diagonal, can make the operator indefinite).  opts->method: V, W or F cycles.  info:
- * cycles run, converged (all columns), the largest column residual, time.
- * col_residuals: host, nrhs entries (final relative residual of each column),
- * or null.  Requires 9 <= r <= 64 and h2mg_store_near; runs h2mg_setup_mg
- * itself when needed.  Errors: as h2mg_solve, plus STATE (near field not
- * stored) and INVALID_ARG (nrhs, ld or rank out of range, method CG). */
+ * tiles are multiplied 16 columns at a time on the matrix cores.  The
+ * near-field tiles of the FP64 products are the stored ones after
+ * h2mg_store_near, else evaluated from the points inside each product; the
+ * FP32 and BF16 cycles always evaluate them, in FP32 (BF16 rounding of the
+ * close blocks, which hold the diagonal, can make the operator indefinite).
+ * opts->method: V, W or F cycles.  info: cycles run, converged (all
+ * columns), the largest column residual, time.  col_residuals: host, nrhs
+ * entries (final relative residual of each column), or null.  Requires
+ * 9 <= r <= 64; runs h2mg_setup_mg itself when needed.  Errors: as
+ * h2mg_solve, plus INVALID_ARG (nrhs, ld or rank out of range, method
+ * CG). */
 h2mg_status h2mg_solve_multi(h2mg_h2_t h, int32_t nrhs, const double* b_dev, int32_t ldb,
                              double* x_dev, int32_t ldx, const h2mg_solve_opts* opts,
                              h2mg_solve_info* info, double* col_residuals, hipStream_t stream);
@@ -402,6 +407,23 @@ h2mg_status h2mg_solve_history(h2mg_h2_t h, double* history_host, int32_t capaci
  * Ignored while kernel timing is enabled and by H2MG_METHOD_CG.  Off by
  * default. */
 h2mg_status h2mg_set_graphs(h2mg_h2_t h, int32_t enabled);
+
+/* Tile-run tuning of the 16-column products (h2mg_matvec_multi,
+ * h2mg_solve_multi, h2mg_solve_batch).  Their tile products run as tasks of
+ * consecutive tiles of one block row (or column); a longer run means fewer
+ * partial results to reduce, a shorter one more parallel tasks.  With tuning
+ * on, every task set (the couplings of the fine level, the near-field
+ * chunk tiles, the restricted operator of every depth) is built for each
+ * run length in {2, 4, 8, 16, 32}, its product plus reduce is timed with HIP
+ * events on this device, and the fastest is kept.  Off by default (run 8).
+ * Changing the setting drops the block buffers, which are rebuilt (and, if
+ * on, tuned) at the next 16-column call. */
+h2mg_status h2mg_set_autotune(h2mg_h2_t h, int32_t enabled);
+/* The run length in use for a task set (which = -2: near field, -1: fine-level
+ * couplings, d >= 0: restricted operator of depth d) and its measured time in
+ * ms per product + reduce (0 when not tuned); run = 0 when that set has not
+ * been built yet.  Errors: INVALID_ARG (null, which out of range). */
+h2mg_status h2mg_block_tuning(h2mg_h2_t h, int32_t which, int32_t* run, double* ms);
 
 /* Kernel timing, for measurement harnesses.  While enabled, every launch of
  * the block GEMV and of the near-field kernel is bracketed by HIP events on

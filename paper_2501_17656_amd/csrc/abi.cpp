@@ -413,6 +413,35 @@ h2mg_status h2mg_store_near(h2mg_h2_t hh, int32_t enable, hipStream_t stream) {
   });
 }
 
+h2mg_status h2mg_set_autotune(h2mg_h2_t hh, int32_t enabled) {
+  return guarded([&] {
+    if (!hh) return fail(H2MG_ERR_INVALID_ARG, "null handle");
+    H2& h = *hh->h;
+    if (h.autotune != (enabled != 0)) {
+      (void)hipStreamSynchronize(h.stream);
+      release_block_work(h);
+      h.autotune = enabled != 0;
+    }
+    return H2MG_OK;
+  });
+}
+
+h2mg_status h2mg_block_tuning(h2mg_h2_t hh, int32_t which, int32_t* run, double* ms) {
+  return guarded([&] {
+    if (!hh || !run || !ms) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    const H2& h = *hh->h;
+    const BlockWork& w = h.blk16;
+    const TileSet* ts = nullptr;
+    if (which == -2) ts = w.near_ready ? &w.near : nullptr;
+    else if (which == -1) ts = w.ready ? &w.fine : nullptr;
+    else if (which >= 0 && which < int(w.coarse.size())) ts = &w.coarse[which];
+    else if (which < -2 || which > h.L) return fail(H2MG_ERR_INVALID_ARG, "which must be -2, -1 or a depth");
+    *run = ts ? ts->run : 0;
+    *ms = ts ? ts->tuned_ms : 0.0;
+    return H2MG_OK;
+  });
+}
+
 h2mg_status h2mg_set_graphs(h2mg_h2_t hh, int32_t enabled) {
   return guarded([&] {
     if (!hh) return fail(H2MG_ERR_INVALID_ARG, "null handle");

@@ -22,7 +22,8 @@ namespace h2mg {
 namespace {
 
 constexpr int NR = MULTI_NR;
-constexpr int RUN = 8;                 // tiles per tile-product task
+constexpr int RUN = 8;                 // tiles per tile-product task (without tuning)
+constexpr int RUNS[] = {2, 4, 8, 16, 32};   // candidates of the tuner
 
 void hip_check(hipError_t e, const char* what) {
   if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
@@ -51,8 +52,9 @@ T* upload_owned(H2& h, const std::vector<T>& v) {
 // order within a row or column, and a row's (column's) tasks are
 // consecutive.
 TileSet make_set(H2& h, const std::vector<int>& ids, const std::vector<int>& rows, const std::vector<int>& cols,
-                 int nrows_total, int row0, int nrows, const int* brow, const int* bcol) {
+                 int nrows_total, int row0, int nrows, const int* brow, const int* bcol, int run) {
   TileSet ts;
+  ts.run = run;
   ts.brow = brow;
   ts.bcol = bcol;
   ts.row0 = row0;
@@ -71,10 +73,10 @@ TileSet make_set(H2& h, const std::vector<int>& ids, const std::vector<int>& row
     for (size_t i = 0; i < kb.size();) {
       size_t e = i;
       while (e < kb.size() && kb[e].first == kb[i].first) ++e;
-      for (size_t c = i; c < e; c += RUN) {
+      for (size_t c = i; c < e; c += size_t(run)) {
         tasks.push_back(kb[i].first);
         tasks.push_back(int(c));
-        tasks.push_back(int(std::min(e, c + RUN)));
+        tasks.push_back(int(std::min(e, c + size_t(run))));
         ptr[size_t(kb[i].first) + 1]++;
       }
       i = e;
@@ -108,9 +110,77 @@ void ensure_partial(H2& h, int64_t elems) {
   w.partial_elems = elems;
 }
 
-// Task sets and buffers: couplings (at build), near-field tiles (once they
-// are stored), restricted operators of every depth (once the hierarchy is).
-void ensure_block(H2& h) {
+void free_set(H2& h, TileSet& ts) {
+  BlockWork& w = h.blk16;
+  for (void* d : {static_cast<void*>(ts.rorder), static_cast<void*>(ts.rtask), static_cast<void*>(ts.rtp),
+                  static_cast<void*>(ts.corder), static_cast<void*>(ts.ctask), static_cast<void*>(ts.ctp)}) {
+    auto it = std::find(w.owned.begin(), w.owned.end(), d);
+    if (it != w.owned.end()) {
+      w.owned.erase(it);
+      h.arena.release(d);
+    }
+  }
+  ts = TileSet();
+}
+
+// The tile product and reduce of one set, as run inside a product.
+void run_set(H2& h, int p, const TileSet& ts, bool near, const void* x, void* out) {
+  BlockWork& w = h.blk16;
+  const int rr = near ? 64 : h.r;
+  if (!near) launch_tgemm(h, p, h.T, ts, h.prec[p].blk, rr, x, w.partial);
+  else if (p == P64 && h.snear.ready) launch_tgemm(h, P64, 8, ts, h.snear.tiles, 64, x, w.partial);
+  else launch_tgemm_eval(h, p == P64 ? P64 : P32, ts, x, w.partial);
+  launch_reduce16(h, p, ts, rr, w.partial, out);
+}
+
+// Task set with the run length (tiles per task) that makes this set's tile
+// product plus reduce fastest on this device, measured with HIP events over
+// two launches per candidate (after one untimed); with tuning off, RUN.
+TileSet tuned_set(H2& h, int p, bool near, const void* x, void* out, const std::vector<int>& ids,
+                  const std::vector<int>& rows, const std::vector<int>& cols, int nrows_total, int row0,
+                  int nrows, const int* brow, const int* bcol) {
+  const int rr = near ? 64 : h.r;
+  if (!h.autotune || ids.empty())
+    return make_set(h, ids, rows, cols, nrows_total, row0, nrows, brow, bcol, RUN);
+  hipEvent_t e0, e1;
+  hip_check(hipEventCreate(&e0), "event");
+  hip_check(hipEventCreate(&e1), "event");
+  TileSet best;
+  float best_ms = 0.0f;
+  try {
+    for (int run : RUNS) {
+      TileSet ts = make_set(h, ids, rows, cols, nrows_total, row0, nrows, brow, bcol, run);
+      ensure_partial(h, int64_t(ts.nrt + ts.nct) * rr * NR);
+      run_set(h, p, ts, near, x, out);
+      hip_check(hipEventRecord(e0, h.stream), "event");
+      for (int rep = 0; rep < 2; ++rep) run_set(h, p, ts, near, x, out);
+      hip_check(hipEventRecord(e1, h.stream), "event");
+      hip_check(hipEventSynchronize(e1), "event sync");
+      float ms = 0.0f;
+      hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+      ts.tuned_ms = 0.5 * ms;
+      if (best.rtask == nullptr || ms < best_ms) {
+        if (best.rtask) free_set(h, best);
+        best = ts;
+        best_ms = ms;
+      } else {
+        free_set(h, ts);
+      }
+    }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return best;
+}
+
+// Task sets and buffers: couplings (at first use), near-field chunk plan and
+// tasks, restricted operators of every depth (once the hierarchy is built).
+// p: the precision the sets are tuned for.
+void ensure_block(H2& h, int p) {
   BlockWork& w = h.blk16;
   const int r = h.r;
   if (!w.ready) {
@@ -120,20 +190,23 @@ void ensure_block(H2& h) {
       for (int d = h.d_top; d <= h.L; ++d)
         for (int b = h.s_first[d]; b < h.s_first[d] + h.s_count[d]; ++b) ids.push_back(b);
       const int row0 = (1 << h.d_top) - 1;
-      w.fine = make_set(h, ids, h.blk_row_h, h.blk_col_h, h.ngid, row0, h.ngid - row0, h.blk_row, h.blk_col);
       w.xall = alloc_owned(h, size_t(h.ngid) * r * NR * sizeof(double));
       w.yall = alloc_owned(h, size_t(h.ngid) * r * NR * sizeof(double));
+      hip_check(hipMemsetAsync(w.xall, 0, size_t(h.ngid) * r * NR * sizeof(double), h.stream), "memset");
+      w.fine = tuned_set(h, p, false, w.xall, w.yall, ids, h.blk_row_h, h.blk_col_h, h.ngid, row0,
+                         h.ngid - row0, h.blk_row, h.blk_col);
       ensure_partial(h, int64_t(w.fine.nrt + w.fine.nct) * r * NR);
     }
     w.bx = static_cast<double*>(alloc_owned(h, size_t(h.n) * NR * sizeof(double)));
     w.by = static_cast<double*>(alloc_owned(h, size_t(h.n) * NR * sizeof(double)));
+    hip_check(hipMemsetAsync(w.bx, 0, size_t(h.n) * NR * sizeof(double), h.stream), "memset");
     w.ready = true;
   }
   const StoredNear& sn = h.snear;
-  if (sn.ready && !w.near_ready) {
+  if (!w.near_ready) {
+    plan_near(h);
     std::vector<int> ids(sn.brow_h.size());
     for (size_t b = 0; b < ids.size(); ++b) ids[b] = int(b);
-    w.near = make_set(h, ids, sn.brow_h, sn.bcol_h, sn.nchunk, 0, sn.nchunk, sn.blk_row, sn.blk_col);
     const size_t nv = size_t(sn.nchunk) * 64 * NR;
     if (!sn.identity) {
       w.xc64 = static_cast<double*>(alloc_owned(h, nv * sizeof(double)));
@@ -142,6 +215,10 @@ void ensure_block(H2& h) {
       hip_check(hipMemsetAsync(w.xc32, 0, nv * sizeof(float), h.stream), "memset");
     }
     w.yc = alloc_owned(h, nv * sizeof(double));
+    const void* xn = sn.identity ? static_cast<const void*>(w.bx)
+                                 : p == P64 ? static_cast<const void*>(w.xc64) : static_cast<const void*>(w.xc32);
+    w.near = tuned_set(h, p, true, xn, w.yc, ids, sn.brow_h, sn.bcol_h, sn.nchunk, 0, sn.nchunk, sn.blk_row,
+                       sn.blk_col);
     ensure_partial(h, int64_t(w.near.nrt + w.near.nct) * 64 * NR);
     w.near_ready = true;
   }
@@ -153,25 +230,13 @@ void ensure_block(H2& h) {
       for (int q = h.d_top; q <= d; ++q)
         for (int b = h.s_first[q]; b < h.s_first[q] + h.s_count[q]; ++b) ids.push_back(b);
       for (int b = h.p_first[d]; b < h.p_first[d] + h.p_count[d]; ++b) ids.push_back(b);
-      w.coarse[d] = make_set(h, ids, h.blk_row_h, h.blk_col_h, h.ngid, row0, (2 << d) - 1 - row0, h.blk_row,
-                             h.blk_col);
+      w.coarse[d] = tuned_set(h, p, false, w.xall, w.yall, ids, h.blk_row_h, h.blk_col_h, h.ngid, row0,
+                              (2 << d) - 1 - row0, h.blk_row, h.blk_col);
       ensure_partial(h, int64_t(w.coarse[d].nrt + w.coarse[d].nct) * r * NR);
     }
     w.coarse_ready = true;
   }
   hip_check(hipStreamSynchronize(h.stream), "block setup");
-}
-
-// FP32 copy of the near-field tiles for low-precision cycles.  The BF16
-// form keeps its near field in FP32 as well: the close blocks hold the
-// diagonal, and BF16 rounding of them (2^-9 relative) can exceed the
-// smallest eigenvalue (the shift) and make the operator indefinite.
-void ensure_near_lp(H2& h, int p) {
-  BlockWork& w = h.blk16;
-  if (p == P64 || w.near_lp[P32]) return;
-  w.near_lp[P32] = alloc_owned(h, size_t(h.snear.nblocks) * 4096 * sizeof(float));
-  launch_cast_near_tiles(h, P32, w.near_lp[P32]);
-  hip_check(hipStreamSynchronize(h.stream), "near tile copy");
 }
 
 // Coefficients of depth d inside a gid-indexed block buffer.
@@ -203,11 +268,14 @@ void apply_fine16(H2& h, int p, const void* X, void* out, double alpha, const vo
     launch_near_pad16(h, p, X, buf);
     xc = buf;
   }
-  int ev;
-  if (p == P64) h.time_begin(ev);
-  launch_tgemm(h, p == P64 ? P64 : P32, 8, w.near, p == P64 ? static_cast<const void*>(sn.tiles) : w.near_lp[P32],
-               64, xc, w.partial);
-  if (p == P64) h.time_end(KS_NEAR16, ev, double(w.near.ntiles + w.near.nctiles) * 4096.0 * sizeof(double));
+  if (p == P64 && sn.ready) {
+    int ev;
+    h.time_begin(ev);
+    launch_tgemm(h, P64, 8, w.near, sn.tiles, 64, xc, w.partial);
+    h.time_end(KS_NEAR16, ev, double(w.near.ntiles + w.near.nctiles) * 4096.0 * sizeof(double));
+  } else {
+    launch_tgemm_eval(h, vprec(p), w.near, xc, w.partial);
+  }
   launch_reduce16(h, p, w.near, 64, w.partial, w.yc);
   launch_leaf_down16(h, p, yhat, w.yc, out, alpha, add, beta);
 }
@@ -428,8 +496,7 @@ struct BlockSolve {
       st = ensure_block_jacobi(H, p);
       if (st != H2MG_OK) return st;
     }
-    ensure_block(H);
-    ensure_near_lp(H, p);
+    ensure_block(H, p);
     h = &H;
     const bool second = sp.method == CYCLE_W || sp.method == CYCLE_F;
     make_work16(H, w64, P64, second && p == P64);
@@ -546,7 +613,6 @@ h2mg_status check_block_args(const H2& h, int nrhs, int ldb, int ldx, const Solv
   if (nrhs < 1 || nrhs > NR) return fail(H2MG_ERR_INVALID_ARG, "nrhs must be 1..%d (got %d)", NR, nrhs);
   if (ldb < nrhs || ldx < nrhs) return fail(H2MG_ERR_INVALID_ARG, "leading dimensions must be >= nrhs");
   if (h.T < 2) return fail(H2MG_ERR_INVALID_ARG, "blocks of vectors need a rank of 9 to 64 (got %d)", h.r);
-  if (!h.snear.ready) return fail(H2MG_ERR_STATE, "blocks of vectors need h2mg_store_near first");
   if (sp.method > CYCLE_F) return fail(H2MG_ERR_INVALID_ARG, "blocks of vectors are solved by V-, W- or F-cycles");
   return H2MG_OK;
 }
@@ -557,9 +623,8 @@ h2mg_status matvec_multi(H2& h, int nrhs, const double* x, int ldx, double* y, i
   if (nrhs < 1 || nrhs > NR) return fail(H2MG_ERR_INVALID_ARG, "nrhs must be 1..%d (got %d)", NR, nrhs);
   if (ldx < nrhs || ldy < nrhs) return fail(H2MG_ERR_INVALID_ARG, "leading dimensions must be >= nrhs");
   if (h.T < 2) return fail(H2MG_ERR_INVALID_ARG, "products with vector blocks need a rank of 9 to 64 (got %d)", h.r);
-  if (!h.snear.ready) return fail(H2MG_ERR_STATE, "products with vector blocks need h2mg_store_near first");
   try {
-    ensure_block(h);
+    ensure_block(h, P64);
     BlockWork& w = h.blk16;
     launch_gather16(h, nrhs, x, ldx, w.bx);
     apply_fine16(h, P64, w.bx, w.by, 1.0, nullptr, 0.0);

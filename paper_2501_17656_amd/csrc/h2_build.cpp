@@ -491,13 +491,12 @@ h2mg_status quadratic_gradient(H2& h, H2* hl, H2* hg, const double* b, const dou
   return H2MG_OK;
 }
 
-namespace {
-
-// Buffers of the 16-column products and cycles (rebuilt on next use).
 void release_block_work(H2& h) {
   for (void* p : h.blk16.owned) h.arena.release(p);
   h.blk16 = BlockWork();
 }
+
+namespace {
 
 void release_stored_near(H2& h) {
   release_block_work(h);               // its near-field task lists refer to the tiles
@@ -506,6 +505,88 @@ void release_stored_near(H2& h) {
 }
 
 }  // namespace
+
+void plan_near(H2& h) {
+  StoredNear& sn = h.snear;
+  if (sn.planned) return;
+  auto own = [&](auto* p) {
+    sn.owned.push_back(static_cast<void*>(p));
+    return p;
+  };
+  const Plan& P = h.plan;
+  const auto& off = P.offsets[h.L];
+  // chunks of at most 64 points per leaf
+  std::vector<int> cbase(h.nleaf + 1, 0), cstart, cn;
+  sn.identity = true;
+  for (int s = 0; s < h.nleaf; ++s) {
+    const int s0 = int(off[s]), ns = int(off[s + 1] - off[s]);
+    const int k = (ns + 63) / 64;
+    if (ns % 64 != 0) sn.identity = false;
+    for (int q = 0; q < k; ++q) {
+      cstart.push_back(s0 + 64 * q);
+      cn.push_back(std::min(64, ns - 64 * q));
+    }
+    cbase[s + 1] = cbase[s] + k;
+  }
+  sn.nchunk = cbase[h.nleaf];
+  // tiles sorted by (row chunk, column chunk): row leaf, its row chunk,
+  // then the leaf's close partners t >= s in order, then their chunks
+  const auto& lst = P.near[h.L];
+  std::vector<int> brow, bcol;
+  for (size_t p = 0; p < lst.size();) {
+    const int64_t s = lst[p];
+    size_t e = p;
+    while (e < lst.size() && lst[e] == s) e += 2;
+    const int ks = cbase[s + 1] - cbase[s];
+    for (int i = 0; i < ks; ++i)
+      for (size_t q = p; q < e; q += 2) {
+        const int64_t t = lst[q + 1];
+        if (t < s) continue;
+        for (int j = (t == s ? i : 0); j < cbase[t + 1] - cbase[t]; ++j) {
+          brow.push_back(cbase[s] + i);
+          bcol.push_back(cbase[t] + j);
+        }
+      }
+    p = e;
+  }
+  sn.nblocks = int64_t(brow.size());
+  // tasks of at most CHUNK tiles of one row chunk; column slots by column
+  std::vector<int> task, rtp(sn.nchunk + 1, 0), cptr(sn.nchunk + 1, 0), slot(brow.size(), -1);
+  for (size_t b = 0; b < brow.size();) {
+    size_t e = b;
+    while (e < brow.size() && brow[e] == brow[b]) ++e;
+    for (size_t c = b; c < e; c += CHUNK) {
+      task.push_back(brow[b]);
+      task.push_back(int(c));
+      task.push_back(int(std::min(e, c + CHUNK)));
+      rtp[brow[b] + 1]++;
+    }
+    b = e;
+  }
+  for (int i = 0; i < sn.nchunk; ++i) rtp[i + 1] += rtp[i];
+  for (size_t b = 0; b < brow.size(); ++b)
+    if (bcol[b] != brow[b]) cptr[bcol[b] + 1]++;
+  for (int i = 0; i < sn.nchunk; ++i) cptr[i + 1] += cptr[i];
+  std::vector<int> fill(cptr.begin(), cptr.end() - 1);
+  for (size_t b = 0; b < brow.size(); ++b)
+    if (bcol[b] != brow[b]) slot[b] = fill[bcol[b]]++;
+  sn.nslot = cptr[sn.nchunk];
+  sn.ntasks = int(task.size() / 3);
+
+  sn.brow_h = brow;
+  sn.bcol_h = bcol;
+  sn.chunk_base = own(upload(h, cbase));
+  sn.chunk_start = own(upload(h, cstart));
+  sn.chunk_n = own(upload(h, cn));
+  sn.blk_row = own(upload(h, brow));
+  sn.blk_col = own(upload(h, bcol));
+  sn.blk_slot = own(upload(h, slot));
+  sn.task = own(upload(h, task));
+  sn.row_task_ptr = own(upload(h, rtp));
+  sn.col_ptr = own(upload(h, cptr));
+  hip_check(hipStreamSynchronize(h.stream), "near plan");
+  sn.planned = true;
+}
 
 h2mg_status store_near(H2& h, int enable) {
   if (!enable) {
@@ -520,77 +601,7 @@ h2mg_status store_near(H2& h, int enable) {
     return p;
   };
   try {
-    const Plan& P = h.plan;
-    const auto& off = P.offsets[h.L];
-    // chunks of at most 64 points per leaf
-    std::vector<int> cbase(h.nleaf + 1, 0), cstart, cn;
-    sn.identity = true;
-    for (int s = 0; s < h.nleaf; ++s) {
-      const int s0 = int(off[s]), ns = int(off[s + 1] - off[s]);
-      const int k = (ns + 63) / 64;
-      if (ns % 64 != 0) sn.identity = false;
-      for (int q = 0; q < k; ++q) {
-        cstart.push_back(s0 + 64 * q);
-        cn.push_back(std::min(64, ns - 64 * q));
-      }
-      cbase[s + 1] = cbase[s] + k;
-    }
-    sn.nchunk = cbase[h.nleaf];
-    // tiles sorted by (row chunk, column chunk): row leaf, its row chunk,
-    // then the leaf's close partners t >= s in order, then their chunks
-    const auto& lst = P.near[h.L];
-    std::vector<int> brow, bcol;
-    for (size_t p = 0; p < lst.size();) {
-      const int64_t s = lst[p];
-      size_t e = p;
-      while (e < lst.size() && lst[e] == s) e += 2;
-      const int ks = cbase[s + 1] - cbase[s];
-      for (int i = 0; i < ks; ++i)
-        for (size_t q = p; q < e; q += 2) {
-          const int64_t t = lst[q + 1];
-          if (t < s) continue;
-          for (int j = (t == s ? i : 0); j < cbase[t + 1] - cbase[t]; ++j) {
-            brow.push_back(cbase[s] + i);
-            bcol.push_back(cbase[t] + j);
-          }
-        }
-      p = e;
-    }
-    sn.nblocks = int64_t(brow.size());
-    // tasks of at most CHUNK tiles of one row chunk; column slots by column
-    std::vector<int> task, rtp(sn.nchunk + 1, 0), cptr(sn.nchunk + 1, 0), slot(brow.size(), -1);
-    for (size_t b = 0; b < brow.size();) {
-      size_t e = b;
-      while (e < brow.size() && brow[e] == brow[b]) ++e;
-      for (size_t c = b; c < e; c += CHUNK) {
-        task.push_back(brow[b]);
-        task.push_back(int(c));
-        task.push_back(int(std::min(e, c + CHUNK)));
-        rtp[brow[b] + 1]++;
-      }
-      b = e;
-    }
-    for (int i = 0; i < sn.nchunk; ++i) rtp[i + 1] += rtp[i];
-    for (size_t b = 0; b < brow.size(); ++b)
-      if (bcol[b] != brow[b]) cptr[bcol[b] + 1]++;
-    for (int i = 0; i < sn.nchunk; ++i) cptr[i + 1] += cptr[i];
-    std::vector<int> fill(cptr.begin(), cptr.end() - 1);
-    for (size_t b = 0; b < brow.size(); ++b)
-      if (bcol[b] != brow[b]) slot[b] = fill[bcol[b]]++;
-    sn.nslot = cptr[sn.nchunk];
-    sn.ntasks = int(task.size() / 3);
-
-    sn.brow_h = brow;
-    sn.bcol_h = bcol;
-    sn.chunk_base = own(upload(h, cbase));
-    sn.chunk_start = own(upload(h, cstart));
-    sn.chunk_n = own(upload(h, cn));
-    sn.blk_row = own(upload(h, brow));
-    sn.blk_col = own(upload(h, bcol));
-    sn.blk_slot = own(upload(h, slot));
-    sn.task = own(upload(h, task));
-    sn.row_task_ptr = own(upload(h, rtp));
-    sn.col_ptr = own(upload(h, cptr));
+    plan_near(h);
     const size_t nvec = size_t(sn.nchunk) * 64;
     sn.partial = own(h.arena.make<double>(size_t(std::max(sn.ntasks, 1)) * 64));
     sn.colpart = own(h.arena.make<double>(size_t(std::max(sn.nslot, 1)) * 64));

@@ -14,8 +14,15 @@ h2mg_status setup_mg(H2& h, int precision_mask);
 // tiles) for every later FP64 fine product; enable == 0: release them and
 // go back to evaluating the near field in every product.
 h2mg_status store_near(H2& h, int enable);
+// Buffers and task sets of the 16-column products and cycles (rebuilt on
+// next use).
+void release_block_work(H2& h);
+// The chunk plan of the near field alone (chunks, tile lists, tasks; no
+// tiles), for products that evaluate the near-field tiles from the points.
+// Throws on failure.
+void plan_near(H2& h);
 // y = A_H2 x for a block of nrhs <= 16 vectors (device, user order, row-major
-// n x ld), FP64; needs 9 <= r <= 64 and the stored near field.
+// n x ld), FP64; needs 9 <= r <= 64.
 h2mg_status matvec_multi(H2& h, int nrhs, const double* x, int ldx, double* y, int ldy);
 // H2 matrix of dk/dl (which 1) or g = k'(r)/r (which 2) on the points and
 // tree of h (shift 0).

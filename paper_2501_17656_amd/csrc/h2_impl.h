@@ -94,7 +94,8 @@ struct NearField {
 // chunk_base[s] * 64 + i; when every leaf holds a multiple of 64 points this
 // is the tree order itself and no padding copy is made.
 struct StoredNear {
-  bool ready = false;
+  bool planned = false;                // chunks, tile lists and tasks built
+  bool ready = false;                  // tiles stored
   bool identity = false;               // padded chunk order == tree order
   int nchunk = 0;
   int ntasks = 0;
@@ -135,6 +136,8 @@ struct TileSet {
   const int* brow = nullptr;           // device: block row / column of every tile
   const int* bcol = nullptr;
   int row0 = 0, nrows = 0;             // rows the reduce writes
+  int run = 0;                         // tiles per task
+  double tuned_ms = 0.0;               // measured product + reduce time (tuned sets)
   int64_t ntiles = 0;                  // tiles in the set (each read by the row pass)
   int64_t nctiles = 0;                 // off-diagonal tiles (read again by the column pass)
 };
@@ -156,7 +159,6 @@ struct BlockWork {
   double* xc64 = nullptr;              // nchunk * 64 x NR (null when the chunk order is the tree order)
   float* xc32 = nullptr;
   void* yc = nullptr;                  // nchunk * 64 x NR
-  void* near_lp[3] = {nullptr, nullptr, nullptr};   // FP32 copy of the near tiles (slot P32)
   double* bx = nullptr;                // n x NR staging blocks of the product entry point
   double* by = nullptr;
   std::vector<void*> owned;
@@ -238,6 +240,10 @@ struct H2 {
   void* bj_fine[3] = {nullptr, nullptr, nullptr};   // nleaf blocks of bj_ld^2
   void* bj_coarse[3] = {nullptr, nullptr, nullptr}; // per gid r^2 (depths d_top+1..L)
 
+  // tile products on 16-column blocks: task run lengths chosen by timing
+  // candidates when the block work is built
+  bool autotune = false;
+
   // cycle graphs: with graphs on, the first cycle of a solve is captured
   // (on a private stream) and every cycle is one graph launch
   bool graphs = false;
@@ -274,7 +280,6 @@ void launch_assemble_kernel_dense(H2& h, double* A, int64_t lda);  // no far blo
 void launch_potrf(H2& h, double* A, int64_t N);   // blocked Cholesky, sets flags[0]
 void launch_cast_precision(H2& h, int p);         // FP64 -> FP32 / BF16 copies
 void launch_near_tiles(H2& h);                    // stored near-field tiles (FP64)
-void launch_cast_near_tiles(H2& h, int p, void* dst);   // FP32 / BF16 copies of them
 // Inverses of the block-Jacobi blocks: leaf blocks K_ss + shift (FP64) and the
 // projected diagonal blocks of depths d_top+1..L (FP64); sets flags[0] on a
 // non-positive pivot.
@@ -317,6 +322,9 @@ int parts16(int64_t nrows);            // partial sums of a per-column dot
 // tiles with FP32 vectors).
 void launch_tgemm(H2& h, int tp, int T, const TileSet& ts, const void* tiles, int rr, const void* x,
                   void* partial);
+// Near-field tile products with the tiles evaluated from the points (near
+// chunk plan of h.snear; vectors of precision p, chunk-padded).
+void launch_tgemm_eval(H2& h, int p, const TileSet& ts, const void* x, void* partial);
 void launch_reduce16(H2& h, int p, const TileSet& ts, int rr, const void* partial, void* out);
 void launch_gather16(H2& h, int nrhs, const double* user, int ldu, double* tree);
 void launch_scatter16(H2& h, int nrhs, const double* tree, double* user, int ldu);

@@ -83,58 +83,73 @@ template <> struct Mfma<float> {
   __device__ static int row(int t, int q) { return 4 * q + t; }
 };
 
-// Tile products of one launch: blocks [0, nrt) run the row-pass tasks
-// (index, i0, i1) over rorder, blocks [nrt, nrt + nct) the column-pass tasks
-// over corder.  Tile b joins block row brow[b] and block column bcol[b]; the
-// operand of a row task is the block of bcol[b], of a column task that of
-// brow[b], at x + index * rr * 16 (rr rows: the rank for coupling tiles, 64
-// for near-field tiles; rows >= rr of the RP = 8T padded tile are zero).
-// partial[block] = the rr x 16 result.
-template <int T, typename Te, typename Tv>
-__global__ __launch_bounds__(64) void k_tgemm(const int* __restrict__ rtask, int nrt,
-                                              const int* __restrict__ rorder,
-                                              const int* __restrict__ ctask,
-                                              const int* __restrict__ corder,
-                                              const Te* __restrict__ tiles,
-                                              const int* __restrict__ brow,
-                                              const int* __restrict__ bcol, int rr,
-                                              const Tv* __restrict__ x, Tv* __restrict__ partial) {
-  constexpr int RP = 8 * T, NS = RP / 16, K = tile_K<Te>(T), NCH = T * T / K;
+// Tile products of one launch.  MODE_LIST: blocks [0, nrt) run the
+// row-pass tasks (index, i0, i1) over rorder, blocks [nrt, nrt + nct) the
+// column-pass tasks over corder.  Tile b joins block row brow[b] and block
+// column bcol[b]; the operand of a row task is the block of bcol[b], of a
+// column task that of brow[b], at x + index * rr * 16 (rr rows: the rank for
+// coupling tiles, 64 for near-field tiles; rows >= rr of the RP = 8T padded
+// tile are zero).  out[block] = the rr x 16 result.
+// MODE_UP (transfer to the parents): block s sums E_c^T x[c] over its two
+// children c = 2s, 2s+1 (tiles base + c).  MODE_DOWN (transfer to the
+// children): block c computes E_c x[c / 2] (tile base + c), plus addend[c]
+// when addend is not null.  stage(b, put) writes the entries (i, j) of tile
+// b through put(i, j, value).
+enum { MODE_LIST = 0, MODE_UP = 1, MODE_DOWN = 2 };
+
+template <int T, int MODE, typename Tv, typename Stage>
+__device__ __forceinline__ void tgemm_body(const int* __restrict__ rtask, int nrt,
+                                           const int* __restrict__ rorder,
+                                           const int* __restrict__ ctask,
+                                           const int* __restrict__ corder,
+                                           const int* __restrict__ brow,
+                                           const int* __restrict__ bcol, int base, int rr,
+                                           const Tv* __restrict__ x, Tv* out_base, const Tv* addend,
+                                           Tv* lds, Stage&& stage) {
+  constexpr int RP = 8 * T, NS = RP / 16;
   constexpr int EB = int(sizeof(Tv));
   using M = Mfma<Tv>;
-  __shared__ Tv lds[RP * RP];
   const int blk = blockIdx.x;
-  const bool tr = blk >= nrt;
-  const int* task = tr ? ctask + 3 * (blk - nrt) : rtask + 3 * blk;
-  const int* order = tr ? corder : rorder;
-  const int* other = tr ? brow : bcol;
-  const int l = threadIdx.x, p = l & 15, q = l >> 4, a = l >> 3, bb = l & 7;
-  const int i0 = task[1], i1 = task[2];
+  bool tr;
+  int i0, i1;
+  const int* order = nullptr;
+  const int* other = nullptr;
+  if constexpr (MODE == MODE_LIST) {
+    tr = blk >= nrt;
+    const int* task = tr ? ctask + 3 * (blk - nrt) : rtask + 3 * blk;
+    order = tr ? corder : rorder;
+    other = tr ? brow : bcol;
+    i0 = task[1];
+    i1 = task[2];
+  } else if constexpr (MODE == MODE_UP) {
+    tr = true;
+    i0 = 2 * blk;
+    i1 = 2 * blk + 2;
+  } else {
+    tr = false;
+    i0 = blk;
+    i1 = blk + 1;
+  }
+  const int l = threadIdx.x, p = l & 15, q = l >> 4;
   const int nkb = (rr + 3) >> 2;
+  auto put = [&](int i, int j, Tv v) { lds[i * RP + (j ^ swz<RP, EB>(i))] = v; };
   typename M::acc_t acc[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) acc[s] = typename M::acc_t{Tv(0), Tv(0), Tv(0), Tv(0)};
   for (int it = i0; it < i1; ++it) {
-    const int b = order[it];
-    const int o = other[b];
-    __syncthreads();                   // the previous tile's operand reads are done
-    const Te* tile = tiles + int64_t(b) * tile_elems(T);
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-      union { u32x4 q4; Te e[16 / sizeof(Te)]; } u;
-      const Te* src = tile + (c * 64 + l) * K;
-      if constexpr (K * sizeof(Te) == 16) {
-        u.q4 = *reinterpret_cast<const u32x4*>(src);
-      } else {
-#pragma unroll
-        for (int k = 0; k < K; ++k) u.e[k] = src[k];
-      }
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const int el = c * K + k, i = T * a + el / T, j = T * bb + el % T;
-        lds[i * RP + (j ^ swz<RP, EB>(i))] = ld_as<Tv, Te>(u.e[k]);
-      }
+    int b, o;
+    if constexpr (MODE == MODE_LIST) {
+      b = order[it];
+      o = other[b];
+    } else if constexpr (MODE == MODE_UP) {
+      b = base + it;
+      o = it;
+    } else {
+      b = base + it;
+      o = it >> 1;
     }
+    __syncthreads();                   // the previous tile's operand reads are done
+    stage(b, put);
     __syncthreads();
     const Tv* xo = x + int64_t(o) * rr * NR;
     for (int kb = 0; kb < nkb; ++kb) {
@@ -147,14 +162,131 @@ __global__ __launch_bounds__(64) void k_tgemm(const int* __restrict__ rtask, int
       }
     }
   }
-  Tv* out = partial + int64_t(blk) * rr * NR;
+  Tv* out = out_base + int64_t(blk) * rr * NR;
+  const Tv* add = addend ? addend + int64_t(blk) * rr * NR : nullptr;
 #pragma unroll
   for (int s = 0; s < NS; ++s)
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int row = 16 * s + M::row(t, q);
-      if (row < rr) out[row * NR + p] = acc[s][t];
+      if (row < rr) out[row * NR + p] = add ? acc[s][t] + add[row * NR + p] : acc[s][t];
     }
+}
+
+// Stored tiles: lane (a, b) of the 8 x 8 lane grid reads its T x T sub-block
+// as coalesced 16-byte chunks of the storage layout.
+template <int T, typename Te, typename Tv>
+struct StageStored {
+  const Te* tiles;
+  template <typename Put>
+  __device__ __forceinline__ void operator()(int b, Put& put) const {
+    constexpr int K = tile_K<Te>(T), NCH = T * T / K;
+    const int l = threadIdx.x, a = l >> 3, bb = l & 7;
+    const Te* tile = tiles + int64_t(b) * tile_elems(T);
+#pragma unroll 8
+    for (int c = 0; c < NCH; ++c) {
+      union { u32x4 q4; Te e[16 / sizeof(Te)]; } u;
+      const Te* src = tile + (c * 64 + l) * K;
+      if constexpr (K * sizeof(Te) == 16) {
+        u.q4 = *reinterpret_cast<const u32x4*>(src);
+      } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) u.e[k] = src[k];
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int el = c * K + k;
+        put(T * a + el / T, T * bb + el % T, ld_as<Tv, Te>(u.e[k]));
+      }
+    }
+  }
+};
+
+template <int T, typename Te, typename Tv>
+__global__ __launch_bounds__(64) void k_tgemm(const int* __restrict__ rtask, int nrt,
+                                              const int* __restrict__ rorder,
+                                              const int* __restrict__ ctask,
+                                              const int* __restrict__ corder,
+                                              const Te* __restrict__ tiles,
+                                              const int* __restrict__ brow,
+                                              const int* __restrict__ bcol, int rr,
+                                              const Tv* __restrict__ x, Tv* __restrict__ partial) {
+  __shared__ Tv lds[64 * T * T];
+  tgemm_body<T, MODE_LIST>(rtask, nrt, rorder, ctask, corder, brow, bcol, 0, rr, x, partial,
+                           static_cast<const Tv*>(nullptr), lds, StageStored<T, Te, Tv>{tiles});
+}
+
+// Transfers between depth d + 1 (children, gids base + c) and depth d.
+template <int T, int MODE, typename Te, typename Tv>
+__global__ __launch_bounds__(64) void k_transfer16(const Te* __restrict__ E, int base, int r,
+                                                   const Tv* __restrict__ x, Tv* out, const Tv* addend) {
+  __shared__ Tv lds[64 * T * T];
+  tgemm_body<T, MODE>(nullptr, 0, nullptr, nullptr, nullptr, nullptr, nullptr, base, r, x, out, addend, lds,
+                      StageStored<T, Te, Tv>{E});
+}
+
+// Near-field tiles evaluated from the points instead of read: tile b is the
+// block between chunk brow[b] and chunk bcol[b] (at most 64 consecutive
+// points of a leaf each; chunk_start / chunk_n), entry (i, j) = the scaled
+// kernel s_i k(|p_i - p_j|) s_j plus the diagonal (the per-point d, else the
+// shift) where a point meets itself, zero outside the chunks.  The kernel is
+// evaluated in the vector precision from squared distances formed in FP64.
+// Lane (a, b) evaluates rows 8a .. 8a+7 and columns 8b .. 8b+7.
+template <typename Tv, int KIND, int DERIV>
+__global__ __launch_bounds__(64) void k_tgemm_eval(const int* __restrict__ rtask, int nrt,
+                                                   const int* __restrict__ rorder,
+                                                   const int* __restrict__ ctask,
+                                                   const int* __restrict__ corder,
+                                                   const int* __restrict__ brow,
+                                                   const int* __restrict__ bcol,
+                                                   const int* __restrict__ chunk_start,
+                                                   const int* __restrict__ chunk_n,
+                                                   const double* __restrict__ pts, int dim,
+                                                   KernelParams kp, PointScale ps,
+                                                   const Tv* __restrict__ x, Tv* __restrict__ partial) {
+  __shared__ Tv lds[64 * 64];
+  const int l = threadIdx.x, a = l >> 3, bb = l & 7;
+  const Tv inv_l = Tv(kp.inv_l), inv_2l2 = Tv(kp.inv_2l2);
+  auto stage = [&](int b, auto& put) {
+    const int rs = chunk_start[brow[b]], nr = chunk_n[brow[b]];
+    const int cs = chunk_start[bcol[b]], nc = chunk_n[bcol[b]];
+    double pc[8][3];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const int j = 8 * bb + v;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) pc[v][d] = (j < nc && d < dim) ? pts[int64_t(cs + j) * dim + d] : 0.0;
+    }
+#pragma unroll 2
+    for (int u = 0; u < 8; ++u) {
+      const int i = 8 * a + u;
+      const bool rowok = i < nr;
+      double pr[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) pr[d] = (rowok && d < dim) ? pts[int64_t(rs + i) * dim + d] : 0.0;
+      const int64_t gi = int64_t(rs) + i;
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const int j = 8 * bb + v;
+        Tv e = Tv(0);
+        if (rowok && j < nc) {
+          double r2 = 0.0;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            const double dx = pr[d] - pc[v][d];
+            r2 += dx * dx;
+          }
+          const int64_t gj = int64_t(cs) + j;
+          e = kernel_fixed<KIND, DERIV, Tv>(inv_l, inv_2l2, Tv(r2));
+          if (ps.s) e *= Tv(ps.s[gi] * ps.s[gj]);
+          if (gi == gj) e += Tv(ps.d ? ps.d[gi] : kp.shift);
+        }
+        put(i, j, e);
+      }
+    }
+  };
+  tgemm_body<8, MODE_LIST>(rtask, nrt, rorder, ctask, corder, brow, bcol, 0, 64, x, partial,
+                           static_cast<const Tv*>(nullptr), lds, stage);
 }
 
 // out[row] (rr x 16) = the row-pass partials [rtp[row], rtp[row+1]) plus the
@@ -235,41 +367,6 @@ __global__ __launch_bounds__(NT) void k_leaf_down16(const int* __restrict__ leaf
     Tv o = Tv(alpha) * v;
     if (beta != 0.0) o += Tv(beta) * add[idx];
     out[idx] = o;
-  }
-}
-
-// xpar[s] = sum over the two children c of E_c^T xchild[c].
-template <typename Te, typename Tv>
-__global__ __launch_bounds__(NT) void k_transfer_up16(int gidc0, const Te* __restrict__ E, int r, int T,
-                                                      const Tv* __restrict__ xchild,
-                                                      Tv* __restrict__ xpar) {
-  const int s = blockIdx.x;
-  for (int e = threadIdx.x; e < r * NR; e += NT) {
-    const int j = e / NR, k = e % NR;
-    Tv v = Tv(0);
-    for (int c = 2 * s; c < 2 * s + 2; ++c) {
-      const Te* tile = E + int64_t(gidc0 + c) * tile_elems(T);
-      for (int i = 0; i < r; ++i)
-        v += ld_as<Tv, Te>(tile[tile_offset<Te>(i, j, T)]) * xchild[(int64_t(c) * r + i) * NR + k];
-    }
-    xpar[(int64_t(s) * r + j) * NR + k] = v;
-  }
-}
-
-// ychild[c] = addend[c] + E_c ypar[c / 2] (addend may be null or alias ychild).
-template <typename Te, typename Tv>
-__global__ __launch_bounds__(NT) void k_transfer_down16(int gidc0, const Te* __restrict__ E, int r, int T,
-                                                        const Tv* __restrict__ ypar, Tv* ychild,
-                                                        const Tv* addend) {
-  const int c = blockIdx.x;
-  const Te* tile = E + int64_t(gidc0 + c) * tile_elems(T);
-  for (int e = threadIdx.x; e < r * NR; e += NT) {
-    const int i = e / NR, k = e % NR;
-    const int64_t idx = (int64_t(c) * r + i) * NR + k;
-    Tv v = addend ? addend[idx] : Tv(0);
-    for (int j = 0; j < r; ++j)
-      v += ld_as<Tv, Te>(tile[tile_offset<Te>(i, j, T)]) * ypar[(int64_t(c >> 1) * r + j) * NR + k];
-    ychild[idx] = v;
   }
 }
 
@@ -517,6 +614,25 @@ void launch_tgemm(H2& h, int tp, int T, const TileSet& ts, const void* tiles, in
   check_launch("tgemm");
 }
 
+void launch_tgemm_eval(H2& h, int p, const TileSet& ts, const void* x, void* partial) {
+  const int nb = ts.nrt + ts.nct;
+  if (nb == 0) return;
+  const StoredNear& sn = h.snear;
+  const PointScale ps{h.scale, h.diag};
+  dispatch_kernel(h.kp.kind, h.kp.deriv, [&](auto kc, auto dc) {
+    constexpr int KIND = decltype(kc)::value, DERIV = decltype(dc)::value;
+    if (p == P64)
+      hipLaunchKernelGGL((k_tgemm_eval<double, KIND, DERIV>), dim3(nb), dim3(64), 0, h.stream, ts.rtask, ts.nrt,
+                         ts.rorder, ts.ctask, ts.corder, ts.brow, ts.bcol, sn.chunk_start, sn.chunk_n, h.pts,
+                         h.dim, h.kp, ps, static_cast<const double*>(x), static_cast<double*>(partial));
+    else
+      hipLaunchKernelGGL((k_tgemm_eval<float, KIND, DERIV>), dim3(nb), dim3(64), 0, h.stream, ts.rtask, ts.nrt,
+                         ts.rorder, ts.ctask, ts.corder, ts.brow, ts.bcol, sn.chunk_start, sn.chunk_n, h.pts,
+                         h.dim, h.kp, ps, static_cast<const float*>(x), static_cast<float*>(partial));
+  });
+  check_launch("tgemm_eval");
+}
+
 void launch_reduce16(H2& h, int p, const TileSet& ts, int rr, const void* partial, void* out) {
   if (ts.nrows == 0) return;
   if (p == P64)
@@ -565,24 +681,29 @@ void launch_leaf_down16(H2& h, int p, const void* yhat, const void* near_y, void
 }
 
 void launch_transfer_up16(H2& h, int p, int d, const void* xchild, void* xpar) {
-  dispatch_prec(p, [&](auto tv, auto te) {
-    using Tv = decltype(tv);
-    using Te = decltype(te);
-    hipLaunchKernelGGL((k_transfer_up16<Te, Tv>), dim3(1 << d), dim3(NT), 0, h.stream, (1 << (d + 1)) - 1,
-                       static_cast<const Te*>(h.prec[p].E), h.r, h.T, static_cast<const Tv*>(xchild),
-                       static_cast<Tv*>(xpar));
+  dispatch_T16(h.T, [&](auto Tc) {
+    constexpr int TT = decltype(Tc)::value;
+    dispatch_prec(p, [&](auto tv, auto te) {
+      using Tv = decltype(tv);
+      using Te = decltype(te);
+      hipLaunchKernelGGL((k_transfer16<TT, MODE_UP, Te, Tv>), dim3(1 << d), dim3(64), 0, h.stream,
+                         static_cast<const Te*>(h.prec[p].E), (1 << (d + 1)) - 1, h.r,
+                         static_cast<const Tv*>(xchild), static_cast<Tv*>(xpar), static_cast<const Tv*>(nullptr));
+    });
   });
   check_launch("transfer_up16");
 }
 
 void launch_transfer_down16(H2& h, int p, int d, const void* ypar, void* ychild, const void* addend) {
-  dispatch_prec(p, [&](auto tv, auto te) {
-    using Tv = decltype(tv);
-    using Te = decltype(te);
-    hipLaunchKernelGGL((k_transfer_down16<Te, Tv>), dim3(1 << (d + 1)), dim3(NT), 0, h.stream,
-                       (1 << (d + 1)) - 1, static_cast<const Te*>(h.prec[p].E), h.r, h.T,
-                       static_cast<const Tv*>(ypar), static_cast<Tv*>(ychild),
-                       static_cast<const Tv*>(addend));
+  dispatch_T16(h.T, [&](auto Tc) {
+    constexpr int TT = decltype(Tc)::value;
+    dispatch_prec(p, [&](auto tv, auto te) {
+      using Tv = decltype(tv);
+      using Te = decltype(te);
+      hipLaunchKernelGGL((k_transfer16<TT, MODE_DOWN, Te, Tv>), dim3(2 << d), dim3(64), 0, h.stream,
+                         static_cast<const Te*>(h.prec[p].E), (1 << (d + 1)) - 1, h.r,
+                         static_cast<const Tv*>(ypar), static_cast<Tv*>(ychild), static_cast<const Tv*>(addend));
+    });
   });
   check_launch("transfer_down16");
 }

@@ -843,16 +843,4 @@ void launch_cast_precision(H2& h, int p) {
   check_launch("cast_precision");
 }
 
-void launch_cast_near_tiles(H2& h, int p, void* dst) {
-  const StoredNear& sn = h.snear;
-  if (sn.nblocks == 0) return;
-  if (p == P32)
-    hipLaunchKernelGGL(k_cast_tiles<float>, dim3(unsigned(sn.nblocks)), dim3(NT), 0, h.stream, sn.tiles,
-                       static_cast<float*>(dst), int64_t(0), 64, 8);
-  else
-    hipLaunchKernelGGL(k_cast_tiles<bf16>, dim3(unsigned(sn.nblocks)), dim3(NT), 0, h.stream, sn.tiles,
-                       static_cast<bf16*>(dst), int64_t(0), 64, 8);
-  check_launch("cast_near_tiles");
-}
-
 }  // namespace h2mg

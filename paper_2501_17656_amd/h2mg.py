@@ -278,6 +278,25 @@ class H2Matrix:
         """Launch each solver cycle as one captured HIP graph."""
         check(lib().h2mg_set_graphs(self._h, int(bool(enabled))))
 
+    def set_autotune(self, enabled: bool) -> None:
+        """Choose the tile-run length of every 16-column task set by timing
+        the candidates on this device (applies from the next 16-column call)."""
+        check(lib().h2mg_set_autotune(self._h, int(bool(enabled))))
+
+    def block_tuning(self) -> dict:
+        """Run length and measured ms of every built 16-column task set:
+        keys "near", "fine" and the depths of the restricted operators."""
+        out = {}
+        for which in [-2, -1] + list(range(0, 64)):
+            run, ms = ctypes.c_int32(), ctypes.c_double()
+            st = lib().h2mg_block_tuning(self._h, which, ctypes.byref(run), ctypes.byref(ms))
+            if st != 0:
+                break
+            if run.value:
+                key = {-2: "near", -1: "fine"}.get(which, which)
+                out[key] = {"run": run.value, "ms": round(ms.value, 4)}
+        return out
+
     def set_timing(self, enabled: bool) -> None:
         check(lib().h2mg_set_timing(self._h, int(bool(enabled))))
 

@@ -17,7 +17,10 @@
   lambda_min / lambda_max is 1e-5, where a run reported NOT_SPD);
 * the batched solve of uneven problems equals the per-problem block solve
   bit for bit (same kernels in the same order, only the streams differ);
-* error paths: nrhs, method, near field not stored, shared handles.
+* the near-field tiles evaluated inside the products (no stored near
+  field) give the stored-tile results up to rounding;
+* the tile-run tuner keeps the results (up to summation order);
+* error paths: nrhs, method, rank, shared handles.
 """
 import numpy as np
 import pytest
@@ -159,6 +162,30 @@ def test_batch_of_uneven_problems_equals_block_solves():
         g.close()
 
 
+def test_autotuned_runs_keep_results():
+    """With tuning on, every task set is rebuilt with the fastest run length
+    among {2, 4, 8, 16, 32}; only the summation order of the partials
+    changes, so two cycles agree with the untuned ones to the rounding
+    sensitivity of this shape."""
+    P, g, o, H = make("gauss3d_gmm4k_r27")
+    n = len(P)
+    B = synth.normal_vector(n, 37, nrhs=16)
+    kw = dict(rtol=1e-300, n_coarse=2, max_cycles=2, smoother="bj", raise_on_error=False)
+    X0, _ = g.solve_multi(_dev(B), **kw)
+    g.set_autotune(True)
+    try:
+        X1, _ = g.solve_multi(_dev(B), **kw)
+        tun = g.block_tuning()
+    finally:
+        g.set_autotune(False)
+    print(f"[gpu] tuned runs: {tun}")
+    assert "fine" in tun and "near" in tun and any(isinstance(k, int) for k in tun)
+    assert all(v["run"] in (2, 4, 8, 16, 32) and v["ms"] > 0 for v in tun.values())
+    rel = np.linalg.norm(_host(X1) - _host(X0)) / np.linalg.norm(_host(X0))
+    print(f"[gpu] tuned vs untuned two cycles: rel diff {rel:.2e}")
+    assert rel <= CYCLE_TOL["gauss3d_gmm4k_r27"]
+
+
 def test_block_error_paths():
     from paper_2501_17656_amd import H2Matrix, H2MGError, solve_batch
     P, g, o, H = make("exp2d_4k")
@@ -174,7 +201,31 @@ def test_block_error_paths():
     with pytest.raises(H2MGError):
         solve_batch([(g, _dev(np.ones((n, 2)))), (g, _dev(np.ones((n, 2))))])
     P2 = synth.uniform_points(2048, 2, 5)
-    g2 = H2Matrix(_dev(P2), "exp", 0.1, 1e-2, 64, 0.7, 4)             # near field not stored
+    g2 = H2Matrix(_dev(P2), "exp", 0.1, 1e-2, 64, 0.7, 2)             # rank 4: tiles too small
     with pytest.raises(H2MGError):
         g2.solve_multi(_dev(np.ones((2048, 2))))
     g2.close()
+
+
+def test_block_solve_with_evaluated_near_field():
+    """Without stored tiles every near-field tile product evaluates its tile
+    from the points; two cycles match the stored-tile cycles up to rounding
+    and the solve reaches the oracle's residual bar."""
+    from paper_2501_17656_amd import H2Matrix
+    kind, n, dim, ker, ell, shift, leaf, eta, m = SHAPES["exp2d_ragged_r9"]
+    P = _points(kind, n, dim)
+    g = H2Matrix(_dev(P), ker, ell, shift, leaf, eta, m)
+    o = make("exp2d_ragged_r9")[2]
+    B = synth.normal_vector(n, 36, nrhs=6)
+    Xe, _ = g.solve_multi(_dev(B), rtol=1e-300, n_coarse=2, max_cycles=2, smoother="bj", raise_on_error=False)
+    g.store_near(True)
+    Xs, _ = g.solve_multi(_dev(B), rtol=1e-300, n_coarse=2, max_cycles=2, smoother="bj", raise_on_error=False)
+    g.store_near(False)
+    assert np.linalg.norm(_host(Xe) - _host(Xs)) <= 1e-12 * np.linalg.norm(_host(Xs))
+    for prec in ("fp64", "fp32"):
+        X, info = g.solve_multi(_dev(B), rtol=1e-8, precision=prec, smoother="bj")
+        X = _host(X)
+        for k in range(6):
+            res = np.linalg.norm(B[:, k] - o.matvec(X[:, k])) / np.linalg.norm(B[:, k])
+            assert res < 1.5e-8, (prec, k, res)
+    g.close()

@@ -3,7 +3,8 @@ matrix-core tile products) against the single-vector product and the oracle.
 
 Each column of the block product must equal the single product of that
 column up to rounding order (1e-13 relative) and the oracle to 1e-12 (the
-matvec bar).  Shapes: rank 64 in 3D with leaves of 64 and 128 points (chunk
+matvec bar), with the near-field tiles stored or evaluated inside the
+product.  Shapes: rank 64 in 3D with leaves of 64 and 128 points (chunk
 order equal to the tree order) and with ragged leaves of 78-79 points (two
 chunks per leaf, the second partial); rank 27 (32 x 32 padded tiles) and
 rank 16 / rank 9 in 2D (16 x 16 tiles, the latter padded); 1, 5 and 16
@@ -75,10 +76,30 @@ def test_block_product_argument_errors():
         g.matvec_multi(_dev(np.zeros((4096, 4))))
     g.close()
     P3 = synth.uniform_points(8192, 3, 4)
-    g = H2Matrix(_dev(P3), "exp", 0.1, 1e-2, 64, 0.7, 4)           # rank 64, near not stored
-    with pytest.raises(H2MGError):
-        g.matvec_multi(_dev(np.zeros((8192, 4))))
-    g.store_near(True)
+    g = H2Matrix(_dev(P3), "exp", 0.1, 1e-2, 64, 0.7, 4)
     with pytest.raises(H2MGError):
         g.matvec_multi(_dev(np.zeros((8192, 17))))
+    g.close()
+
+
+@pytest.mark.parametrize("name", ["exp3d_leaf128_ragged", "gauss3d_r27", "exp2d_r9_ragged"])
+def test_block_product_with_evaluated_near_field(name):
+    """Without stored tiles the near-field tiles are evaluated inside the
+    product; the result matches the oracle to the matvec bar and the
+    stored-tile product up to rounding order."""
+    from paper_2501_17656_amd import H2Matrix
+    n, dim, ker, ell, shift, leaf, eta, m = SHAPES[name]
+    P = synth.uniform_points(n, dim, 21)
+    g = H2Matrix(_dev(P), ker, ell, shift, leaf, eta, m)
+    o = OracleH2(P, ker, shift, leaf, eta, m, ell)
+    X = synth.normal_vector(n, 23, nrhs=16)
+    Ye = _host(g.matvec_multi(_dev(X)))
+    g.store_near(True)
+    Ys = _host(g.matvec_multi(_dev(X)))
+    for k in (0, 9):
+        yo = o.matvec(X[:, k])
+        rel = np.linalg.norm(Ye[:, k] - yo) / np.linalg.norm(yo)
+        print(f"[gpu] {name} evaluated near field, column {k}: rel err vs oracle {rel:.2e}")
+        assert rel <= 1e-12
+    assert np.linalg.norm(Ye - Ys) <= 1e-13 * np.linalg.norm(Ys)
     g.close()
