@@ -210,10 +210,12 @@ def spd_probe(args, torch, synth, H2Matrix):
 
 def block_product(args, torch, g, w, single_ms):
     """Y = A_H2 X for a block of 16 vectors (matrix-core tile products; each
-    stored tile streamed twice, once per pass): time per block product, the
-    equivalent time per vector, and the matrix-core rate of the near-field
-    tile passes (2 * 64 * 64 * 16 flops per tile and pass)."""
+    stored off-diagonal tile streamed twice, once per pass; tile runs tuned
+    on the first call): time per block product, the equivalent time per
+    vector, and the matrix-core rate of the near-field tile passes
+    (2 * 64 * 64 * 16 flops per tile and pass)."""
     X = torch.from_numpy(synth_block(w, 16)).cuda()
+    g.set_autotune(True)                                      # tile runs chosen on the first call
     try:
         Y = g.matvec_multi(X)
     except Exception as ex:
@@ -232,8 +234,10 @@ def block_product(args, torch, g, w, single_ms):
     tile_bytes = st["work"] / max(st["launches"], 1)          # both passes
     flops = tile_bytes / 8.0 * 2.0 * 16.0                     # 2 flops per stored word and column
     g.set_timing(False)
+    tuning = g.block_tuning()
     return {"ms": round(ms, 3), "ms_per_vector": round(ms / 16, 3),
             "speedup_vs_16_single_products": round(16 * single_ms / ms, 2),
+            "tile_runs": {k: v["run"] for k, v in tuning.items()},
             "near_tile_passes_ms": round(near_ms, 3),
             "near_tile_passes_gbs": round(tile_bytes / (near_ms * 1e-3) / 1e9, 1),
             "near_mfma_tflops": round(flops / (near_ms * 1e-3) / 1e12, 2),

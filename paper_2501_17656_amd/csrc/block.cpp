@@ -23,7 +23,7 @@ namespace {
 
 constexpr int NR = MULTI_NR;
 constexpr int RUN = 8;                 // tiles per tile-product task (without tuning)
-constexpr int RUNS[] = {2, 4, 8, 16, 32};   // candidates of the tuner
+constexpr int RUNS[] = {32, 16, 8, 4, 2};   // candidates of the tuner, by growing partial-sum memory
 
 void hip_check(hipError_t e, const char* what) {
   if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
@@ -150,7 +150,14 @@ TileSet tuned_set(H2& h, int p, bool near, const void* x, void* out, const std::
   try {
     for (int run : RUNS) {
       TileSet ts = make_set(h, ids, rows, cols, nrows_total, row0, nrows, brow, bcol, run);
-      ensure_partial(h, int64_t(ts.nrt + ts.nct) * rr * NR);
+      const int64_t need = int64_t(ts.nrt + ts.nct) * rr * NR;
+      size_t free_b = 0, total_b = 0;
+      hip_check(hipMemGetInfo(&free_b, &total_b), "memory info");
+      if (best.rtask && need > h.blk16.partial_elems && size_t(need) * sizeof(double) > free_b / 4) {
+        free_set(h, ts);               // its partial sums would take too much of the free memory
+        continue;
+      }
+      ensure_partial(h, need);
       run_set(h, p, ts, near, x, out);
       hip_check(hipEventRecord(e0, h.stream), "event");
       for (int rep = 0; rep < 2; ++rep) run_set(h, p, ts, near, x, out);
@@ -235,6 +242,20 @@ void ensure_block(H2& h, int p) {
       ensure_partial(h, int64_t(w.coarse[d].nrt + w.coarse[d].nct) * r * NR);
     }
     w.coarse_ready = true;
+  }
+  // partial sums for the largest chosen set only (tuning may have grown them)
+  int64_t need = 0;
+  auto fit = [&](const TileSet& ts, int rr) { need = std::max(need, int64_t(ts.nrt + ts.nct) * rr * NR); };
+  fit(w.fine, r);
+  fit(w.near, 64);
+  for (const TileSet& ts : w.coarse) fit(ts, r);
+  if (need > 0 && need < w.partial_elems) {
+    hip_check(hipStreamSynchronize(h.stream), "sync");
+    h.arena.release(w.partial);
+    w.owned.erase(std::find(w.owned.begin(), w.owned.end(), w.partial));
+    w.partial = nullptr;
+    w.partial_elems = 0;
+    ensure_partial(h, need);
   }
   hip_check(hipStreamSynchronize(h.stream), "block setup");
 }

@@ -93,8 +93,12 @@ template <> struct Mfma<float> {
 // MODE_UP (transfer to the parents): block s sums E_c^T x[c] over its two
 // children c = 2s, 2s+1 (tiles base + c).  MODE_DOWN (transfer to the
 // children): block c computes E_c x[c / 2] (tile base + c), plus addend[c]
-// when addend is not null.  stage(b, put) writes the entries (i, j) of tile
-// b through put(i, j, value).
+// when addend is not null.
+// The stage object fills LDS with a tile: load(b, regs) issues its global
+// loads, store(b, regs, put) writes entry (i, j) through put(i, j, value).
+// When Stage::PREFETCH, the loads of the next tile are issued right after the
+// current tile is in LDS, so they overlap its products; the operand rows of
+// the tile are loaded before it is staged.
 enum { MODE_LIST = 0, MODE_UP = 1, MODE_DOWN = 2 };
 
 template <int T, int MODE, typename Tv, typename Stage>
@@ -105,8 +109,8 @@ __device__ __forceinline__ void tgemm_body(const int* __restrict__ rtask, int nr
                                            const int* __restrict__ brow,
                                            const int* __restrict__ bcol, int base, int rr,
                                            const Tv* __restrict__ x, Tv* out_base, const Tv* addend,
-                                           Tv* lds, Stage&& stage) {
-  constexpr int RP = 8 * T, NS = RP / 16;
+                                           Tv* lds, const Stage& stage) {
+  constexpr int RP = 8 * T, NS = RP / 16, NKB = RP / 4;
   constexpr int EB = int(sizeof(Tv));
   using M = Mfma<Tv>;
   const int blk = blockIdx.x;
@@ -130,35 +134,67 @@ __device__ __forceinline__ void tgemm_body(const int* __restrict__ rtask, int nr
     i0 = blk;
     i1 = blk + 1;
   }
+  auto tile_of = [&](int it) {
+    if constexpr (MODE == MODE_LIST) return order[it];
+    else return base + it;
+  };
+  auto other_of = [&](int it, int b) {
+    if constexpr (MODE == MODE_LIST) return other[b];
+    else if constexpr (MODE == MODE_UP) return it;
+    else return it >> 1;
+  };
   const int l = threadIdx.x, p = l & 15, q = l >> 4;
   const int nkb = (rr + 3) >> 2;
   auto put = [&](int i, int j, Tv v) { lds[i * RP + (j ^ swz<RP, EB>(i))] = v; };
   typename M::acc_t acc[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) acc[s] = typename M::acc_t{Tv(0), Tv(0), Tv(0), Tv(0)};
+  typename Stage::Regs regs;
+  int b = tile_of(i0);
+  if constexpr (Stage::PREFETCH) stage.load(b, regs);
   for (int it = i0; it < i1; ++it) {
-    int b, o;
-    if constexpr (MODE == MODE_LIST) {
-      b = order[it];
-      o = other[b];
-    } else if constexpr (MODE == MODE_UP) {
-      b = base + it;
-      o = it;
-    } else {
-      b = base + it;
-      o = it >> 1;
+    const int o = other_of(it, b);
+    const Tv* xo = x + int64_t(o) * rr * NR;
+    // operand rows: loaded ahead for tiles up to 32 x 32, inside the product
+    // loop for 64 x 64 tiles (whose registers go to staging)
+    constexpr bool XPRE = NKB <= 8;
+    Tv xr[XPRE ? NKB : 1];
+    if constexpr (XPRE) {
+#pragma unroll
+      for (int kb = 0; kb < NKB; ++kb) {
+        const int kr = 4 * kb + q;
+        xr[kb] = kr < rr ? xo[kr * NR + p] : Tv(0);
+      }
     }
     __syncthreads();                   // the previous tile's operand reads are done
-    stage(b, put);
+    if constexpr (!Stage::PREFETCH) stage.load(b, regs);
+    stage.store(b, regs, put);
+    if (it + 1 < i1) {
+      b = tile_of(it + 1);
+      if constexpr (Stage::PREFETCH) stage.load(b, regs);
+    }
     __syncthreads();
-    const Tv* xo = x + int64_t(o) * rr * NR;
-    for (int kb = 0; kb < nkb; ++kb) {
-      const int kr = 4 * kb + q;
-      const Tv xb = kr < rr ? xo[kr * NR + p] : Tv(0);
+    if constexpr (XPRE) {
 #pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        const int ri = tr ? kr : 16 * s + p, cj = tr ? 16 * s + p : kr;
-        acc[s] = M::mma(lds[ri * RP + (cj ^ swz<RP, EB>(ri))], xb, acc[s]);
+      for (int kb = 0; kb < NKB; ++kb) {
+        if (kb < nkb) {
+          const int kr = 4 * kb + q;
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
+            const int ri = tr ? kr : 16 * s + p, cj = tr ? 16 * s + p : kr;
+            acc[s] = M::mma(lds[ri * RP + (cj ^ swz<RP, EB>(ri))], xr[kb], acc[s]);
+          }
+        }
+      }
+    } else {
+      for (int kb = 0; kb < nkb; ++kb) {
+        const int kr = 4 * kb + q;
+        const Tv xb = kr < rr ? xo[kr * NR + p] : Tv(0);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const int ri = tr ? kr : 16 * s + p, cj = tr ? 16 * s + p : kr;
+          acc[s] = M::mma(lds[ri * RP + (cj ^ swz<RP, EB>(ri))], xb, acc[s]);
+        }
       }
     }
   }
@@ -174,29 +210,59 @@ __device__ __forceinline__ void tgemm_body(const int* __restrict__ rtask, int nr
 }
 
 // Stored tiles: lane (a, b) of the 8 x 8 lane grid reads its T x T sub-block
-// as coalesced 16-byte chunks of the storage layout.
+// as coalesced 16-byte chunks of the storage layout.  Tiles of at most 8
+// chunks per lane (T <= 4) are prefetched into registers; 64 x 64 tiles are
+// loaded and staged chunk by chunk.
 template <int T, typename Te, typename Tv>
 struct StageStored {
+  static constexpr int K = tile_K<Te>(T), NCH = T * T / K;
+  static constexpr bool PREFETCH = NCH <= 8;
+  union Chunk {
+    u32x4 q4;
+    Te e[16 / sizeof(Te)];
+  };
+  struct Regs {
+    Chunk c[PREFETCH ? NCH : 1];
+  };
   const Te* tiles;
+  __device__ __forceinline__ static void load_chunk(const Te* src, Chunk& u) {
+    if constexpr (K * sizeof(Te) == 16) {
+      u.q4 = *reinterpret_cast<const u32x4*>(src);
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) u.e[k] = src[k];
+    }
+  }
+  __device__ __forceinline__ void load(int b, Regs& R) const {
+    if constexpr (PREFETCH) {
+      const int l = threadIdx.x;
+      const Te* tile = tiles + int64_t(b) * tile_elems(T);
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) load_chunk(tile + (c * 64 + l) * K, R.c[c]);
+    }
+  }
   template <typename Put>
-  __device__ __forceinline__ void operator()(int b, Put& put) const {
-    constexpr int K = tile_K<Te>(T), NCH = T * T / K;
+  __device__ __forceinline__ void store(int b, const Regs& R, Put& put) const {
     const int l = threadIdx.x, a = l >> 3, bb = l & 7;
-    const Te* tile = tiles + int64_t(b) * tile_elems(T);
+    if constexpr (PREFETCH) {
+#pragma unroll
+      for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const int el = c * K + k;
+          put(T * a + el / T, T * bb + el % T, ld_as<Tv, Te>(R.c[c].e[k]));
+        }
+    } else {
+      const Te* tile = tiles + int64_t(b) * tile_elems(T);
 #pragma unroll 8
-    for (int c = 0; c < NCH; ++c) {
-      union { u32x4 q4; Te e[16 / sizeof(Te)]; } u;
-      const Te* src = tile + (c * 64 + l) * K;
-      if constexpr (K * sizeof(Te) == 16) {
-        u.q4 = *reinterpret_cast<const u32x4*>(src);
-      } else {
+      for (int c = 0; c < NCH; ++c) {
+        Chunk u;
+        load_chunk(tile + (c * 64 + l) * K, u);
 #pragma unroll
-        for (int k = 0; k < K; ++k) u.e[k] = src[k];
-      }
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const int el = c * K + k;
-        put(T * a + el / T, T * bb + el % T, ld_as<Tv, Te>(u.e[k]));
+        for (int k = 0; k < K; ++k) {
+          const int el = c * K + k;
+          put(T * a + el / T, T * bb + el % T, ld_as<Tv, Te>(u.e[k]));
+        }
       }
     }
   }
@@ -225,29 +291,23 @@ __global__ __launch_bounds__(64) void k_transfer16(const Te* __restrict__ E, int
                       StageStored<T, Te, Tv>{E});
 }
 
-// Near-field tiles evaluated from the points instead of read: tile b is the
-// block between chunk brow[b] and chunk bcol[b] (at most 64 consecutive
-// points of a leaf each; chunk_start / chunk_n), entry (i, j) = the scaled
-// kernel s_i k(|p_i - p_j|) s_j plus the diagonal (the per-point d, else the
-// shift) where a point meets itself, zero outside the chunks.  The kernel is
-// evaluated in the vector precision from squared distances formed in FP64.
-// Lane (a, b) evaluates rows 8a .. 8a+7 and columns 8b .. 8b+7.
 template <typename Tv, int KIND, int DERIV>
-__global__ __launch_bounds__(64) void k_tgemm_eval(const int* __restrict__ rtask, int nrt,
-                                                   const int* __restrict__ rorder,
-                                                   const int* __restrict__ ctask,
-                                                   const int* __restrict__ corder,
-                                                   const int* __restrict__ brow,
-                                                   const int* __restrict__ bcol,
-                                                   const int* __restrict__ chunk_start,
-                                                   const int* __restrict__ chunk_n,
-                                                   const double* __restrict__ pts, int dim,
-                                                   KernelParams kp, PointScale ps,
-                                                   const Tv* __restrict__ x, Tv* __restrict__ partial) {
-  __shared__ Tv lds[64 * 64];
-  const int l = threadIdx.x, a = l >> 3, bb = l & 7;
-  const Tv inv_l = Tv(kp.inv_l), inv_2l2 = Tv(kp.inv_2l2);
-  auto stage = [&](int b, auto& put) {
+struct StageEval {
+  static constexpr bool PREFETCH = false;
+  struct Regs {};
+  const int* brow;
+  const int* bcol;
+  const int* chunk_start;
+  const int* chunk_n;
+  const double* pts;
+  int dim;
+  KernelParams kp;
+  PointScale ps;
+  __device__ __forceinline__ void load(int, Regs&) const {}
+  template <typename Put>
+  __device__ __forceinline__ void store(int b, const Regs&, Put& put) const {
+    const int l = threadIdx.x, a = l >> 3, bb = l & 7;
+    const Tv inv_l = Tv(kp.inv_l), inv_2l2 = Tv(kp.inv_2l2);
     const int rs = chunk_start[brow[b]], nr = chunk_n[brow[b]];
     const int cs = chunk_start[bcol[b]], nc = chunk_n[bcol[b]];
     double pc[8][3];
@@ -284,9 +344,32 @@ __global__ __launch_bounds__(64) void k_tgemm_eval(const int* __restrict__ rtask
         put(i, j, e);
       }
     }
-  };
+  }
+};
+
+// Near-field tiles evaluated from the points instead of read: tile b is the
+// block between chunk brow[b] and chunk bcol[b] (at most 64 consecutive
+// points of a leaf each; chunk_start / chunk_n), entry (i, j) = the scaled
+// kernel s_i k(|p_i - p_j|) s_j plus the diagonal (the per-point d, else the
+// shift) where a point meets itself, zero outside the chunks.  The kernel is
+// evaluated in the vector precision from squared distances formed in FP64.
+// Lane (a, b) evaluates rows 8a .. 8a+7 and columns 8b .. 8b+7.
+template <typename Tv, int KIND, int DERIV>
+__global__ __launch_bounds__(64) void k_tgemm_eval(const int* __restrict__ rtask, int nrt,
+                                                   const int* __restrict__ rorder,
+                                                   const int* __restrict__ ctask,
+                                                   const int* __restrict__ corder,
+                                                   const int* __restrict__ brow,
+                                                   const int* __restrict__ bcol,
+                                                   const int* __restrict__ chunk_start,
+                                                   const int* __restrict__ chunk_n,
+                                                   const double* __restrict__ pts, int dim,
+                                                   KernelParams kp, PointScale ps,
+                                                   const Tv* __restrict__ x, Tv* __restrict__ partial) {
+  __shared__ Tv lds[64 * 64];
   tgemm_body<8, MODE_LIST>(rtask, nrt, rorder, ctask, corder, brow, bcol, 0, 64, x, partial,
-                           static_cast<const Tv*>(nullptr), lds, stage);
+                           static_cast<const Tv*>(nullptr), lds,
+                           StageEval<Tv, KIND, DERIV>{brow, bcol, chunk_start, chunk_n, pts, dim, kp, ps});
 }
 
 // out[row] (rr x 16) = the row-pass partials [rtp[row], rtp[row+1]) plus the
