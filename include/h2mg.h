@@ -236,6 +236,14 @@ h2mg_status h2mg_bem_panels(const double* vertices_dev, int64_t nv, const int64_
 h2mg_status h2mg_bem_point_source_rhs(const double* centroids_dev, const double* scale_dev,
                                       int64_t n, const double* x0_host, double* rhs_dev,
                                       hipStream_t stream);
+/* rhs_dev[i] = s_i * sum_k c_k h_k(y_i): W^(1/2) f for a right-hand side
+ * given by a harmonic polynomial (the Dirichlet data of a harmonic
+ * function, as in the boundary-element benchmark), with the harmonic basis
+ * of degree <= 2 in 3D, h = (1, x, y, z, xy, yz, zx, x^2 - y^2,
+ * x^2 + y^2 - 2 z^2) and coeffs_host = (c_0 .. c_8) (9 host doubles).
+ * Errors: INVALID_ARG (null, n < 1, a non-finite coefficient). */
+h2mg_status h2mg_bem_harmonic_rhs(const double* centroids_dev, const double* scale_dev, int64_t n,
+                                  const double* coeffs_host, double* rhs_dev, hipStream_t stream);
 /* sigma_dev[i] = y_dev[i] / s_i: the density of the paper's system from the
  * solution of the symmetric one. */
 h2mg_status h2mg_bem_density(const double* y_dev, const double* scale_dev, int64_t n,

@@ -86,5 +86,19 @@ def symmetric_scaling(V: np.ndarray, T: np.ndarray, self_term: str = "analytic")
     return y, np.sqrt(w), diagonal(V, T, self_term)
 
 
+def harmonic_basis(points: np.ndarray) -> np.ndarray:
+    """The harmonic polynomials of degree <= 2 in 3D, one column each:
+    1, x, y, z, xy, yz, zx, x^2 - y^2, x^2 + y^2 - 2 z^2."""
+    x, y, z = points[:, 0], points[:, 1], points[:, 2]
+    return np.stack([np.ones_like(x), x, y, z, x * y, y * z, z * x, x * x - y * y,
+                     x * x + y * y - 2.0 * z * z], axis=1)
+
+
+def harmonic_rhs(points: np.ndarray, coeffs) -> np.ndarray:
+    """Values of the harmonic polynomial sum_k c_k h_k at the points (the
+    right-hand side of a Dirichlet problem whose solution is harmonic)."""
+    return harmonic_basis(points) @ np.asarray(coeffs, dtype=np.float64)
+
+
 def point_source_rhs(points: np.ndarray, x0) -> np.ndarray:
     return 1.0 / (4.0 * np.pi * np.linalg.norm(points - np.asarray(x0, dtype=np.float64), axis=1))

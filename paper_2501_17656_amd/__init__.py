@@ -7,6 +7,6 @@ L = b^T A^{-1} b as a differentiable torch function.  Every numerical step runs 
 libh2mg.so; this package only marshals arguments.
 """
 from .h2mg import H2Matrix, Plan, KERNELS, PRECISIONS  # noqa: F401
-from .h2mg import bem_density, bem_panels, bem_point_source_rhs, solve_batch  # noqa: F401
+from .h2mg import bem_density, bem_harmonic_rhs, bem_panels, bem_point_source_rhs, solve_batch  # noqa: F401
 from ._lib import H2MGError  # noqa: F401
 from .autograd import quadratic_loss  # noqa: F401

@@ -84,6 +84,7 @@ SIGNATURES = {
     "h2mg_bem_panels": (c_int32, [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),
     "h2mg_bem_point_source_rhs": (c_int32, [c_void_p, c_void_p, c_int64, P_double, c_void_p, c_void_p]),
     "h2mg_bem_density": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
+    "h2mg_bem_harmonic_rhs": (c_int32, [c_void_p, c_void_p, c_int64, P_double, c_void_p, c_void_p]),
     "h2mg_smooth": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p]),
     "h2mg_build_derivative": (c_int32, [c_void_p, c_int32, c_void_p, ctypes.POINTER(c_void_p)]),
     "h2mg_quadratic_gradient": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double,

@@ -188,6 +188,17 @@ h2mg_status h2mg_bem_point_source_rhs(const double* y, const double* s, int64_t 
   });
 }
 
+h2mg_status h2mg_bem_harmonic_rhs(const double* y, const double* s, int64_t n, const double* coeffs,
+                                  double* f, hipStream_t stream) {
+  return guarded([&] {
+    if (!y || !s || !coeffs || !f || n < 1) return fail(H2MG_ERR_INVALID_ARG, "null argument or n < 1");
+    for (int k = 0; k < 9; ++k)
+      if (!std::isfinite(coeffs[k])) return fail(H2MG_ERR_INVALID_ARG, "coefficients must be finite");
+    launch_bem_harmonic(stream, n, y, coeffs, s, f);
+    return check_stream_err(stream);
+  });
+}
+
 h2mg_status h2mg_bem_density(const double* yv, const double* s, int64_t n, double* sigma,
                              hipStream_t stream) {
   return guarded([&] {

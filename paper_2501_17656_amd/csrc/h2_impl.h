@@ -351,6 +351,10 @@ void launch_bem_panels(hipStream_t st, int64_t nt, const double* V, const int64_
 // f_i = s_i / (4 pi |y_i - x0|) (x0: 3 host doubles).
 void launch_bem_rhs(hipStream_t st, int64_t n, const double* y, const double* x0, const double* s,
                     double* f);
+// f_i = s_i * sum_k c_k h_k(y_i), c: 9 host doubles for the harmonic basis
+// 1, x, y, z, xy, yz, zx, x^2 - y^2, x^2 + y^2 - 2 z^2.
+void launch_bem_harmonic(hipStream_t st, int64_t n, const double* y, const double* coeffs, const double* s,
+                         double* f);
 // out_i = x_i / s_i.
 void launch_div(hipStream_t st, int64_t n, const double* x, const double* s, double* out);
 

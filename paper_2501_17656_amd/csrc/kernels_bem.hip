@@ -71,6 +71,23 @@ __global__ __launch_bounds__(NT) void k_bem_rhs(int64_t n, const double* __restr
   f[i] = s[i] * INV_4PI / sqrt(dx * dx + dy * dy + dz * dz);
 }
 
+struct Harmonic {
+  double c[9];
+};
+
+// f_i = s_i * sum_k c_k h_k(y_i) over 1, x, y, z, xy, yz, zx, x^2 - y^2,
+// x^2 + y^2 - 2 z^2.
+__global__ __launch_bounds__(NT) void k_bem_harmonic(int64_t n, const double* __restrict__ y, Harmonic h,
+                                                     const double* __restrict__ s, double* __restrict__ f) {
+  const int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x;
+  if (i >= n) return;
+  const double x0 = y[3 * i], x1 = y[3 * i + 1], x2 = y[3 * i + 2];
+  const double v = h.c[0] + h.c[1] * x0 + h.c[2] * x1 + h.c[3] * x2 + h.c[4] * x0 * x1 + h.c[5] * x1 * x2 +
+                   h.c[6] * x2 * x0 + h.c[7] * (x0 * x0 - x1 * x1) +
+                   h.c[8] * (x0 * x0 + x1 * x1 - 2.0 * x2 * x2);
+  f[i] = s[i] * v;
+}
+
 __global__ __launch_bounds__(NT) void k_div(int64_t n, const double* __restrict__ x,
                                             const double* __restrict__ s, double* __restrict__ out) {
   const int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x;
@@ -98,6 +115,15 @@ void launch_bem_rhs(hipStream_t st, int64_t n, const double* y, const double* x0
   if (n == 0) return;
   hipLaunchKernelGGL(k_bem_rhs, dim3(blocks(n)), dim3(NT), 0, st, n, y, x0[0], x0[1], x0[2], s, f);
   check_launch("bem_rhs");
+}
+
+void launch_bem_harmonic(hipStream_t st, int64_t n, const double* y, const double* coeffs, const double* s,
+                         double* f) {
+  if (n == 0) return;
+  Harmonic h;
+  for (int k = 0; k < 9; ++k) h.c[k] = coeffs[k];
+  hipLaunchKernelGGL(k_bem_harmonic, dim3(blocks(n)), dim3(NT), 0, st, n, y, h, s, f);
+  check_launch("bem_harmonic");
 }
 
 void launch_div(hipStream_t st, int64_t n, const double* x, const double* s, double* out) {

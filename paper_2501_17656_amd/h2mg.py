@@ -383,6 +383,20 @@ def bem_point_source_rhs(centroids, scale, x0):
     return f
 
 
+def bem_harmonic_rhs(centroids, scale, coeffs):
+    """W^(1/2) f for f = sum_k c_k h_k, the harmonic basis 1, x, y, z, xy, yz,
+    zx, x^2 - y^2, x^2 + y^2 - 2 z^2 (nine floats)."""
+    import torch
+    n = int(scale.numel())
+    c = [float(v) for v in coeffs]
+    if len(c) != 9:
+        raise ValueError("coeffs must hold 9 values")
+    f = torch.empty(n, dtype=torch.float64, device=scale.device)
+    check(lib().h2mg_bem_harmonic_rhs(_dev_f64(centroids), _dev_f64(scale, n, "scale"), n,
+                                      (ctypes.c_double * 9)(*c), _dev_f64(f), _stream()))
+    return f
+
+
 def bem_density(y, scale):
     """sigma = y / s."""
     import torch

@@ -88,6 +88,13 @@ def bumpy_torus_mesh(n_major: int, n_minor: int, bumps: int = 40, amplitude: flo
     return V, tris.astype(np.int64)
 
 
+def harmonic_coefficients(seed: int = 7) -> np.ndarray:
+    """Nine N(0,1) coefficients for the degree-2 harmonic polynomial basis
+    (1, x, y, z, xy, yz, zx, x^2 - y^2, x^2 + y^2 - 2 z^2) of a random
+    boundary-element right-hand side."""
+    return np.random.default_rng(seed).standard_normal(9)
+
+
 def normal_vector(n: int, seed: int = 1, nrhs: int = 1) -> np.ndarray:
     """Standard normal vector (n,) or matrix (n, nrhs)."""
     rng = np.random.default_rng(seed)

@@ -17,7 +17,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle.bem import collocation_matrix, panels, point_source_rhs, symmetric_scaling
+from oracle.bem import collocation_matrix, harmonic_rhs, panels, point_source_rhs, symmetric_scaling
 from oracle.galerkin import Hierarchy
 from oracle.h2 import H2 as OracleH2
 
@@ -129,3 +129,23 @@ def test_bem_solve_gives_the_density(smoother, prec):
     assert info["converged"] and res < 1.5e-8
     assert err_h2 < 1e-5          # kappa(S) ~ 230 times the 1e-8 residual
     assert err < 4e-3             # the oracle's own A_H2 solution is 1.9e-3 away
+
+
+def test_bem_harmonic_rhs_solve_gives_the_density():
+    """Dirichlet data of a random harmonic polynomial (the benchmark's
+    right-hand side): the scaled values match the oracle's, and the FP32
+    block-smoother solve reaches the dense collocation density within the
+    compression error."""
+    from paper_2501_17656_amd import bem_density, bem_harmonic_rhs
+    V, T, y, s, d, g, o = bem_problem()
+    c = synth.harmonic_coefficients(7)
+    f = bem_harmonic_rhs(y, s, c)
+    yo, so, do = symmetric_scaling(V, T)
+    fo = so * harmonic_rhs(yo, c)
+    np.testing.assert_allclose(_host(f), fo, rtol=1e-13, atol=1e-15 * np.abs(fo).max())
+    sol, info = g.solve(f, rtol=1e-8, smoother="bj", precision="fp32")
+    sigma = _host(bem_density(sol, s))
+    sigma_dense = np.linalg.solve(collocation_matrix(V, T), harmonic_rhs(yo, c))
+    err = np.linalg.norm(sigma - sigma_dense) / np.linalg.norm(sigma_dense)
+    print(f"[gpu] bem harmonic rhs: {info['cycles']} cycles, density vs dense collocation {err:.2e}")
+    assert info["converged"] and err < 4e-3

@@ -114,6 +114,48 @@ def test_uniform_density_on_a_sphere_gives_the_radius():
     assert abs(np.median(u) / rho - 1) < 0.01
 
 
+def test_harmonic_basis_is_harmonic_and_independent():
+    from oracle.bem import harmonic_basis
+    rng = np.random.default_rng(4)
+    P = rng.random((50, 3))
+    h = 1e-3
+    lap = -6.0 * harmonic_basis(P)
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = h
+        lap += harmonic_basis(P + e) + harmonic_basis(P - e)
+    lap /= h * h
+    assert np.abs(lap).max() < 1e-5            # degree <= 2: central differences are exact
+    assert np.linalg.matrix_rank(harmonic_basis(P)) == 9
+
+
+@pytest.mark.parametrize("k,degree", [(0, 0), (3, 1), (4, 2), (8, 2)])
+def test_sphere_density_of_a_harmonic_polynomial(k, degree):
+    """On a sphere of radius rho the single layer maps the surface harmonic of
+    degree l to rho / (2 l + 1) times itself, so Dirichlet data given by a
+    homogeneous harmonic polynomial f of degree l has the density
+    sigma = (2 l + 1) f / rho.  The discretised system reproduces it away
+    from the poles of the latitude-longitude mesh (|z| < 0.8 rho, where its
+    triangles degenerate) to first order: the error halves when the mesh is
+    refined twice in each direction."""
+    from oracle.bem import harmonic_rhs, panels
+    rho = 0.7
+    errs = []
+    for nt, nphi in ((20, 40), (40, 80)):
+        V, T = _sphere(nt, nphi, radius=rho)
+        y = panels(V, T)[0]
+        c = np.zeros(9)
+        c[k] = 1.0
+        f = harmonic_rhs(y, c)
+        sigma = np.linalg.solve(collocation_matrix(V, T), f)
+        exact = (2 * degree + 1) * f / rho
+        band = np.abs(y[:, 2]) < 0.8 * rho
+        errs.append(np.linalg.norm((sigma - exact)[band]) / np.linalg.norm(exact[band]))
+        big = band & (np.abs(exact) > 0.3 * np.abs(exact).max())
+        assert abs(np.median(sigma[big] / exact[big]) - 1.0) < 0.02
+    assert errs[1] < 0.04 and errs[1] < 0.65 * errs[0], errs
+
+
 def test_symmetric_form_is_a_similarity_of_the_collocation_matrix():
     V, T = synth.bumpy_torus_mesh(24, 12, bumps=5, seed=3)
     A = collocation_matrix(V, T)
