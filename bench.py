@@ -378,6 +378,16 @@ def batched(args, torch, synth, H2Matrix):
         solve_group()
     nrhs_total = 16 * len(sizes)
     ok = all(p["batch_status"] == "OK" for p in per)
+    # tile-product rates of the largest problem (product + reduce, FP32, as tuned)
+    rates = {}
+    big = max(per, key=lambda p: p["n"])
+    for key, v in (big["tuning"] or {}).items():
+        if not v["ms"]:
+            continue
+        if key == "near":
+            rates["near_evaluated_Gentries_per_s"] = round(v["tiles_read"] * 4096 / (v["ms"] * 1e-3) / 1e9, 1)
+        else:
+            rates[f"{key}_GB_per_s"] = round(v["tiles_read"] * 32 * 32 * 4 / (v["ms"] * 1e-3) / 1e9, 1)
     out = {
         "workload": (f"{len(sizes)} problems, N log-uniform in [16384, 262144] (total {int(sizes.sum())} points), "
                      f"Gaussian-mixture clouds in 3D (8 components, sigma 0.05), gauss l=0.1 + {shift}*I "
@@ -393,6 +403,7 @@ def batched(args, torch, synth, H2Matrix):
         "single_rhs_solves_s_extrapolated": round(t_single, 3),
         "speedup_batched_vs_single_rhs": round(t_single / t_batch, 2),
         "speedup_batched_vs_sequential_blocks": round(t_seq / t_batch, 3),
+        "largest_problem_tile_rates": {"n": big["n"], **rates},
         "problems": per,
     }
     log(f"batched: {len(sizes)} problems x 16 RHS in {t_batch:.2f} s ({nrhs_total / t_batch:.1f} RHS/s), "

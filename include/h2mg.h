@@ -428,10 +428,12 @@ h2mg_status h2mg_set_graphs(h2mg_h2_t h, int32_t enabled);
  * on, tuned) at the next 16-column call. */
 h2mg_status h2mg_set_autotune(h2mg_h2_t h, int32_t enabled);
 /* The run length in use for a task set (which = -2: near field, -1: fine-level
- * couplings, d >= 0: restricted operator of depth d) and its measured time in
- * ms per product + reduce (0 when not tuned); run = 0 when that set has not
- * been built yet.  Errors: INVALID_ARG (null, which out of range). */
-h2mg_status h2mg_block_tuning(h2mg_h2_t h, int32_t which, int32_t* run, double* ms);
+ * couplings, d >= 0: restricted operator of depth d), its measured time in
+ * ms per product + reduce (0 when not tuned) and the tiles one product reads
+ * (every tile once for its block row, the off-diagonal ones again for their
+ * block column); run = 0 when that set has not been built yet.  Errors:
+ * INVALID_ARG (null, which out of range). */
+h2mg_status h2mg_block_tuning(h2mg_h2_t h, int32_t which, int32_t* run, double* ms, int64_t* tiles_read);
 
 /* Kernel timing, for measurement harnesses.  While enabled, every launch of
  * the block GEMV and of the near-field kernel is bracketed by HIP events on

@@ -72,7 +72,7 @@ SIGNATURES = {
     "h2mg_store_near": (c_int32, [c_void_p, c_int32, c_void_p]),
     "h2mg_set_graphs": (c_int32, [c_void_p, c_int32]),
     "h2mg_set_autotune": (c_int32, [c_void_p, c_int32]),
-    "h2mg_block_tuning": (c_int32, [c_void_p, c_int32, P_int32, P_double]),
+    "h2mg_block_tuning": (c_int32, [c_void_p, c_int32, P_int32, P_double, P_int64]),
     "h2mg_matvec_multi": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_int32, c_void_p]),
     "h2mg_solve_multi": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_int32,
                                    ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), P_double, c_void_p]),

@@ -437,9 +437,9 @@ h2mg_status h2mg_set_autotune(h2mg_h2_t hh, int32_t enabled) {
   });
 }
 
-h2mg_status h2mg_block_tuning(h2mg_h2_t hh, int32_t which, int32_t* run, double* ms) {
+h2mg_status h2mg_block_tuning(h2mg_h2_t hh, int32_t which, int32_t* run, double* ms, int64_t* tiles_read) {
   return guarded([&] {
-    if (!hh || !run || !ms) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    if (!hh || !run || !ms || !tiles_read) return fail(H2MG_ERR_INVALID_ARG, "null argument");
     const H2& h = *hh->h;
     const BlockWork& w = h.blk16;
     const TileSet* ts = nullptr;
@@ -449,6 +449,7 @@ h2mg_status h2mg_block_tuning(h2mg_h2_t hh, int32_t which, int32_t* run, double*
     else if (which < -2 || which > h.L) return fail(H2MG_ERR_INVALID_ARG, "which must be -2, -1 or a depth");
     *run = ts ? ts->run : 0;
     *ms = ts ? ts->tuned_ms : 0.0;
+    *tiles_read = ts ? ts->ntiles + ts->nctiles : 0;
     return H2MG_OK;
   });
 }

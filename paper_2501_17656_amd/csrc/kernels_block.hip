@@ -28,6 +28,7 @@
 
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 
 #include "h2_impl.h"
 
@@ -149,55 +150,68 @@ __device__ __forceinline__ void tgemm_body(const int* __restrict__ rtask, int nr
   typename M::acc_t acc[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) acc[s] = typename M::acc_t{Tv(0), Tv(0), Tv(0), Tv(0)};
-  typename Stage::Regs regs;
-  int b = tile_of(i0);
-  if constexpr (Stage::PREFETCH) stage.load(b, regs);
-  for (int it = i0; it < i1; ++it) {
-    const int o = other_of(it, b);
-    const Tv* xo = x + int64_t(o) * rr * NR;
-    // operand rows: loaded ahead for tiles up to 32 x 32, inside the product
-    // loop for 64 x 64 tiles (whose registers go to staging)
-    constexpr bool XPRE = NKB <= 8;
-    Tv xr[XPRE ? NKB : 1];
-    if constexpr (XPRE) {
+  // The pass (row or transposed) is uniform per block; each has its own loop
+  // with the LDS addressing fixed at compile time.
+  auto run = [&](auto trc) {
+    constexpr bool TR = decltype(trc)::value;
+    // row pass: operand row 16s + p is fixed per s, its swizzle hoisted
+    int rowsw[NS];
 #pragma unroll
-      for (int kb = 0; kb < NKB; ++kb) {
-        const int kr = 4 * kb + q;
-        xr[kb] = kr < rr ? xo[kr * NR + p] : Tv(0);
+    for (int s = 0; s < NS; ++s) rowsw[s] = swz<RP, EB>(16 * s + p);
+    auto mma_step = [&](int kb, Tv xb) {
+      const int kr = 4 * kb + q;
+      if constexpr (TR) {
+        const int sk = swz<RP, EB>(kr);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc[s] = M::mma(lds[kr * RP + ((16 * s + p) ^ sk)], xb, acc[s]);
+      } else {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc[s] = M::mma(lds[(16 * s + p) * RP + (kr ^ rowsw[s])], xb, acc[s]);
       }
-    }
-    __syncthreads();                   // the previous tile's operand reads are done
-    if constexpr (!Stage::PREFETCH) stage.load(b, regs);
-    stage.store(b, regs, put);
-    if (it + 1 < i1) {
-      b = tile_of(it + 1);
-      if constexpr (Stage::PREFETCH) stage.load(b, regs);
-    }
-    __syncthreads();
-    if constexpr (XPRE) {
+    };
+    typename Stage::Regs regs;
+    int b = tile_of(i0);
+    if constexpr (Stage::PREFETCH) stage.load(b, regs);
+    for (int it = i0; it < i1; ++it) {
+      const int o = other_of(it, b);
+      const Tv* xo = x + int64_t(o) * rr * NR;
+      // operand rows: loaded ahead for tiles up to 32 x 32, inside the product
+      // loop for 64 x 64 tiles (whose registers go to staging)
+      constexpr bool XPRE = NKB <= 8;
+      Tv xr[XPRE ? NKB : 1];
+      if constexpr (XPRE) {
 #pragma unroll
-      for (int kb = 0; kb < NKB; ++kb) {
-        if (kb < nkb) {
+        for (int kb = 0; kb < NKB; ++kb) {
           const int kr = 4 * kb + q;
-#pragma unroll
-          for (int s = 0; s < NS; ++s) {
-            const int ri = tr ? kr : 16 * s + p, cj = tr ? 16 * s + p : kr;
-            acc[s] = M::mma(lds[ri * RP + (cj ^ swz<RP, EB>(ri))], xr[kb], acc[s]);
-          }
+          xr[kb] = kr < rr ? xo[kr * NR + p] : Tv(0);
         }
       }
-    } else {
-      for (int kb = 0; kb < nkb; ++kb) {
-        const int kr = 4 * kb + q;
-        const Tv xb = kr < rr ? xo[kr * NR + p] : Tv(0);
+      __syncthreads();                 // the previous tile's operand reads are done
+      if constexpr (!Stage::PREFETCH) stage.load(b, regs);
+      stage.store(b, regs, put);
+      if (it + 1 < i1) {
+        b = tile_of(it + 1);
+        if constexpr (Stage::PREFETCH) stage.load(b, regs);
+      }
+      __syncthreads();
+      if constexpr (XPRE) {
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-          const int ri = tr ? kr : 16 * s + p, cj = tr ? 16 * s + p : kr;
-          acc[s] = M::mma(lds[ri * RP + (cj ^ swz<RP, EB>(ri))], xb, acc[s]);
+        for (int kb = 0; kb < NKB; ++kb)
+          if (kb < nkb) mma_step(kb, xr[kb]);
+      } else if (nkb == NKB) {
+#pragma unroll 4
+        for (int kb = 0; kb < NKB; ++kb) mma_step(kb, xo[(4 * kb + q) * NR + p]);
+      } else {
+#pragma unroll 4
+        for (int kb = 0; kb < nkb; ++kb) {
+          const int kr = 4 * kb + q;
+          mma_step(kb, kr < rr ? xo[kr * NR + p] : Tv(0));
         }
       }
     }
-  }
+  };
+  if (tr) run(std::integral_constant<bool, true>{});
+  else run(std::integral_constant<bool, false>{});
   Tv* out = out_base + int64_t(blk) * rr * NR;
   const Tv* add = addend ? addend + int64_t(blk) * rr * NR : nullptr;
 #pragma unroll
@@ -254,7 +268,7 @@ struct StageStored {
         }
     } else {
       const Te* tile = tiles + int64_t(b) * tile_elems(T);
-#pragma unroll 8
+#pragma unroll 32
       for (int c = 0; c < NCH; ++c) {
         Chunk u;
         load_chunk(tile + (c * 64 + l) * K, u);

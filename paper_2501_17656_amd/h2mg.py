@@ -284,17 +284,18 @@ class H2Matrix:
         check(lib().h2mg_set_autotune(self._h, int(bool(enabled))))
 
     def block_tuning(self) -> dict:
-        """Run length and measured ms of every built 16-column task set:
-        keys "near", "fine" and the depths of the restricted operators."""
+        """Run length, measured ms (product + reduce) and tiles read per
+        product of every built 16-column task set: keys "near", "fine" and
+        the depths of the restricted operators."""
         out = {}
         for which in [-2, -1] + list(range(0, 64)):
-            run, ms = ctypes.c_int32(), ctypes.c_double()
-            st = lib().h2mg_block_tuning(self._h, which, ctypes.byref(run), ctypes.byref(ms))
+            run, ms, tiles = ctypes.c_int32(), ctypes.c_double(), ctypes.c_int64()
+            st = lib().h2mg_block_tuning(self._h, which, ctypes.byref(run), ctypes.byref(ms), ctypes.byref(tiles))
             if st != 0:
                 break
             if run.value:
                 key = {-2: "near", -1: "fine"}.get(which, which)
-                out[key] = {"run": run.value, "ms": round(ms.value, 4)}
+                out[key] = {"run": run.value, "ms": round(ms.value, 4), "tiles_read": tiles.value}
         return out
 
     def set_timing(self, enabled: bool) -> None:
