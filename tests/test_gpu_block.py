@@ -112,6 +112,20 @@ def test_block_solve_reaches_oracle_solution(name, nrhs, prec, smoother):
     assert info["converged"] and info["rel_residual"] < 1e-8
 
 
+def test_block_single_level_direct_solve():
+    """No far blocks: one level, solved directly by the dense Cholesky factor
+    on all 16 columns in one cycle."""
+    P, g, o, H = make("no_far")
+    n = len(P)
+    B = synth.normal_vector(n, 38, nrhs=16)
+    X, info = g.solve_multi(_dev(B), rtol=1e-8)
+    X = _host(X)
+    assert g.levels == 1 and info["cycles"] == 1
+    for k in range(16):
+        res = np.linalg.norm(B[:, k] - o.matvec(X[:, k])) / np.linalg.norm(B[:, k])
+        assert res < 1e-12, (k, res)
+
+
 def test_block_columns_are_independent():
     """A column's iterate does not depend on the other columns: solving a
     single column reproduces that column of the 16-column cycles (the per
