@@ -344,13 +344,15 @@ h2mg_status h2mg_solve_multi(h2mg_h2_t h, int32_t nrhs, const double* b_dev, int
  * the device busy together; with h2mg_set_graphs on a handle its cycles are
  * graph launches.  Every stream first waits for the work already enqueued
  * on `stream`; the call returns when every problem has finished.  Handles
- * must be distinct.  infos: host array of nprob entries, or null.  Returns
- * the status of the first failing problem (the others still run to their
- * end); errors as h2mg_solve_multi. */
+ * must be distinct.  infos, statuses: host arrays of nprob entries (each
+ * problem's info and status), or null.  Returns the status of the first
+ * failing problem (the others still run to their end); errors as
+ * h2mg_solve_multi. */
 h2mg_status h2mg_solve_batch(int32_t nprob, const h2mg_h2_t* hs, const int32_t* nrhs,
                              const double* const* b_dev, const int32_t* ldb, double* const* x_dev,
                              const int32_t* ldx, const h2mg_solve_opts* opts,
-                             h2mg_solve_info* infos, int32_t nstreams, hipStream_t stream);
+                             h2mg_solve_info* infos, h2mg_status* statuses, int32_t nstreams,
+                             hipStream_t stream);
 
 /* Build the H2-MG hierarchy (Section 3.3): restricted operators
  * A_k = U_{k-1}^T A_{k-1} V_{k-1}^T for every level, i.e. the projected close

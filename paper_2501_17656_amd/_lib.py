@@ -78,7 +78,7 @@ SIGNATURES = {
                                    ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), P_double, c_void_p]),
     "h2mg_solve_batch": (c_int32, [c_int32, ctypes.POINTER(c_void_p), P_int32, ctypes.POINTER(c_void_p), P_int32,
                                    ctypes.POINTER(c_void_p), P_int32, ctypes.POINTER(SolveOpts),
-                                   ctypes.POINTER(SolveInfo), c_int32, c_void_p]),
+                                   ctypes.POINTER(SolveInfo), P_int32, c_int32, c_void_p]),
     "h2mg_build_scaled": (c_int32, [c_void_p, c_int64, c_int32, ctypes.POINTER(Kernel), ctypes.POINTER(BuildOpts),
                                     c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_void_p)]),
     "h2mg_bem_panels": (c_int32, [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),

@@ -401,7 +401,7 @@ h2mg_status h2mg_solve_multi(h2mg_h2_t hh, int32_t nrhs, const double* b, int32_
 h2mg_status h2mg_solve_batch(int32_t nprob, const h2mg_h2_t* hs, const int32_t* nrhs,
                              const double* const* b, const int32_t* ldb, double* const* x,
                              const int32_t* ldx, const h2mg_solve_opts* opts, h2mg_solve_info* infos,
-                             int32_t nstreams, hipStream_t stream) {
+                             h2mg_status* statuses, int32_t nstreams, hipStream_t stream) {
   return guarded([&] {
     if (nprob < 1 || !hs || !nrhs || !b || !ldb || !x || !ldx)
       return fail(H2MG_ERR_INVALID_ARG, "null argument or empty batch");
@@ -412,7 +412,8 @@ h2mg_status h2mg_solve_batch(int32_t nprob, const h2mg_h2_t* hs, const int32_t* 
       if (!hs[i]) return fail(H2MG_ERR_INVALID_ARG, "null handle in problem %d", i);
       hv[i] = hs[i]->h;
     }
-    return solve_batch(nprob, hv.data(), nrhs, b, ldb, x, ldx, to_params(opts), infos, nstreams, stream);
+    return solve_batch(nprob, hv.data(), nrhs, b, ldb, x, ldx, to_params(opts), infos, statuses, nstreams,
+                       stream);
   });
 }
 

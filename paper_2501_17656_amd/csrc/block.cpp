@@ -684,7 +684,7 @@ h2mg_status solve_multi(H2& h, int nrhs, const double* b, int ldb, double* x, in
 
 h2mg_status solve_batch(int nprob, H2* const* hs, const int* nrhs, const double* const* b, const int* ldb,
                         double* const* x, const int* ldx, const SolveParams& sp, h2mg_solve_info* infos,
-                        int nstreams, hipStream_t user) {
+                        h2mg_status* statuses, int nstreams, hipStream_t user) {
   if (nprob < 1) return fail(H2MG_ERR_INVALID_ARG, "a batch needs at least one problem");
   for (int i = 0; i < nprob; ++i) {
     if (!hs[i] || !b[i] || !x[i]) return fail(H2MG_ERR_INVALID_ARG, "null argument in problem %d", i);
@@ -764,6 +764,8 @@ h2mg_status solve_batch(int nprob, H2* const* hs, const int* nrhs, const double*
                                : fail(err, "%s", message[0].c_str());
   }
   cleanup();
+  if (statuses)
+    for (int i = 0; i < nprob; ++i) statuses[i] = result[i];
   for (int i = 0; i < nprob; ++i)
     if (result[i] != H2MG_OK) return fail(result[i], "problem %d: %s", i, message[i].c_str());
   return H2MG_OK;

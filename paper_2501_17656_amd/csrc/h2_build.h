@@ -75,9 +75,10 @@ h2mg_status solve_multi(H2& h, int nrhs, const double* b, int ldb, double* x, in
 // Independent problems solved together: problem i on handle hs[i] (distinct
 // handles), with its cycles on one of nstreams streams; every stream first
 // waits for the work enqueued so far on `user`.  Returns the first failing
-// problem's status (the others still run to their end).
+// problem's status (the others still run to their end); statuses (may be
+// null) receives every problem's.
 h2mg_status solve_batch(int nprob, H2* const* hs, const int* nrhs, const double* const* b, const int* ldb,
                         double* const* x, const int* ldx, const SolveParams& sp, h2mg_solve_info* infos,
-                        int nstreams, hipStream_t user);
+                        h2mg_status* statuses, int nstreams, hipStream_t user);
 
 }  // namespace h2mg

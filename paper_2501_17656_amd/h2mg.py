@@ -348,9 +348,11 @@ def solve_batch(problems, rtol: float = 1e-8, n_fine: int = 1, n_coarse: int = 4
         xp[i] = _dev_f64(X, name="X").value
     o = H2Matrix._opts(rtol, n_fine, n_coarse, max_cycles, precision, 0, smoother, method)
     infos = (_lib.SolveInfo * k)()
-    st = lib().h2mg_solve_batch(k, hs, nr, bp, nr, xp, nr, ctypes.byref(o), infos, int(nstreams), _stream())
+    stats = (ctypes.c_int32 * k)()
+    st = lib().h2mg_solve_batch(k, hs, nr, bp, nr, xp, nr, ctypes.byref(o), infos, stats, int(nstreams),
+                                _stream())
     msg = _lib.last_error() if st != 0 else ""
-    out = [_info_dict(g, infos[i], st, msg) for i, (g, _) in enumerate(problems)]
+    out = [_info_dict(g, infos[i], stats[i], msg if stats[i] else "") for i, (g, _) in enumerate(problems)]
     if st != 0 and raise_on_error:
         check(st, msg)
     return xs, out

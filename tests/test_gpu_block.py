@@ -200,6 +200,25 @@ def test_autotuned_runs_keep_results():
     assert rel <= CYCLE_TOL["gauss3d_gmm4k_r27"]
 
 
+def test_batch_reports_a_failing_problem_and_finishes_the_others():
+    """One problem of the batch is indefinite after compression (the rank-27
+    Gaussian-mixture shape of the single-vector error tests): the batch
+    returns its NOT_SPD status while the other problem still converges."""
+    from paper_2501_17656_amd import H2Matrix, H2MGError, solve_batch
+    kind, n, dim, ker, ell, shift, leaf, eta, m = SHAPES["gauss3d_gmm_r27"]
+    bad = H2Matrix(_dev(_points(kind, n, dim)), ker, ell, shift, leaf, eta, m)
+    P = synth.gaussian_mixture_points(3000, 3, seed=41)
+    good = H2Matrix(_dev(P), "gauss", 0.1, 1.0, 64, 0.7, 3)
+    probs = [(bad, _dev(synth.normal_vector(n, 60, nrhs=4))), (good, _dev(synth.normal_vector(3000, 61, nrhs=4)))]
+    with pytest.raises(H2MGError, match="NOT_SPD"):
+        solve_batch(probs, rtol=1e-8, smoother="bj")
+    xs, infos = solve_batch(probs, rtol=1e-8, smoother="bj", raise_on_error=False)
+    assert infos[0]["status"] == "NOT_SPD" and not infos[0]["converged"]
+    assert infos[1]["converged"] and infos[1]["rel_residual"] < 1e-8
+    bad.close()
+    good.close()
+
+
 def test_block_error_paths():
     from paper_2501_17656_amd import H2Matrix, H2MGError, solve_batch
     P, g, o, H = make("exp2d_4k")
