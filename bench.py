@@ -76,6 +76,8 @@ def parse():
                     help="torus parameter grid (panels = 2 * a * b)")
     ap.add_argument("--cpu-leaves", type=int, default=48)
     ap.add_argument("--json-out", default="")
+    ap.add_argument("--block-product", action="store_true",
+                    help="run only the 16-vector block product on the headline matrix")
     ap.add_argument("--batched", action="store_true",
                     help="run only the batched solve of many uneven problems with 16 RHS each")
     ap.add_argument("--batch-problems", type=int, default=48)
@@ -247,6 +249,27 @@ def block_product(args, torch, g, w, single_ms):
 def synth_block(w, nrhs):
     import synth
     return synth.normal_vector(w.n, w.x_seed, nrhs=nrhs)
+
+
+def block_product_only(args, torch, synth, H2Matrix):
+    """Only the 16-vector block product on the 2^20 headline matrix (near
+    field stored, tile runs tuned), for profiling its kernels."""
+    w = synth.workload(args.headline)
+    g = H2Matrix(torch.from_numpy(w.make_points()).cuda(), w.kernel, w.length_scale, w.shift, w.leaf,
+                 w.eta, w.cheb_m)
+    g.store_near(True)
+    single = torch.from_numpy(w.make_x()).cuda()
+    y = g.matvec(single)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.matvec_reps):
+        g.matvec(single, out=y)
+    torch.cuda.synchronize()
+    single_ms = (time.perf_counter() - t0) / args.matvec_reps * 1e3
+    out = block_product(args, torch, g, w, single_ms)
+    out["single_product_ms"] = round(single_ms, 3)
+    g.close()
+    return out
 
 
 def stored_near_matvec(args, torch, g, w, time_matvecs):
@@ -751,6 +774,9 @@ def main():
         return
     if args.error_components:
         error_components(args, torch, synth, H2Matrix)
+        return
+    if args.block_product:
+        print(json.dumps({"block_product": block_product_only(args, torch, synth, H2Matrix)}), flush=True)
         return
     if args.batched:
         out = batched(args, torch, synth, H2Matrix)
