@@ -95,11 +95,13 @@ template <> struct Mfma<float> {
 // children c = 2s, 2s+1 (tiles base + c).  MODE_DOWN (transfer to the
 // children): block c computes E_c x[c / 2] (tile base + c), plus addend[c]
 // when addend is not null.
-// The stage object fills LDS with a tile: load(b, regs) issues its global
-// loads, store(b, regs, put) writes entry (i, j) through put(i, j, value).
-// When Stage::PREFETCH, the loads of the next tile are issued right after the
-// current tile is in LDS, so they overlap its products; the operand rows of
-// the tile are loaded before it is staged.
+// A block has one wave per 16-row slab of the result (RP / 16 = T / 2
+// waves); all of them stage the tile into LDS together, then wave w runs the
+// matrix-core products of slab w.  The stage object fills LDS: load(b, regs)
+// issues this thread's share of the tile's global loads, store(b, regs, put)
+// writes entry (i, j) through put(i, j, value).  When Stage::PREFETCH, the
+// loads of the next tile are issued as soon as the current one is in LDS, so
+// they overlap its products; the operand rows are loaded before staging.
 enum { MODE_LIST = 0, MODE_UP = 1, MODE_DOWN = 2 };
 
 template <int T, int MODE, typename Tv, typename Stage>
@@ -111,7 +113,7 @@ __device__ __forceinline__ void tgemm_body(const int* __restrict__ rtask, int nr
                                            const int* __restrict__ bcol, int base, int rr,
                                            const Tv* __restrict__ x, Tv* out_base, const Tv* addend,
                                            Tv* lds, const Stage& stage) {
-  constexpr int RP = 8 * T, NS = RP / 16, NKB = RP / 4;
+  constexpr int RP = 8 * T, NKB = RP / 4;
   constexpr int EB = int(sizeof(Tv));
   using M = Mfma<Tv>;
   const int blk = blockIdx.x;
@@ -144,30 +146,20 @@ __device__ __forceinline__ void tgemm_body(const int* __restrict__ rtask, int nr
     else if constexpr (MODE == MODE_UP) return it;
     else return it >> 1;
   };
-  const int l = threadIdx.x, p = l & 15, q = l >> 4;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, p = l & 15, q = l >> 4;
   const int nkb = (rr + 3) >> 2;
   auto put = [&](int i, int j, Tv v) { lds[i * RP + (j ^ swz<RP, EB>(i))] = v; };
-  typename M::acc_t acc[NS];
-#pragma unroll
-  for (int s = 0; s < NS; ++s) acc[s] = typename M::acc_t{Tv(0), Tv(0), Tv(0), Tv(0)};
+  typename M::acc_t acc = typename M::acc_t{Tv(0), Tv(0), Tv(0), Tv(0)};
+  const int slab = 16 * w + p;          // this lane's result row (row pass) / column (transposed)
   // The pass (row or transposed) is uniform per block; each has its own loop
   // with the LDS addressing fixed at compile time.
   auto run = [&](auto trc) {
     constexpr bool TR = decltype(trc)::value;
-    // row pass: operand row 16s + p is fixed per s, its swizzle hoisted
-    int rowsw[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) rowsw[s] = swz<RP, EB>(16 * s + p);
+    const int slabsw = swz<RP, EB>(slab);
     auto mma_step = [&](int kb, Tv xb) {
       const int kr = 4 * kb + q;
-      if constexpr (TR) {
-        const int sk = swz<RP, EB>(kr);
-#pragma unroll
-        for (int s = 0; s < NS; ++s) acc[s] = M::mma(lds[kr * RP + ((16 * s + p) ^ sk)], xb, acc[s]);
-      } else {
-#pragma unroll
-        for (int s = 0; s < NS; ++s) acc[s] = M::mma(lds[(16 * s + p) * RP + (kr ^ rowsw[s])], xb, acc[s]);
-      }
+      if constexpr (TR) acc = M::mma(lds[kr * RP + (slab ^ swz<RP, EB>(kr))], xb, acc);
+      else acc = M::mma(lds[slab * RP + (kr ^ slabsw)], xb, acc);
     };
     typename Stage::Regs regs;
     int b = tile_of(i0);
@@ -175,18 +167,13 @@ __device__ __forceinline__ void tgemm_body(const int* __restrict__ rtask, int nr
     for (int it = i0; it < i1; ++it) {
       const int o = other_of(it, b);
       const Tv* xo = x + int64_t(o) * rr * NR;
-      // operand rows: loaded ahead for tiles up to 32 x 32, inside the product
-      // loop for 64 x 64 tiles (whose registers go to staging)
-      constexpr bool XPRE = NKB <= 8;
-      Tv xr[XPRE ? NKB : 1];
-      if constexpr (XPRE) {
+      Tv xr[NKB];
 #pragma unroll
-        for (int kb = 0; kb < NKB; ++kb) {
-          const int kr = 4 * kb + q;
-          xr[kb] = kr < rr ? xo[kr * NR + p] : Tv(0);
-        }
+      for (int kb = 0; kb < NKB; ++kb) {
+        const int kr = 4 * kb + q;
+        xr[kb] = kr < rr ? xo[kr * NR + p] : Tv(0);
       }
-      __syncthreads();                 // the previous tile's operand reads are done
+      __syncthreads();                 // every wave's operand reads of the previous tile are done
       if constexpr (!Stage::PREFETCH) stage.load(b, regs);
       stage.store(b, regs, put);
       if (it + 1 < i1) {
@@ -194,20 +181,9 @@ __device__ __forceinline__ void tgemm_body(const int* __restrict__ rtask, int nr
         if constexpr (Stage::PREFETCH) stage.load(b, regs);
       }
       __syncthreads();
-      if constexpr (XPRE) {
 #pragma unroll
-        for (int kb = 0; kb < NKB; ++kb)
-          if (kb < nkb) mma_step(kb, xr[kb]);
-      } else if (nkb == NKB) {
-#pragma unroll 4
-        for (int kb = 0; kb < NKB; ++kb) mma_step(kb, xo[(4 * kb + q) * NR + p]);
-      } else {
-#pragma unroll 4
-        for (int kb = 0; kb < nkb; ++kb) {
-          const int kr = 4 * kb + q;
-          mma_step(kb, kr < rr ? xo[kr * NR + p] : Tv(0));
-        }
-      }
+      for (int kb = 0; kb < NKB; ++kb)
+        if (kb < nkb) mma_step(kb, xr[kb]);
     }
   };
   if (tr) run(std::integral_constant<bool, true>{});
@@ -215,28 +191,28 @@ __device__ __forceinline__ void tgemm_body(const int* __restrict__ rtask, int nr
   Tv* out = out_base + int64_t(blk) * rr * NR;
   const Tv* add = addend ? addend + int64_t(blk) * rr * NR : nullptr;
 #pragma unroll
-  for (int s = 0; s < NS; ++s)
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int row = 16 * s + M::row(t, q);
-      if (row < rr) out[row * NR + p] = add ? acc[s][t] + add[row * NR + p] : acc[s][t];
-    }
+  for (int t = 0; t < 4; ++t) {
+    const int row = 16 * w + M::row(t, q);
+    if (row < rr) out[row * NR + p] = add ? acc[t] + add[row * NR + p] : acc[t];
+  }
 }
 
-// Stored tiles: lane (a, b) of the 8 x 8 lane grid reads its T x T sub-block
-// as coalesced 16-byte chunks of the storage layout.  Tiles of at most 8
-// chunks per lane (T <= 4) are prefetched into registers; 64 x 64 tiles are
-// loaded and staged chunk by chunk.
+// Stored tiles: lane (a, b) of the 8 x 8 lane grid holds the T x T sub-block
+// of rows aT.., columns bT.. of the storage layout, cut into NCH chunks of 16
+// bytes; wave w of the block loads chunks w, w + W, ... (W = T / 2 waves),
+// so each thread keeps NCH / W chunks in registers while they are in flight.
 template <int T, typename Te, typename Tv>
 struct StageStored {
-  static constexpr int K = tile_K<Te>(T), NCH = T * T / K;
-  static constexpr bool PREFETCH = NCH <= 8;
+  static constexpr int W = T / 2;
+  static constexpr int K = tile_K<Te>(T), NCH = T * T / K, NPW = NCH / W;
+  static constexpr bool PREFETCH = true;
+  static_assert(NCH % W == 0, "chunks must split evenly over the waves");
   union Chunk {
     u32x4 q4;
     Te e[16 / sizeof(Te)];
   };
   struct Regs {
-    Chunk c[PREFETCH ? NCH : 1];
+    Chunk c[NPW];
   };
   const Te* tiles;
   __device__ __forceinline__ static void load_chunk(const Te* src, Chunk& u) {
@@ -248,49 +224,33 @@ struct StageStored {
     }
   }
   __device__ __forceinline__ void load(int b, Regs& R) const {
-    if constexpr (PREFETCH) {
-      const int l = threadIdx.x;
-      const Te* tile = tiles + int64_t(b) * tile_elems(T);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const Te* tile = tiles + int64_t(b) * tile_elems(T);
 #pragma unroll
-      for (int c = 0; c < NCH; ++c) load_chunk(tile + (c * 64 + l) * K, R.c[c]);
-    }
+    for (int cc = 0; cc < NPW; ++cc) load_chunk(tile + ((w + W * cc) * 64 + l) * K, R.c[cc]);
   }
   template <typename Put>
-  __device__ __forceinline__ void store(int b, const Regs& R, Put& put) const {
-    const int l = threadIdx.x, a = l >> 3, bb = l & 7;
-    if constexpr (PREFETCH) {
+  __device__ __forceinline__ void store(int, const Regs& R, Put& put) const {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, a = l >> 3, bb = l & 7;
 #pragma unroll
-      for (int c = 0; c < NCH; ++c)
+    for (int cc = 0; cc < NPW; ++cc)
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const int el = c * K + k;
-          put(T * a + el / T, T * bb + el % T, ld_as<Tv, Te>(R.c[c].e[k]));
-        }
-    } else {
-      const Te* tile = tiles + int64_t(b) * tile_elems(T);
-#pragma unroll 32
-      for (int c = 0; c < NCH; ++c) {
-        Chunk u;
-        load_chunk(tile + (c * 64 + l) * K, u);
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const int el = c * K + k;
-          put(T * a + el / T, T * bb + el % T, ld_as<Tv, Te>(u.e[k]));
-        }
+      for (int k = 0; k < K; ++k) {
+        const int el = (w + W * cc) * K + k;
+        put(T * a + el / T, T * bb + el % T, ld_as<Tv, Te>(R.c[cc].e[k]));
       }
-    }
   }
 };
 
 template <int T, typename Te, typename Tv>
-__global__ __launch_bounds__(64) void k_tgemm(const int* __restrict__ rtask, int nrt,
-                                              const int* __restrict__ rorder,
-                                              const int* __restrict__ ctask,
-                                              const int* __restrict__ corder,
-                                              const Te* __restrict__ tiles,
-                                              const int* __restrict__ brow,
-                                              const int* __restrict__ bcol, int rr,
-                                              const Tv* __restrict__ x, Tv* __restrict__ partial) {
+__global__ __launch_bounds__(32 * T) void k_tgemm(const int* __restrict__ rtask, int nrt,
+                                                  const int* __restrict__ rorder,
+                                                  const int* __restrict__ ctask,
+                                                  const int* __restrict__ corder,
+                                                  const Te* __restrict__ tiles,
+                                                  const int* __restrict__ brow,
+                                                  const int* __restrict__ bcol, int rr,
+                                                  const Tv* __restrict__ x, Tv* __restrict__ partial) {
   __shared__ Tv lds[64 * T * T];
   tgemm_body<T, MODE_LIST>(rtask, nrt, rorder, ctask, corder, brow, bcol, 0, rr, x, partial,
                            static_cast<const Tv*>(nullptr), lds, StageStored<T, Te, Tv>{tiles});
@@ -298,13 +258,16 @@ __global__ __launch_bounds__(64) void k_tgemm(const int* __restrict__ rtask, int
 
 // Transfers between depth d + 1 (children, gids base + c) and depth d.
 template <int T, int MODE, typename Te, typename Tv>
-__global__ __launch_bounds__(64) void k_transfer16(const Te* __restrict__ E, int base, int r,
-                                                   const Tv* __restrict__ x, Tv* out, const Tv* addend) {
+__global__ __launch_bounds__(32 * T) void k_transfer16(const Te* __restrict__ E, int base, int r,
+                                                       const Tv* __restrict__ x, Tv* out, const Tv* addend) {
   __shared__ Tv lds[64 * T * T];
   tgemm_body<T, MODE>(nullptr, 0, nullptr, nullptr, nullptr, nullptr, nullptr, base, r, x, out, addend, lds,
                       StageStored<T, Te, Tv>{E});
 }
 
+// Near-field tiles evaluated from the points: lane (a, b) of wave w
+// evaluates rows 8a + 2w, 8a + 2w + 1 and columns 8b .. 8b+7 of the 64 x 64
+// tile (4 waves).
 template <typename Tv, int KIND, int DERIV>
 struct StageEval {
   static constexpr bool PREFETCH = false;
@@ -320,7 +283,7 @@ struct StageEval {
   __device__ __forceinline__ void load(int, Regs&) const {}
   template <typename Put>
   __device__ __forceinline__ void store(int b, const Regs&, Put& put) const {
-    const int l = threadIdx.x, a = l >> 3, bb = l & 7;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, a = l >> 3, bb = l & 7;
     const Tv inv_l = Tv(kp.inv_l), inv_2l2 = Tv(kp.inv_2l2);
     const int rs = chunk_start[brow[b]], nr = chunk_n[brow[b]];
     const int cs = chunk_start[bcol[b]], nc = chunk_n[bcol[b]];
@@ -331,9 +294,9 @@ struct StageEval {
 #pragma unroll
       for (int d = 0; d < 3; ++d) pc[v][d] = (j < nc && d < dim) ? pts[int64_t(cs + j) * dim + d] : 0.0;
     }
-#pragma unroll 2
-    for (int u = 0; u < 8; ++u) {
-      const int i = 8 * a + u;
+#pragma unroll
+    for (int uu = 0; uu < 2; ++uu) {
+      const int i = 8 * a + 2 * w + uu;
       const bool rowok = i < nr;
       double pr[3];
 #pragma unroll
@@ -344,14 +307,16 @@ struct StageEval {
         const int j = 8 * bb + v;
         Tv e = Tv(0);
         if (rowok && j < nc) {
-          double r2 = 0.0;
+          // coordinate differences in FP64 (no cancellation), their squares
+          // in the vector precision
+          Tv r2 = Tv(0);
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
-            const double dx = pr[d] - pc[v][d];
+            const Tv dx = Tv(pr[d] - pc[v][d]);
             r2 += dx * dx;
           }
           const int64_t gj = int64_t(cs) + j;
-          e = kernel_fixed<KIND, DERIV, Tv>(inv_l, inv_2l2, Tv(r2));
+          e = kernel_fixed<KIND, DERIV, Tv>(inv_l, inv_2l2, r2);
           if (ps.s) e *= Tv(ps.s[gi] * ps.s[gj]);
           if (gi == gj) e += Tv(ps.d ? ps.d[gi] : kp.shift);
         }
@@ -365,21 +330,20 @@ struct StageEval {
 // block between chunk brow[b] and chunk bcol[b] (at most 64 consecutive
 // points of a leaf each; chunk_start / chunk_n), entry (i, j) = the scaled
 // kernel s_i k(|p_i - p_j|) s_j plus the diagonal (the per-point d, else the
-// shift) where a point meets itself, zero outside the chunks.  The kernel is
-// evaluated in the vector precision from squared distances formed in FP64.
-// Lane (a, b) evaluates rows 8a .. 8a+7 and columns 8b .. 8b+7.
+// shift) where a point meets itself, zero outside the chunks.  Coordinate
+// differences are formed in FP64, the rest in the vector precision.
 template <typename Tv, int KIND, int DERIV>
-__global__ __launch_bounds__(64) void k_tgemm_eval(const int* __restrict__ rtask, int nrt,
-                                                   const int* __restrict__ rorder,
-                                                   const int* __restrict__ ctask,
-                                                   const int* __restrict__ corder,
-                                                   const int* __restrict__ brow,
-                                                   const int* __restrict__ bcol,
-                                                   const int* __restrict__ chunk_start,
-                                                   const int* __restrict__ chunk_n,
-                                                   const double* __restrict__ pts, int dim,
-                                                   KernelParams kp, PointScale ps,
-                                                   const Tv* __restrict__ x, Tv* __restrict__ partial) {
+__global__ __launch_bounds__(256) void k_tgemm_eval(const int* __restrict__ rtask, int nrt,
+                                                    const int* __restrict__ rorder,
+                                                    const int* __restrict__ ctask,
+                                                    const int* __restrict__ corder,
+                                                    const int* __restrict__ brow,
+                                                    const int* __restrict__ bcol,
+                                                    const int* __restrict__ chunk_start,
+                                                    const int* __restrict__ chunk_n,
+                                                    const double* __restrict__ pts, int dim,
+                                                    KernelParams kp, PointScale ps,
+                                                    const Tv* __restrict__ x, Tv* __restrict__ partial) {
   __shared__ Tv lds[64 * 64];
   tgemm_body<8, MODE_LIST>(rtask, nrt, rorder, ctask, corder, brow, bcol, 0, 64, x, partial,
                            static_cast<const Tv*>(nullptr), lds,
@@ -703,7 +667,7 @@ void launch_tgemm(H2& h, int tp, int T, const TileSet& ts, const void* tiles, in
     dispatch_prec(tp, [&](auto tv, auto te) {
       using Tv = decltype(tv);
       using Te = decltype(te);
-      hipLaunchKernelGGL((k_tgemm<TT, Te, Tv>), dim3(nb), dim3(64), 0, h.stream, ts.rtask, ts.nrt,
+      hipLaunchKernelGGL((k_tgemm<TT, Te, Tv>), dim3(nb), dim3(32 * TT), 0, h.stream, ts.rtask, ts.nrt,
                          ts.rorder, ts.ctask, ts.corder, static_cast<const Te*>(tiles), ts.brow, ts.bcol,
                          rr, static_cast<const Tv*>(x), static_cast<Tv*>(partial));
     });
@@ -719,11 +683,11 @@ void launch_tgemm_eval(H2& h, int p, const TileSet& ts, const void* x, void* par
   dispatch_kernel(h.kp.kind, h.kp.deriv, [&](auto kc, auto dc) {
     constexpr int KIND = decltype(kc)::value, DERIV = decltype(dc)::value;
     if (p == P64)
-      hipLaunchKernelGGL((k_tgemm_eval<double, KIND, DERIV>), dim3(nb), dim3(64), 0, h.stream, ts.rtask, ts.nrt,
+      hipLaunchKernelGGL((k_tgemm_eval<double, KIND, DERIV>), dim3(nb), dim3(256), 0, h.stream, ts.rtask, ts.nrt,
                          ts.rorder, ts.ctask, ts.corder, ts.brow, ts.bcol, sn.chunk_start, sn.chunk_n, h.pts,
                          h.dim, h.kp, ps, static_cast<const double*>(x), static_cast<double*>(partial));
     else
-      hipLaunchKernelGGL((k_tgemm_eval<float, KIND, DERIV>), dim3(nb), dim3(64), 0, h.stream, ts.rtask, ts.nrt,
+      hipLaunchKernelGGL((k_tgemm_eval<float, KIND, DERIV>), dim3(nb), dim3(256), 0, h.stream, ts.rtask, ts.nrt,
                          ts.rorder, ts.ctask, ts.corder, ts.brow, ts.bcol, sn.chunk_start, sn.chunk_n, h.pts,
                          h.dim, h.kp, ps, static_cast<const float*>(x), static_cast<float*>(partial));
   });
@@ -783,7 +747,7 @@ void launch_transfer_up16(H2& h, int p, int d, const void* xchild, void* xpar) {
     dispatch_prec(p, [&](auto tv, auto te) {
       using Tv = decltype(tv);
       using Te = decltype(te);
-      hipLaunchKernelGGL((k_transfer16<TT, MODE_UP, Te, Tv>), dim3(1 << d), dim3(64), 0, h.stream,
+      hipLaunchKernelGGL((k_transfer16<TT, MODE_UP, Te, Tv>), dim3(1 << d), dim3(32 * TT), 0, h.stream,
                          static_cast<const Te*>(h.prec[p].E), (1 << (d + 1)) - 1, h.r,
                          static_cast<const Tv*>(xchild), static_cast<Tv*>(xpar), static_cast<const Tv*>(nullptr));
     });
@@ -797,7 +761,7 @@ void launch_transfer_down16(H2& h, int p, int d, const void* ypar, void* ychild,
     dispatch_prec(p, [&](auto tv, auto te) {
       using Tv = decltype(tv);
       using Te = decltype(te);
-      hipLaunchKernelGGL((k_transfer16<TT, MODE_DOWN, Te, Tv>), dim3(2 << d), dim3(64), 0, h.stream,
+      hipLaunchKernelGGL((k_transfer16<TT, MODE_DOWN, Te, Tv>), dim3(2 << d), dim3(32 * TT), 0, h.stream,
                          static_cast<const Te*>(h.prec[p].E), (1 << (d + 1)) - 1, h.r,
                          static_cast<const Tv*>(ypar), static_cast<Tv*>(ychild), static_cast<const Tv*>(addend));
     });
