@@ -17,6 +17,11 @@ iterative refinement, both with the block smoother on the diagonal blocks.
 two solves are repeated with the paper's plain CG smoother and reported
 (--no-cg skips them).
 
+Also reported (not timed as the step): the small configuration's latency,
+the differentiation workload, the boundary-element problem at 10^6 panels,
+and the first 8 problems of the batched configuration (many right-hand
+sides of many uneven problems; `--batched` runs all 48).
+
 Inputs are generated on the host and copied to HBM before the timed region;
 every numerical step runs in libh2mg.so.  Prints one JSON line.
 
@@ -81,6 +86,9 @@ def parse():
     ap.add_argument("--batched", action="store_true",
                     help="run only the batched solve of many uneven problems with 16 RHS each")
     ap.add_argument("--batch-problems", type=int, default=48)
+    ap.add_argument("--batch-default-problems", type=int, default=8,
+                    help="problems of the batched configuration run by the default benchmark")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched run of the default benchmark")
     ap.add_argument("--batch-seed", type=int, default=3)
     ap.add_argument("--batch-shift", type=float, default=3.0)
     ap.add_argument("--batch-streams", type=int, default=4)
@@ -321,7 +329,7 @@ def stored_near_matvec(args, torch, g, w, time_matvecs):
     return out
 
 
-def batched(args, torch, synth, H2Matrix):
+def batched(args, torch, synth, H2Matrix, n_problems=None):
     """Many right-hand sides of many uneven problems: Gaussian-mixture point
     clouds in 3D (8 components, sigma 0.05), N log-uniform in [2^14, 2^18],
     Gaussian kernel l = 0.1, rank 27 (3^3 Chebyshev), leaf 64, eta 0.7, 16
@@ -335,6 +343,8 @@ def batched(args, torch, synth, H2Matrix):
     from paper_2501_17656_amd import solve_batch
     rng = np.random.default_rng(args.batch_seed)
     sizes = np.exp(rng.uniform(np.log(16384), np.log(262144), args.batch_problems)).astype(int)
+    if n_problems is not None:
+        sizes = sizes[:n_problems]       # the first problems of the same sequence
     shift = args.batch_shift
     budget = args.batch_budget_gb * 1e9
     t_build = t_batch = t_seq = t_single = 0.0
@@ -788,6 +798,8 @@ def main():
     c1 = None if args.no_c1 else c1_latency(args, torch, synth, H2Matrix)
     diff = None if args.no_diff else differentiation(args, torch, synth, H2Matrix)
     bem = None if args.no_bem else boundary_elements(args, torch, synth, H2Matrix)
+    # the first problems of the batched configuration (`--batched` runs all of them)
+    batch = None if args.no_batched else batched(args, torch, synth, H2Matrix, args.batch_default_problems)
     headline = part_a(args, torch, synth, H2Matrix) if args.headline else None
     if headline:
         log(f"part A: build {headline['build_s']} s, matvec {headline['matvec_ms']} ms, "
@@ -919,6 +931,7 @@ def main():
         "c1_small_config": c1,
         "differentiation": diff,
         "boundary_elements": bem,
+        "batched_first_problems": batch,
         "headline_shift_1e-3": headline,
     }
     if not args.no_cpu:
