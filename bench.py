@@ -89,6 +89,8 @@ def parse():
     ap.add_argument("--batch-default-problems", type=int, default=8,
                     help="problems of the batched configuration run by the default benchmark")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched run of the default benchmark")
+    ap.add_argument("--no-block-solve", action="store_true",
+                    help="skip the 16-right-hand-side solve of the timed workload")
     ap.add_argument("--batch-seed", type=int, default=3)
     ap.add_argument("--batch-shift", type=float, default=3.0)
     ap.add_argument("--batch-streams", type=int, default=4)
@@ -257,6 +259,31 @@ def block_product(args, torch, g, w, single_ms):
 def synth_block(w, nrhs):
     import synth
     return synth.normal_vector(w.n, w.x_seed, nrhs=nrhs)
+
+
+def many_rhs_solve(args, torch, g, w, single_s):
+    """16 right-hand sides of the timed workload solved at once
+    (h2mg_solve_multi: every cycle on all columns, tile products on the
+    matrix cores, the near field evaluated inside the products), with the
+    same precision and smoother as the timed mixed solve."""
+    B = torch.from_numpy(synth_block(w, 16)).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    try:
+        X, info = g.solve_multi(B, rtol=1e-8, precision=args.mixed, smoother=args.smoother,
+                                max_cycles=args.max_cycles, raise_on_error=False)
+    except Exception as ex:
+        return {"error": str(ex)}
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = {"rhs": 16, "time_to_1e-8_s": round(dt, 3), "cycles": info["cycles"], "status": info["status"],
+           "max_rel_residual": info["rel_residual"], "s_per_rhs": round(dt / 16, 3),
+           "speedup_vs_16_single_solves": round(16 * single_s / dt, 2),
+           "device_memory_gb": round(g.memory_bytes() / 1e9, 1)}
+    log(f"16 right-hand sides at once ({args.mixed}+fp64 refinement): {dt:.2f} s, {info['cycles']} cycles, "
+        f"{info['status']}, {16 * single_s / dt:.2f}x the throughput of single solves")
+    del X, B
+    return out
 
 
 def block_product_only(args, torch, synth, H2Matrix):
@@ -871,6 +898,7 @@ def main():
         times.append(time.perf_counter() - t0)
     g = rec["g"]
     res64, resm = rec["i64"], rec["im"]
+    block_solve = None if args.no_block_solve else many_rhs_solve(args, torch, g, w, rec["mixed_s"])
     cg_runs = None
     if not args.no_cg and args.smoother != "cg":
         cg_runs = {}
@@ -928,6 +956,7 @@ def main():
         "roofline": rec["rlm"] if mixed_ok and rec["rlm"] else rec["rl64"],
         "roofline_fp64_gemv": rec["rl64"],
         "paper_cg_smoother": cg_runs,
+        "sixteen_rhs_solve": block_solve,
         "c1_small_config": c1,
         "differentiation": diff,
         "boundary_elements": bem,
