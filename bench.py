@@ -579,6 +579,17 @@ def differentiation(args, torch, synth, H2Matrix):
     t2 = time.perf_counter()
     out.update({"build_and_setup_s": round(t1 - t0, 3), "solve_s": round(t2 - t1, 3),
                 "solve_cycles": info["cycles"], "solve_status": info["status"]})
+    # the same forward solve with FP32 cycles inside FP64 refinement
+    g.setup(("fp64", "fp32"))
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
+    xm, im = g.solve(b, rtol=1e-10, smoother="bj", precision="fp32", raise_on_error=False)
+    torch.cuda.synchronize()
+    out.update({"solve_fp32_refinement_s": round(time.perf_counter() - t5, 3),
+                "solve_fp32_refinement_steps": im["cycles"], "solve_fp32_refinement_status": im["status"],
+                "solutions_rel_diff": float((xm - x).norm() / x.norm())})
+    del xm
+    t2 = time.perf_counter()
     if info["converged"]:
         hl, hg = g.derivative("dl"), g.derivative("g")
         torch.cuda.synchronize()
@@ -593,8 +604,8 @@ def differentiation(args, torch, synth, H2Matrix):
         hl.close()
         hg.close()
     g.close()
-    log(f"differentiation {w.name}: solve {out['solve_s']} s ({out['solve_status']}), "
-        f"backward {out.get('backward_total_s')} s")
+    log(f"differentiation {w.name}: solve {out['solve_s']} s ({out['solve_status']}), FP32 refinement "
+        f"{out['solve_fp32_refinement_s']} s, backward {out.get('backward_total_s')} s")
     return out
 
 

@@ -23,7 +23,7 @@ class _QuadraticLoss(torch.autograd.Function):
                      cfg["leaf"], cfg["eta"], cfg["m"])
         bd = b.detach().contiguous()
         x, info = g.solve(bd, rtol=cfg["rtol"], smoother=cfg["smoother"], method=cfg["method"],
-                          max_cycles=cfg["max_cycles"])
+                          max_cycles=cfg["max_cycles"], precision=cfg["precision"])
         loss, _, _, _, _ = g.quadratic_gradient(None, None, bd, x)
         ctx.g, ctx.x, ctx.b, ctx.info = g, x, bd, info
         ctx.dtypes = (length_scale, shift)
@@ -54,11 +54,13 @@ class _QuadraticLoss(torch.autograd.Function):
 
 def quadratic_loss(points, length_scale, shift, b, kernel: str = "exp", leaf: int = 64,
                    eta: float = 0.7, m: int = 4, rtol: float = 1e-10, smoother: str = "bj",
-                   method: str = "v", max_cycles: int = 500):
+                   method: str = "v", max_cycles: int = 500, precision: str = "fp64"):
     """L = b^T A^{-1} b with A the H2 approximation of K(points; length_scale)
     + shift I, differentiable in points (n x dim), length_scale, shift (0-d
     tensors or floats) and b (device float64 tensors).  The solve stops at
-    relative residual rtol, which bounds the accuracy of L and its gradient."""
+    relative residual rtol, which bounds the accuracy of L and its gradient;
+    precision "fp32" / "bf16" runs its cycles in that precision inside FP64
+    refinement (same fixed point)."""
     cfg = dict(kernel=kernel, leaf=int(leaf), eta=float(eta), m=int(m), rtol=float(rtol),
-               smoother=smoother, method=method, max_cycles=int(max_cycles))
+               smoother=smoother, method=method, max_cycles=int(max_cycles), precision=precision)
     return _QuadraticLoss.apply(points, length_scale, shift, b, cfg)

@@ -139,6 +139,27 @@ def test_autograd_backward_and_finite_differences():
     assert float(s.grad) / 3.0 == pytest.approx(fd_s, rel=1e-5)
 
 
+def test_autograd_with_mixed_precision_solve():
+    """FP32 cycles inside FP64 refinement reach the same x (both solves stop
+    at 1e-12), so the loss and every gradient agree with the FP64 solve's."""
+    from paper_2501_17656_amd.autograd import quadratic_loss
+    st = setup_problem()
+    P, b = st["P"], st["b"]
+    out = []
+    for prec in ("fp64", "fp32"):
+        pts = _dev(P).requires_grad_(True)
+        ell = torch.tensor(ELL, dtype=torch.float64, device="cuda", requires_grad=True)
+        s = torch.tensor(SHIFT, dtype=torch.float64, device="cuda", requires_grad=True)
+        loss = quadratic_loss(pts, ell, s, _dev(b), kernel=KIND, leaf=LEAF, eta=ETA, m=M, rtol=1e-12,
+                              precision=prec)
+        loss.backward()
+        out.append((float(loss.detach()), float(ell.grad), float(s.grad), pts.grad.clone()))
+    (L0, l0, s0, p0), (L1, l1, s1, p1) = out
+    assert L1 == pytest.approx(L0, rel=1e-9)
+    assert l1 == pytest.approx(l0, rel=1e-8) and s1 == pytest.approx(s0, rel=1e-8)
+    assert torch.allclose(p1, p0, rtol=1e-7, atol=1e-7 * float(p0.abs().max()))
+
+
 def test_gradient_argument_errors():
     from paper_2501_17656_amd import H2Matrix, H2MGError
     st = setup_problem()
