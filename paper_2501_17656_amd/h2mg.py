@@ -150,14 +150,18 @@ class H2Matrix:
 
     def matvec_multi(self, X, out=None):
         """Y = A_H2 X for X of shape (n, nrhs), nrhs <= 16 (FP64; needs a rank
-        of 9 to 64 and store_near())."""
+        of 9 to 64; the close blocks are the stored tiles after store_near(),
+        else they are evaluated from the points inside the product)."""
         import torch
         if X.dim() != 2 or X.shape[0] != self.n:
             raise ValueError("X must have shape (n, nrhs)")
-        Y = torch.empty_like(X) if out is None else out
         nrhs = int(X.shape[1])
-        check(lib().h2mg_matvec_multi(self._h, nrhs, _dev_f64(X, name="X"), nrhs, _dev_f64(Y, name="Y"),
-                                      nrhs, _stream()))
+        xp = _dev_f64(X, name="X")
+        Y = torch.empty_like(X) if out is None else out
+        yp = _dev_f64(Y, name="out")
+        if tuple(Y.shape) != tuple(X.shape):
+            raise ValueError(f"out must have the shape of X {tuple(X.shape)} (got {tuple(Y.shape)})")
+        check(lib().h2mg_matvec_multi(self._h, nrhs, xp, nrhs, yp, nrhs, _stream()))
         return Y
 
     def store_near(self, enable: bool = True) -> None:
@@ -251,18 +255,24 @@ class H2Matrix:
                     max_cycles: int = 500, precision: str = "fp64", X0=None, raise_on_error: bool = True,
                     smoother: str = "cg", method: str = "v"):
         """Solve A_H2 X = B for B of shape (n, nrhs), nrhs <= 16, all columns
-        per cycle (needs a rank of 9 to 64 and store_near()).  Returns
-        (X, info); info["column_residuals"] holds each column's final
+        per cycle (needs a rank of 9 to 64; the close blocks are the stored
+        tiles after store_near(), else evaluated inside the products).
+        Returns (X, info); info["column_residuals"] holds each column's final
         relative residual."""
         import torch
         if B.dim() != 2 or B.shape[0] != self.n:
             raise ValueError("B must have shape (n, nrhs)")
         nrhs = int(B.shape[1])
+        bp = _dev_f64(B, name="B")
+        if X0 is not None:
+            _dev_f64(X0, name="X0")
+            if tuple(X0.shape) != tuple(B.shape):
+                raise ValueError(f"X0 must have the shape of B {tuple(B.shape)} (got {tuple(X0.shape)})")
         X = torch.zeros_like(B) if X0 is None else X0.clone()
         o = self._opts(rtol, n_fine, n_coarse, max_cycles, precision, X0 is not None, smoother, method)
         info = _lib.SolveInfo()
         cr = (ctypes.c_double * nrhs)()
-        st = lib().h2mg_solve_multi(self._h, nrhs, _dev_f64(B, name="B"), nrhs, _dev_f64(X, name="X"), nrhs,
+        st = lib().h2mg_solve_multi(self._h, nrhs, bp, nrhs, _dev_f64(X, name="X"), nrhs,
                                     ctypes.byref(o), ctypes.byref(info), cr, _stream())
         msg = _lib.last_error() if st != 0 else ""
         out = _info_dict(self, info, st, msg)

@@ -127,3 +127,24 @@ def test_block_product_of_the_scaled_form(stored):
         print(f"[gpu] scaled form, stored {stored}, column {k}: rel err {rel:.2e}")
         assert rel <= 1e-12
     g.close()
+
+
+def test_block_calls_reject_mismatched_out_and_x0():
+    """matvec_multi's out and solve_multi's X0 must have the shape of X / B:
+    a smaller buffer is refused before any launch (the library would write
+    n * nrhs elements into it)."""
+    from paper_2501_17656_amd import H2Matrix
+    n = 1200
+    P = synth.uniform_points(n, 2, 21)
+    g = H2Matrix(_dev(P), "exp", 0.1, 1e-2, 32, 0.7, 3)
+    X = _dev(synth.normal_vector(n, 22, nrhs=16))
+    for bad in (torch.empty((n, 1), dtype=torch.float64, device="cuda"),
+                torch.empty((n, 8), dtype=torch.float64, device="cuda"),
+                torch.empty((n * 16,), dtype=torch.float64, device="cuda")):
+        with pytest.raises(ValueError):
+            g.matvec_multi(X, out=bad)
+        with pytest.raises(ValueError):
+            g.solve_multi(X, X0=bad, max_cycles=1)
+    with pytest.raises(TypeError):
+        g.matvec_multi(X, out=torch.empty((n, 16), dtype=torch.float32, device="cuda"))
+    g.close()

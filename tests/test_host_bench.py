@@ -26,3 +26,83 @@ def test_batched_sizes_are_log_uniform_in_range():
     assert int(sizes.sum()) == 4199708          # the batch measured in the design notes
     # log-uniform: about half of the problems below the geometric mean 65536
     assert 16 <= int((sizes < 65536).sum()) <= 32
+
+
+def _bench():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_default_run_asks_for_no_extra_part():
+    """The driver's command (--gpus 1 --steps 20 --warmup 5) requests none of
+    the opt-in parts, and the extra runners then do nothing at all (they get
+    None for every handle, so any work they started would fail)."""
+    bench = _bench()
+    args = bench.parse(["--gpus", "1", "--steps", "20", "--warmup", "5"])
+    assert bench.extras_requested(args) == []
+    assert bench.run_extras(args, [], None, None, None, None, None, None, 0.0) == {}
+    assert bench.run_extras_alone(args, [], None, None, None) == {}
+    # every flag maps to its part
+    every = bench.parse(["--c1", "--diff", "--bem", "--batched-first", "3", "--part-a",
+                         "--cg-smoother", "--sixteen-rhs"])
+    assert bench.extras_requested(every) == list(bench.EXTRAS)
+
+
+def test_extra_parts_are_called_only_from_the_extra_runners():
+    """Static check of bench.py: the long opt-in parts are called from the
+    runners of the extras (or from their own exclusive modes), never from the
+    default path in main()."""
+    import ast
+    tree = ast.parse(open(os.path.join(ROOT, "bench.py")).read())
+    long_parts = {"c1_latency", "differentiation", "boundary_elements", "batched", "part_a",
+                  "many_rhs_solve"}
+    allowed = {"run_extras", "run_extras_alone"}
+    callers = {}
+    for fn in tree.body:
+        if not isinstance(fn, ast.FunctionDef):
+            continue
+        for node in ast.walk(fn):
+            if isinstance(node, ast.Call) and isinstance(node.func, ast.Name) and node.func.id in long_parts:
+                callers.setdefault(node.func.id, set()).add(fn.name)
+    for part, fns in callers.items():
+        extra = fns - allowed
+        # main() may call batched() only in its exclusive --batched mode
+        if part == "batched":
+            extra -= {"main"}
+        assert not extra, (part, extra)
+    main = next(f for f in tree.body if isinstance(f, ast.FunctionDef) and f.name == "main")
+    batched_calls = [n for n in ast.walk(main) if isinstance(n, ast.Call)
+                     and isinstance(n.func, ast.Name) and n.func.id == "batched"]
+    assert len(batched_calls) == 1            # the --batched mode, which returns right after
+
+
+def test_timed_solves_respect_the_budget():
+    """Warmup and timed steps stop early when the next solve would pass the
+    deadline, after at least one of each; the counts reported are the ones run."""
+    bench = _bench()
+
+    class FakeTorch:
+        class cuda:
+            @staticmethod
+            def synchronize():
+                pass
+
+    class FakeG:
+        calls = 0
+
+        def solve(self, b, **kw):
+            FakeG.calls += 1
+            return "x", {"cycles": 3, "status": "OK", "rel_residual": 1e-9, "converged": True}
+
+    import time as _t
+    args = bench.parse(["--steps", "20", "--warmup", "5"])
+    # deadline already passed: one warmup and one timed solve still run
+    warm, times, infos, x = bench.timed_solves(args, FakeTorch, FakeG(), None, _t.perf_counter() - 1)
+    assert warm == 1 and len(times) == 1 and FakeG.calls == 2
+    # generous deadline: everything requested runs
+    FakeG.calls = 0
+    warm, times, infos, x = bench.timed_solves(args, FakeTorch, FakeG(), None, _t.perf_counter() + 3600)
+    assert warm == 5 and len(times) == 20 and FakeG.calls == 25
