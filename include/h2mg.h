@@ -372,6 +372,18 @@ h2mg_status h2mg_level_size(h2mg_h2_t h, int32_t level, int64_t* size);
  * level >= 2: coefficient order).  Requires h2mg_setup_mg for level >= 2. */
 h2mg_status h2mg_level_apply(h2mg_h2_t h, int32_t level, const double* x_dev,
                              double* y_dev, hipStream_t stream);
+/* y = A_k x with the level's operators in the given h2mg_precision, the
+ * product the low-precision V-cycles apply (Section 3.3, eq. a2_str, for
+ * level >= 2; Section 3.1 for level 1): FP32 or BF16 bases, transfers,
+ * couplings and projected blocks, the level-1 near field evaluated in FP32,
+ * FP32 vectors and FP32 accumulation.  x and y are FP64 device vectors of
+ * N_k elements (user order on level 1, coefficient order above); x is
+ * rounded to FP32 on entry and y widened from FP32 on exit.  The handle
+ * allocates two FP32 vectors of N_k for the call.  Errors: INVALID_ARG for a
+ * bad level or precision, STATE when h2mg_setup_mg has not prepared that
+ * precision (level >= 2, or any level for a non-FP64 precision); OOM; HIP. */
+h2mg_status h2mg_level_apply_precision(h2mg_h2_t h, int32_t level, int32_t precision,
+                                       const double* x_dev, double* y_dev, hipStream_t stream);
 /* Restriction r_{k+1} = U_k^T r_k and prolongation e_k = V_k^T e_{k+1} = U_k e_{k+1}
  * between levels k and k+1 (Algorithm 1).  Level 1 vectors in user order. */
 h2mg_status h2mg_restrict(h2mg_h2_t h, int32_t level, const double* r_dev,

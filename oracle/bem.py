@@ -101,4 +101,6 @@ def harmonic_rhs(points: np.ndarray, coeffs) -> np.ndarray:
 
 
 def point_source_rhs(points: np.ndarray, x0) -> np.ndarray:
+    """f_j = 1 / (4 pi ||y_j - x_0||): the potential of a unit point charge at
+    x_0 off the surface (Section 4.3's right-hand side)."""
     return 1.0 / (4.0 * np.pi * np.linalg.norm(points - np.asarray(x0, dtype=np.float64), axis=1))

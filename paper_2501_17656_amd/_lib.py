@@ -61,6 +61,7 @@ SIGNATURES = {
     "h2mg_level_count": (c_int32, [c_void_p, P_int32]),
     "h2mg_level_size": (c_int32, [c_void_p, c_int32, P_int64]),
     "h2mg_level_apply": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    "h2mg_level_apply_precision": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
     "h2mg_restrict": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
     "h2mg_prolong": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
     "h2mg_vcycle": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(SolveOpts), c_void_p]),

@@ -267,6 +267,42 @@ h2mg_status h2mg_level_apply(h2mg_h2_t hh, int32_t level, const double* x, doubl
   });
 }
 
+h2mg_status h2mg_level_apply_precision(h2mg_h2_t hh, int32_t level, int32_t precision,
+                                       const double* x, double* y, hipStream_t stream) {
+  return guarded([&] {
+    if (!hh || !x || !y) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    if (precision < H2MG_FP64 || precision > H2MG_BF16_IR)
+      return fail(H2MG_ERR_INVALID_ARG, "unknown precision %d", precision);
+    if (precision == H2MG_FP64) return h2mg_level_apply(hh, level, x, y, stream);
+    H2& h = *hh->h;
+    h.stream = stream;
+    const int p = precision == H2MG_FP32_IR ? P32 : P16;
+    if (level < 1 || level > h.levels) return fail(H2MG_ERR_INVALID_ARG, "level out of range");
+    if (!h.mg_built || !h.prec[p].ready)
+      return fail(H2MG_ERR_STATE, "call h2mg_setup_mg with the %s precision bit first",
+                  p == P32 ? "FP32" : "BF16");
+    const int64_t nk = h.level_size(level);
+    float* x32 = h.arena.make<float>(size_t(nk));
+    float* y32 = h.arena.make<float>(size_t(nk));
+    if (level == 1) {
+      launch_gather(h, x, h.vtree);
+      launch_cast(h, P32, x32, P64, h.vtree, nk);
+      apply_fine(h, p, x32, y32, 1.0, nullptr, 0.0);
+      launch_cast(h, P64, h.vtree2, P32, y32, nk);
+      launch_scatter(h, h.vtree2, y);
+    } else {
+      launch_cast(h, P32, x32, P64, x, nk);
+      apply_coarse(h, p, level, x32, y32);
+      launch_cast(h, P64, y, P32, y32, nk);
+    }
+    const h2mg_status st = check_stream_err(stream);
+    (void)hipStreamSynchronize(stream);
+    h.arena.release(x32);
+    h.arena.release(y32);
+    return st;
+  });
+}
+
 h2mg_status h2mg_restrict(h2mg_h2_t hh, int32_t level, const double* r, double* r_next,
                           hipStream_t stream) {
   return guarded([&] {

@@ -186,11 +186,18 @@ class H2Matrix:
         check(lib().h2mg_level_size(self._h, level, ctypes.byref(v)))
         return v.value
 
-    def level_apply(self, level: int, x, out=None):
+    def level_apply(self, level: int, x, out=None, precision: str = "fp64"):
+        """y = A_k x on level k (FP64 vectors; precision "fp32" / "bf16" applies
+        the low-precision operators of the mixed cycles, prepared by setup)."""
         import torch
         y = torch.empty_like(x) if out is None else out
         nk = self.level_size(level)
-        check(lib().h2mg_level_apply(self._h, level, _dev_f64(x, nk, "x"), _dev_f64(y, nk, "y"), _stream()))
+        xp, yp = _dev_f64(x, nk, "x"), _dev_f64(y, nk, "y")
+        if precision == "fp64":
+            check(lib().h2mg_level_apply(self._h, level, xp, yp, _stream()))
+        else:
+            check(lib().h2mg_level_apply_precision(self._h, level, PRECISIONS[precision], xp, yp,
+                                                   _stream()))
         return y
 
     def restrict(self, level: int, r):

@@ -6,10 +6,10 @@ block rows of one leaf) costs O(n_leaf * n), so rows of a few leaves can be
 checked at any size.  Checked here, in the launch configuration the
 benchmark times:
   * matvec rows, near field evaluated and near field stored (1e-12 relative);
-  * after a mixed-precision solve of the shift-1 variant, the residual rows
-    b - A_H2 x recomputed by the oracle: small (the solve's 1e-8 target, with
-    a margin for sampling a few rows) and equal to the library's own residual
-    rows up to rounding.
+  * after the FP64 solve and the mixed-precision solve of the shift-1
+    variant, the residual rows b - A_H2 x recomputed by the oracle: small (the
+    solve's 1e-8 target, with a margin for sampling a few rows) and equal to
+    the library's own residual rows up to rounding.
 """
 import numpy as np
 import pytest
@@ -62,24 +62,34 @@ def test_matvec_rows_at_full_size():
 
 
 def test_solution_residual_rows_at_full_size():
+    """FP64 solve and FP32-refinement solve of the shift-1 variant (the timed
+    workload) on one build; for both, the oracle's residual rows."""
     from paper_2501_17656_amd import H2Matrix
     w = synth.workload("matern3d_1m_spd")
     P, b = w.make_points(), w.make_rhs()
     print(f"[gpu] build {w.name} n={w.n}", flush=True)
     g = H2Matrix(_dev(P), w.kernel, w.length_scale, w.shift, w.leaf, w.eta, w.cheb_m)
+    g.setup(("fp64", "fp32"))
     bd = _dev(b)
-    x, info = g.solve(bd, rtol=1e-8, precision="fp32", smoother="bj")
-    print(f"[gpu] mixed solve: {info['cycles']} steps, rel res {info['rel_residual']:.2e}", flush=True)
-    assert info["converged"] and info["rel_residual"] < 1e-8
-    r_gpu = _host(bd - g.matvec(x))
-    xh = _host(x)
+    sols = {}
+    for prec in ("fp64", "fp32"):
+        x, info = g.solve(bd, rtol=1e-8, precision=prec, smoother="bj")
+        print(f"[gpu] {prec} solve: {info['cycles']} cycles/steps, rel res {info['rel_residual']:.2e}",
+              flush=True)
+        assert info["converged"] and info["rel_residual"] < 1e-8
+        sols[prec] = (_host(x), _host(bd - g.matvec(x)))
     g.close()
     o = OracleH2(P, w.kernel, w.shift, w.leaf, w.eta, w.cheb_m, w.length_scale)
     for leaf in LEAVES:
         rows = _rows(o, leaf)
-        r_o = b[rows] - o.matvec_rows(xh, leaf)
         nb = np.linalg.norm(b[rows])
-        print(f"[gpu] leaf {leaf}: oracle residual rows {np.linalg.norm(r_o) / nb:.2e}, "
-              f"library vs oracle {np.linalg.norm(r_gpu[rows] - r_o) / nb:.2e}")
-        assert np.linalg.norm(r_o) <= 1e-6 * nb
-        assert np.linalg.norm(r_gpu[rows] - r_o) <= 1e-10 * nb
+        for prec, (xh, r_gpu) in sols.items():
+            r_o = b[rows] - o.matvec_rows(xh, leaf)
+            print(f"[gpu] leaf {leaf} {prec}: oracle residual rows {np.linalg.norm(r_o) / nb:.2e}, "
+                  f"library vs oracle {np.linalg.norm(r_gpu[rows] - r_o) / nb:.2e}")
+            assert np.linalg.norm(r_o) <= 1e-6 * nb
+            assert np.linalg.norm(r_gpu[rows] - r_o) <= 1e-10 * nb
+    # the two solutions agree to the conditioning of a 1e-8 residual
+    dx = np.linalg.norm(sols["fp32"][0] - sols["fp64"][0]) / np.linalg.norm(sols["fp64"][0])
+    print(f"[gpu] fp32-refinement vs fp64 solution: {dx:.2e}")
+    assert dx <= 1e-6

@@ -191,3 +191,36 @@ def test_scaled_h2_is_exact_for_a_polynomial_kernel_and_matches_dense():
     S = (s2[:, None] * A) / s2[None, :]
     z = synth.normal_vector(len(T), 8)
     np.testing.assert_allclose(hb.matvec(z), S @ z, rtol=1e-12, atol=1e-14)
+
+
+def _sphere_mean(fun, centre, radius, nt=48, nphi=96):
+    """Mean of fun over the sphere |y - centre| = radius: Gauss-Legendre in
+    cos(theta), the trapezoidal rule in phi (exponentially accurate for
+    functions analytic on the sphere)."""
+    t, wt = np.polynomial.legendre.leggauss(nt)
+    phi = 2 * np.pi * np.arange(nphi) / nphi
+    st = np.sqrt(1 - t * t)
+    pts = np.stack([np.outer(st, np.cos(phi)), np.outer(st, np.sin(phi)),
+                    np.outer(t, np.ones(nphi))], axis=-1).reshape(-1, 3)
+    w = np.repeat(wt, nphi) / (2.0 * nphi)           # weights sum to 1
+    return float(w @ fun(np.asarray(centre) + radius * pts))
+
+
+def test_point_source_rhs_mean_value_property():
+    """The point-source potential is harmonic away from x_0: its mean over a
+    sphere that does not enclose x_0 is its value at the centre,
+    1 / (4 pi |c - x_0|); over a sphere that encloses x_0 it is
+    1 / (4 pi R) (Newton's shell theorem).  A dropped 4 pi, a squared
+    distance or a sign error fails one of the two."""
+    x0 = np.array([0.3, -0.2, 1.5])
+    c = np.array([0.1, 0.4, -0.3])
+    f = lambda y: point_source_rhs(y, x0)               # noqa: E731
+    d = float(np.linalg.norm(c - x0))
+    for R in (0.3 * d, 0.6 * d):
+        assert abs(_sphere_mean(f, c, R) - 1.0 / (4 * np.pi * d)) <= 1e-12 / d
+    for R in (1.7 * d, 3.0 * d):
+        assert abs(_sphere_mean(f, c, R) - 1.0 / (4 * np.pi * R)) <= 1e-12 / R
+    # positive and decreasing with the distance
+    y = x0 + np.array([[1.0, 0, 0], [2.0, 0, 0], [0, 0, 4.0]])
+    v = point_source_rhs(y, x0)
+    assert np.all(v > 0) and np.allclose(v, 1 / (4 * np.pi * np.array([1.0, 2.0, 4.0])), rtol=1e-15)
