@@ -102,6 +102,8 @@ def parse(argv=None):
                     help="also solve the timed workload with the paper's plain CG smoother")
     ap.add_argument("--sixteen-rhs", action="store_true",
                     help="also solve 16 right-hand sides of the timed workload at once")
+    ap.add_argument("--bem-one-point", action="store_true",
+                    help="close boundary-element entries by the one-point rule (default: seven points)")
     ap.add_argument("--bem-grid", type=int, nargs=2, default=[1000, 500],
                     help="torus parameter grid (panels = 2 * a * b)")
     ap.add_argument("--json-out", default="")
@@ -371,10 +373,10 @@ def lanczos_probe(args, torch, synth, H2Matrix):
 
 def block_product(args, torch, g, w, single_ms):
     """Y = A_H2 X for a block of 16 vectors (matrix-core tile products; each
-    stored off-diagonal tile streamed twice, once per pass; tile runs tuned
-    on the first call): time per block product, the equivalent time per
-    vector, and the matrix-core rate of the near-field tile passes
-    (2 * 64 * 64 * 16 flops per tile and pass)."""
+    stored tile read once, its row and transposed products from the same
+    staged copy; tile runs tuned on the first call): time per block product,
+    the equivalent time per vector, the algorithmic GB/s of the near-field
+    tiles (each stored tile counted once) and their matrix-core rate."""
     X = torch.from_numpy(synth_block(w, 16)).cuda()
     g.set_autotune(True)                                      # tile runs chosen on the first call
     try:
@@ -392,15 +394,18 @@ def block_product(args, torch, g, w, single_ms):
     ms = e0.elapsed_time(e1) / args.matvec_reps
     st = g.kernel_stats("near_gemm16_fp64")
     near_ms = st["ms"] / max(st["launches"], 1)
-    tile_bytes = st["work"] / max(st["launches"], 1)          # both passes
-    flops = tile_bytes / 8.0 * 2.0 * 16.0                     # 2 flops per stored word and column
+    tile_bytes = st["work"] / max(st["launches"], 1)          # each stored tile once (algorithmic)
+    # every stored word serves the row product and, off the diagonal, the
+    # transposed one: at most 2 x 2 flops per word and column
+    flops = tile_bytes / 8.0 * 4.0 * 16.0
     g.set_timing(False)
     tuning = g.block_tuning()
     return {"ms": round(ms, 3), "ms_per_vector": round(ms / 16, 3),
             "speedup_vs_16_single_products": round(16 * single_ms / ms, 2),
             "tile_runs": {k: v["run"] for k, v in tuning.items()},
-            "near_tile_passes_ms": round(near_ms, 3),
-            "near_tile_passes_gbs": round(tile_bytes / (near_ms * 1e-3) / 1e9, 1),
+            "near_tile_products_ms": round(near_ms, 3),
+            "near_tiles_algorithmic_gbs": round(tile_bytes / (near_ms * 1e-3) / 1e9, 1),
+            "near_tiles_frac_of_hbm_peak": round(tile_bytes / (near_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3),
             "near_mfma_tflops": round(flops / (near_ms * 1e-3) / 1e12, 2),
             "near_mfma_frac_of_fp64_peak": round(flops / (near_ms * 1e-3) / 1e12 / 78.6, 3)}
 
@@ -524,12 +529,13 @@ def batched(args, torch, synth, H2Matrix, n_problems=None):
         sizes = sizes[:n_problems]       # the first problems of the same sequence
     shift = args.batch_shift
     budget = args.batch_budget_gb * 1e9
-    t_build = t_batch = t_seq = t_single = 0.0
+    t_build = t_batch = t_seq = t_single = t_onelaunch = 0.0
+    group_equal = []
     per = []
     group = []
 
     def solve_group():
-        nonlocal t_batch, t_seq, t_single
+        nonlocal t_batch, t_seq, t_single, t_onelaunch
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         xs, infos = solve_batch([(g, B) for g, B, _ in group], rtol=1e-8, precision="fp32",
@@ -539,6 +545,18 @@ def batched(args, torch, synth, H2Matrix, n_problems=None):
         t_batch += dt
         log(f"batched: group of {len(group)} (N {sum(g.n for g, _, _ in group)}) solved together in "
             f"{dt:.2f} s, cycles {[i['cycles'] for i in infos]}")
+        # the same problems with every tile-product step in one launch over all of them
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xg, infg = solve_batch([(g, B) for g, B, _ in group], rtol=1e-8, precision="fp32",
+                               smoother="bj", raise_on_error=False, mode="group")
+        torch.cuda.synchronize()
+        dtg = time.perf_counter() - t0
+        t_onelaunch += dtg
+        same = all(bool(torch.equal(a, b)) for a, b in zip(xs, xg))
+        group_equal.append(same)
+        log(f"batched: the same group with one launch per tile-product step: {dtg:.2f} s, "
+            f"bitwise equal to the stream solves: {same}")
         for (g, B, i), info in zip(group, infos):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -609,6 +627,9 @@ def batched(args, torch, synth, H2Matrix, n_problems=None):
         "build_and_setup_s": round(t_build, 2),
         "batched_solve_s": round(t_batch, 3),
         "rhs_per_s_batched": round(nrhs_total / t_batch, 2),
+        "one_launch_per_step_solve_s": round(t_onelaunch, 3),
+        "rhs_per_s_one_launch_per_step": round(nrhs_total / t_onelaunch, 2),
+        "one_launch_per_step_bitwise_equal": all(group_equal),
         "sequential_block_solves_s": round(t_seq, 3),
         "single_rhs_solves_s_extrapolated": round(t_single, 3),
         "speedup_batched_vs_single_rhs": round(t_single / t_batch, 2),
@@ -819,7 +840,7 @@ def boundary_elements(args, torch, synth, H2Matrix):
     hierarchy, FP64 and FP32-refinement solves with the paper's CG smoother
     for Dirichlet data given by a random harmonic polynomial of degree 2,
     and the matvec."""
-    from paper_2501_17656_amd import bem_density, bem_harmonic_rhs, bem_panels
+    from paper_2501_17656_amd import bem_density, bem_harmonic_rhs, bem_panels, bem_quadrature7
     nmaj, nmin = args.bem_grid
     V, T = synth.bumpy_torus_mesh(nmaj, nmin)
     Vd = torch.from_numpy(V).cuda()
@@ -828,6 +849,11 @@ def boundary_elements(args, torch, synth, H2Matrix):
     t0 = time.perf_counter()
     y, sc, dg = bem_panels(Vd, Td)
     g = H2Matrix(y, "laplace", 1.0, 0.0, 128, 0.7, 4, scale=sc, diag=dg)
+    if not args.bem_one_point:
+        # the close entries by the seven-point rule on both triangles (stored tiles)
+        qy, qu = bem_quadrature7(Vd, Td)
+        g.set_near_quadrature(qy, qu)
+        del qy, qu
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     g.setup(("fp64", "fp32"))
@@ -836,7 +862,8 @@ def boundary_elements(args, torch, synth, H2Matrix):
     coeffs = synth.harmonic_coefficients(7)
     f = bem_harmonic_rhs(y, sc, coeffs)
     out = {"workload": f"bumpy torus (R 1, r 0.35, 40 bumps of 0.05), {len(T)} panels, Laplace single "
-                       f"layer 1/(4 pi r), closed-form self term, symmetric scaled form, leaf 128, "
+                       f"layer 1/(4 pi r), closed-form self term, symmetric scaled form, close entries by "
+                       f"{'the one-point rule' if args.bem_one_point else 'the seven-point rule on both triangles'}, leaf 128, "
                        f"eta 0.7, rank 64, right-hand side a random harmonic polynomial of degree 2 (seed 7), "
                        f"rtol 1e-8, CG smoother (the block "
                        f"smoother's FP32 PCG breaks down at 10^6 panels)",
@@ -1096,6 +1123,13 @@ def main(argv=None):
     g.set_graphs(not args.no_graphs)
     log(f"build {t1 - t0:.2f} s, hierarchy {t2 - t1:.2f} s, {g.levels} levels, "
         f"{g.memory_bytes() / 1e9:.1f} GB")
+    # block-GEMV launch of each level's product (grid sizes identify the
+    # launches in a kernel trace)
+    gemv_launches = {}
+    for k in range(1, g.levels + 1):
+        info = g.gemv_launch_info(k)
+        info["depth"] = None if k == 1 else (g.level_size(k) // w.rank).bit_length() - 1
+        gemv_launches[k] = info
     x64, i64 = g.solve(b_d, rtol=1e-8, max_cycles=args.max_cycles, precision="fp64",
                        smoother=args.smoother, raise_on_error=False)
     torch.cuda.synchronize()
@@ -1177,6 +1211,7 @@ def main(argv=None):
         "matvec": mv,
         "roofline": rlm if mixed_ok and rlm else rl64,
         "roofline_fp64_gemv": rl64,
+        "gemv_launches": gemv_launches,
     }
     out.update(extra)
     if not args.no_cpu:

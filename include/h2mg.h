@@ -231,6 +231,18 @@ h2mg_status h2mg_build_scaled(const double* points_dev, int64_t n, int32_t dim,
 h2mg_status h2mg_bem_panels(const double* vertices_dev, int64_t nv, const int64_t* triangles_dev,
                             int64_t nt, double* centroids_dev, double* scale_dev,
                             double* diag_dev, hipStream_t stream);
+/* The seven-point near field of the boundary-element benchmark: Radon's
+ * rule (exact for polynomials of degree <= 5) on every triangle.  Writes
+ * qy_dev (nt x 7 x 3 doubles: the rule's points) and qu_dev (nt x 7:
+ * the rule's weights times sqrt(area_i)).  Passed to
+ * h2mg_set_near_quadrature, the close entries of the symmetric form become
+ * the rule applied on both triangles to the double integral of
+ * 1 / (4 pi |x - y|), divided by s_i s_j -- the reading of a 7-point
+ * near-field rule that keeps the operator symmetric (Section 4.3 gives only
+ * the one-point collocation entry).  Same arguments and errors as
+ * h2mg_bem_panels. */
+h2mg_status h2mg_bem_quadrature7(const double* vertices_dev, int64_t nv, const int64_t* triangles_dev,
+                                 int64_t nt, double* qy_dev, double* qu_dev, hipStream_t stream);
 /* rhs_dev[i] = s_i / (4 pi |y_i - x0|): W^(1/2) f for the point source x0
  * (3 host doubles) of Section 4.3; centroids and scale from h2mg_bem_panels. */
 h2mg_status h2mg_bem_point_source_rhs(const double* centroids_dev, const double* scale_dev,
@@ -252,6 +264,22 @@ h2mg_status h2mg_bem_density(const double* y_dev, const double* scale_dev, int64
 /* y = A_H2 x (Section 3.1 matvec: upsweep x_i = V_i x_{i-1}, couplings,
  * downsweep y_{i-1} = D_i x_{i-1} + U_i y_i, near field y = D x + U_1 y_1).
  * x_dev, y_dev: device, length n, user order; they must not overlap. */
+/* Close entries by quadrature (Section 3.1's close blocks D, evaluated with
+ * a quadrature rule instead of point values): point i carries nq
+ * sub-points qy_dev[i] (nq x dim doubles, row-major) with weights
+ * qu_dev[i] (nq doubles), both device, user order, copied by the call; the
+ * entry between distinct points i, j of a close leaf pair becomes
+ * sum_p sum_q qu[i][p] qu[j][q] k(|qy[i][p] - qy[j][q]|), the diagonal
+ * keeps d (or the shift), and far blocks keep the point values.  Must be
+ * called right after the build (before any product, store or setup); it
+ * stores the near field (as h2mg_store_near, which cannot release it
+ * afterwards), and every product reads the stored tiles -- FP64, or an FP32
+ * copy that h2mg_setup_mg makes for the low precisions.  Errors:
+ * INVALID_ARG (null, nq outside 1..64), STATE (called after a product or
+ * setup, or twice), OOM, HIP. */
+h2mg_status h2mg_set_near_quadrature(h2mg_h2_t h, const double* qy_dev, const double* qu_dev,
+                                     int32_t nq, hipStream_t stream);
+
 h2mg_status h2mg_matvec(h2mg_h2_t h, const double* x_dev, double* y_dev,
                         hipStream_t stream);
 
@@ -353,6 +381,24 @@ h2mg_status h2mg_solve_batch(int32_t nprob, const h2mg_h2_t* hs, const int32_t* 
                              const int32_t* ldx, const h2mg_solve_opts* opts,
                              h2mg_solve_info* infos, h2mg_status* statuses, int32_t nstreams,
                              hipStream_t stream);
+
+/* The problems of h2mg_solve_batch solved in one sequence of launches on
+ * `stream` (Algorithm 1 for every problem, spec batching form): the
+ * problems advance cycle by cycle together, and each tile product of a
+ * cycle step -- the couplings, the restricted operators of each level, the
+ * near-field tiles -- is one kernel launch over the task lists of every
+ * active problem (up to 16 per launch; problems whose level does not exist
+ * at that step are left out, and a problem's coarsest level is solved
+ * directly when the others go deeper).  Vector steps stay per problem.  A
+ * problem's arithmetic is the same, in the same order, as in its own
+ * h2mg_solve_multi, so results are bitwise equal.  With h2mg_set_graphs on
+ * every handle, one graph holds the cycle of all active problems (recorded
+ * again when a problem finishes).  Arguments, ownership and errors as
+ * h2mg_solve_batch. */
+h2mg_status h2mg_solve_group(int32_t nprob, const h2mg_h2_t* hs, const int32_t* nrhs,
+                             const double* const* b_dev, const int32_t* ldb, double* const* x_dev,
+                             const int32_t* ldx, const h2mg_solve_opts* opts,
+                             h2mg_solve_info* infos, h2mg_status* statuses, hipStream_t stream);
 
 /* Build the H2-MG hierarchy (Section 3.3): restricted operators
  * A_k = U_{k-1}^T A_{k-1} V_{k-1}^T for every level, i.e. the projected close
@@ -464,6 +510,14 @@ h2mg_status h2mg_block_tuning(h2mg_h2_t h, int32_t which, int32_t* run, double* 
 h2mg_status h2mg_set_timing(h2mg_h2_t h, int32_t enabled);
 h2mg_status h2mg_kernel_stats(h2mg_h2_t h, int32_t kind, int64_t* launches, double* total_ms,
                               double* total_work);
+
+/* The block-GEMV launch of one product, for reading profiles: level 1 is
+ * the fine matvec's couplings of every depth, level k >= 2 the restricted
+ * operator of depth L - k + 2 (Section 3.3, eq. a2_str).  tasks: waves of
+ * the launch (one 64-lane wave per task, four per 256-thread block);
+ * blocks: stored r x r blocks it streams.  Level >= 2 needs
+ * h2mg_setup_mg.  Errors: INVALID_ARG for a bad level, STATE. */
+h2mg_status h2mg_gemv_launch_info(h2mg_h2_t h, int32_t level, int64_t* tasks, int64_t* blocks);
 
 /* Device memory held by the handle, in bytes. */
 h2mg_status h2mg_memory_bytes(h2mg_h2_t h, int64_t* bytes);

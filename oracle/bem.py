@@ -100,6 +100,50 @@ def harmonic_rhs(points: np.ndarray, coeffs) -> np.ndarray:
     return harmonic_basis(points) @ np.asarray(coeffs, dtype=np.float64)
 
 
+def radon7():
+    """Radon's seven-point rule on a triangle (exact for polynomials of degree
+    <= 5): barycentric coordinates (7, 3) and weights (7,) summing to 1.  The
+    centroid with weight 9/40, and the two orbits (a, a, 1 - 2a) with
+    a = (6 -+ sqrt 15) / 21 and weights (155 -+ sqrt 15) / 1200."""
+    r15 = np.sqrt(15.0)
+    a1, a2 = (6.0 - r15) / 21.0, (6.0 + r15) / 21.0
+    w1, w2 = (155.0 - r15) / 1200.0, (155.0 + r15) / 1200.0
+    bary = [[1 / 3, 1 / 3, 1 / 3]]
+    wts = [9.0 / 40.0]
+    for a, w in ((a1, w1), (a2, w2)):
+        for k in range(3):
+            b = [a, a, a]
+            b[k] = 1.0 - 2.0 * a
+            bary.append(b)
+            wts.append(w)
+    return np.array(bary), np.array(wts)
+
+
+def quadrature7(V: np.ndarray, T: np.ndarray):
+    """Radon's seven-point rule on every triangle: points (nt, 7, 3) and
+    weights (nt, 7), the rule's weights times the triangle's area."""
+    bary, wts = radon7()
+    a, b, c = V[T[:, 0]], V[T[:, 1]], V[T[:, 2]]
+    pts = (bary[None, :, 0, None] * a[:, None, :] + bary[None, :, 1, None] * b[:, None, :]
+           + bary[None, :, 2, None] * c[:, None, :])
+    area = 0.5 * np.linalg.norm(np.cross(b - a, c - a), axis=1)
+    return pts, area[:, None] * wts[None, :]
+
+
+def near_quadrature7(V: np.ndarray, T: np.ndarray):
+    """Per-panel quadrature of the symmetric form's close entries (config 5's
+    near field, in the reading that keeps the operator symmetric): the entry
+    between distinct panels i and j is the seven-point rule applied on both
+    triangles to the double integral of 1 / (4 pi |x - y|), divided by
+    s_i s_j = sqrt(w_i w_j):
+        S_ij = sum_p sum_q u_ip u_jq / (4 pi |y_ip - y_jq|),  u_ip = omega_ip / s_i.
+    Returns (points (nt, 7, 3), u (nt, 7)); with the centroid as the only
+    point and u_i = s_i this is the one-point entry s_i s_j / (4 pi r_ij)."""
+    pts, om = quadrature7(V, T)
+    s = np.sqrt(om.sum(axis=1))
+    return pts, om / s[:, None]
+
+
 def point_source_rhs(points: np.ndarray, x0) -> np.ndarray:
     """f_j = 1 / (4 pi ||y_j - x_0||): the potential of a unit point charge at
     x_0 off the surface (Section 4.3's right-hand side)."""

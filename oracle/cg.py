@@ -35,7 +35,7 @@ def cg(apply, r: np.ndarray, e0=None, n: int = 1) -> np.ndarray:
         e = np.zeros_like(r)
         s = r.copy()
     else:
-        e = np.array(e0, dtype=np.float64, copy=True)
+        e = np.array(e0, copy=True)
         s = r - apply(e)
     p = s.copy()
     gamma = float(s @ s)
@@ -61,7 +61,7 @@ def pcg(apply, precond, r: np.ndarray, e0=None, n: int = 1) -> np.ndarray:
         e = np.zeros_like(r)
         s = r.copy()
     else:
-        e = np.array(e0, dtype=np.float64, copy=True)
+        e = np.array(e0, copy=True)
         s = r - apply(e)
     z = precond(s)
     p = z.copy()

@@ -44,7 +44,7 @@ class H2:
     """
 
     def __init__(self, points, kern, shift, leaf, eta, m, length_scale=None, scale=None,
-                 diag=None):
+                 diag=None, near_quad=None):
         if isinstance(kern, str):
             kern = make_kernel(kern, length_scale)
         self.kern = kern
@@ -60,6 +60,14 @@ class H2:
         perm = self.tree.perm
         self.sc = None if scale is None else np.asarray(scale, dtype=np.float64)[perm]
         self.dg = None if diag is None else np.asarray(diag, dtype=np.float64)[perm]
+        # close entries by quadrature: point i carries sub-points Y[i, p] with
+        # weights U[i, p], and the entry between distinct points i, j of a close
+        # leaf pair is sum_p sum_q U[i, p] U[j, q] k(|Y[i, p] - Y[j, q]|)
+        # (far blocks keep the point values; the diagonal keeps d or the shift)
+        self.qy = self.qu = None
+        if near_quad is not None:
+            self.qy = np.asarray(near_quad[0], dtype=np.float64)[perm]
+            self.qu = np.asarray(near_quad[1], dtype=np.float64)[perm]
         floor = cheb.width_floor(self.tree)
         self.c, self.h = [], []
         for d in range(self.L + 1):
@@ -105,6 +113,8 @@ class H2:
         s == t; rows and columns scaled by s in the scaled form)."""
         rs, rt = self.rows(self.L, s), self.rows(self.L, t)
         Xs = self.P[rs]
+        if self.qy is not None:
+            return self._quad_block(rs, rt, s == t)
         if s == t:
             K = kernel_matrix(self.kern, Xs, 0.0 if self.dg is not None else self.shift)
         else:
@@ -113,6 +123,21 @@ class H2:
             K = self.sc[rs, None] * K * self.sc[None, rt]
         if s == t and self.dg is not None:
             K[np.diag_indices_from(K)] += self.dg[rs]
+        return K
+
+    def _quad_block(self, rs, rt, diagonal):
+        """Close block by quadrature on both points (see __init__)."""
+        ys, us = self.qy[rs], self.qu[rs]            # (ns, q, dim), (ns, q)
+        yt, ut = self.qy[rt], self.qu[rt]
+        ns, q, dim = ys.shape
+        nt = yt.shape[0]
+        K = np.zeros((ns, nt))
+        for p in range(q):
+            for r in range(q):
+                Kpr = kernel_matrix(self.kern, ys[:, p, :], 0.0, yt[:, r, :])
+                K += us[:, p, None] * Kpr * ut[None, :, r]
+        if diagonal:
+            K[np.diag_indices_from(K)] = self.dg[rs] if self.dg is not None else self.shift
         return K
 
     # ---- products -----------------------------------------------------

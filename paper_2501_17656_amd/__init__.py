@@ -9,6 +9,7 @@ at a time (`matvec`, `solve`) or 16 at a time (`matvec_multi`,
 libh2mg.so; this package only marshals arguments.
 """
 from .h2mg import H2Matrix, Plan, KERNELS, PRECISIONS  # noqa: F401
-from .h2mg import bem_density, bem_harmonic_rhs, bem_panels, bem_point_source_rhs, solve_batch  # noqa: F401
+from .h2mg import (bem_density, bem_harmonic_rhs, bem_panels, bem_point_source_rhs, bem_quadrature7,  # noqa: F401
+                   solve_batch)
 from ._lib import H2MGError  # noqa: F401
 from .autograd import quadratic_loss  # noqa: F401

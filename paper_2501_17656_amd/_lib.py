@@ -69,6 +69,7 @@ SIGNATURES = {
                              ctypes.POINTER(SolveInfo), c_void_p]),
     "h2mg_solve_history": (c_int32, [c_void_p, P_double, c_int32]),
     "h2mg_memory_bytes": (c_int32, [c_void_p, P_int64]),
+    "h2mg_gemv_launch_info": (c_int32, [c_void_p, c_int32, P_int64, P_int64]),
     "h2mg_set_timing": (c_int32, [c_void_p, c_int32]),
     "h2mg_store_near": (c_int32, [c_void_p, c_int32, c_void_p]),
     "h2mg_set_graphs": (c_int32, [c_void_p, c_int32]),
@@ -80,10 +81,15 @@ SIGNATURES = {
     "h2mg_solve_batch": (c_int32, [c_int32, ctypes.POINTER(c_void_p), P_int32, ctypes.POINTER(c_void_p), P_int32,
                                    ctypes.POINTER(c_void_p), P_int32, ctypes.POINTER(SolveOpts),
                                    ctypes.POINTER(SolveInfo), P_int32, c_int32, c_void_p]),
+    "h2mg_solve_group": (c_int32, [c_int32, ctypes.POINTER(c_void_p), P_int32, ctypes.POINTER(c_void_p), P_int32,
+                                   ctypes.POINTER(c_void_p), P_int32, ctypes.POINTER(SolveOpts),
+                                   ctypes.POINTER(SolveInfo), P_int32, c_void_p]),
     "h2mg_build_scaled": (c_int32, [c_void_p, c_int64, c_int32, ctypes.POINTER(Kernel), ctypes.POINTER(BuildOpts),
                                     c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_void_p)]),
     "h2mg_bem_panels": (c_int32, [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),
     "h2mg_bem_point_source_rhs": (c_int32, [c_void_p, c_void_p, c_int64, P_double, c_void_p, c_void_p]),
+    "h2mg_bem_quadrature7": (c_int32, [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
+    "h2mg_set_near_quadrature": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
     "h2mg_bem_density": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
     "h2mg_bem_harmonic_rhs": (c_int32, [c_void_p, c_void_p, c_int64, P_double, c_void_p, c_void_p]),
     "h2mg_smooth": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p]),

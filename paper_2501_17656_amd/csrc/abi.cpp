@@ -179,6 +179,25 @@ h2mg_status h2mg_bem_panels(const double* V, int64_t nv, const int64_t* T, int64
   });
 }
 
+h2mg_status h2mg_bem_quadrature7(const double* V, int64_t nv, const int64_t* T, int64_t nt, double* qy,
+                                 double* qu, hipStream_t stream) {
+  return guarded([&] {
+    if (!V || !T || !qy || !qu) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    if (nv < 3 || nt < 1) return fail(H2MG_ERR_INVALID_ARG, "need at least 3 vertices and 1 triangle");
+    launch_bem_quadrature7(stream, nt, V, T, qy, qu);
+    return check_stream_err(stream);
+  });
+}
+
+h2mg_status h2mg_set_near_quadrature(h2mg_h2_t hh, const double* qy, const double* qu, int32_t nq,
+                                     hipStream_t stream) {
+  return guarded([&] {
+    if (!hh || !qy || !qu) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    hh->h->stream = stream;
+    return set_near_quadrature(*hh->h, qy, qu, nq);
+  });
+}
+
 h2mg_status h2mg_bem_point_source_rhs(const double* y, const double* s, int64_t n, const double* x0,
                                       double* f, hipStream_t stream) {
   return guarded([&] {
@@ -453,6 +472,23 @@ h2mg_status h2mg_solve_batch(int32_t nprob, const h2mg_h2_t* hs, const int32_t* 
   });
 }
 
+h2mg_status h2mg_solve_group(int32_t nprob, const h2mg_h2_t* hs, const int32_t* nrhs,
+                             const double* const* b, const int32_t* ldb, double* const* x,
+                             const int32_t* ldx, const h2mg_solve_opts* opts, h2mg_solve_info* infos,
+                             h2mg_status* statuses, hipStream_t stream) {
+  return guarded([&] {
+    if (nprob < 1 || !hs || !nrhs || !b || !ldb || !x || !ldx)
+      return fail(H2MG_ERR_INVALID_ARG, "null argument or empty group");
+    if (!valid_solve_opts(opts)) return fail(H2MG_ERR_INVALID_ARG, "invalid solve options");
+    std::vector<H2*> hv(nprob);
+    for (int i = 0; i < nprob; ++i) {
+      if (!hs[i]) return fail(H2MG_ERR_INVALID_ARG, "null handle in problem %d", i);
+      hv[i] = hs[i]->h;
+    }
+    return solve_group(nprob, hv.data(), nrhs, b, ldb, x, ldx, to_params(opts), infos, statuses, stream);
+  });
+}
+
 h2mg_status h2mg_store_near(h2mg_h2_t hh, int32_t enable, hipStream_t stream) {
   return guarded([&] {
     if (!hh) return fail(H2MG_ERR_INVALID_ARG, "null handle");
@@ -520,6 +556,24 @@ h2mg_status h2mg_kernel_stats(h2mg_h2_t hh, int32_t kind, int64_t* launches, dou
     *launches = h.kstat[kind].launches;
     *total_ms = h.kstat[kind].ms;
     *total_work = h.kstat[kind].bytes;
+    return H2MG_OK;
+  });
+}
+
+h2mg_status h2mg_gemv_launch_info(h2mg_h2_t hh, int32_t level, int64_t* tasks, int64_t* blocks) {
+  return guarded([&] {
+    if (!hh || !tasks || !blocks) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    H2& h = *hh->h;
+    if (level < 1 || level > h.levels) return fail(H2MG_ERR_INVALID_ARG, "level out of range");
+    if (level == 1) {
+      *tasks = h.fine_launch.ntasks;
+      *blocks = h.fine_launch.nblocks;
+      return H2MG_OK;
+    }
+    if (!h.mg_built) return fail(H2MG_ERR_STATE, "call h2mg_setup_mg first");
+    const Launch& l = h.coarse_launch[h.level_depth(level)];
+    *tasks = l.ntasks;
+    *blocks = l.nblocks;
     return H2MG_OK;
   });
 }

@@ -51,16 +51,24 @@ T* upload_owned(H2& h, const std::vector<T>& v) {
 // every tile, column-pass tasks the off-diagonal ones; tiles keep their id
 // order within a row or column, and a row's (column's) tasks are
 // consecutive.
+// Read-once form when a tile's transposed product (rr x 16 words) is at most
+// half the stored tile (RP x RP words): writing and reducing it moves less
+// than reading the tile a second time.
+bool use_dual(int T, int rr) { return rr * NR * 2 <= (8 * T) * (8 * T); }
+
 TileSet make_set(H2& h, const std::vector<int>& ids, const std::vector<int>& rows, const std::vector<int>& cols,
-                 int nrows_total, int row0, int nrows, const int* brow, const int* bcol, int run) {
+                 int nrows_total, int row0, int nrows, const int* brow, const int* bcol, int run,
+                 bool dual) {
   TileSet ts;
   ts.run = run;
+  ts.dual = dual;
   ts.brow = brow;
   ts.bcol = bcol;
   ts.row0 = row0;
   ts.nrows = nrows;
   ts.ntiles = int64_t(ids.size());
-  auto build = [&](bool by_col, std::vector<int>& order, std::vector<int>& tasks, std::vector<int>& ptr) {
+  auto build = [&](bool by_col, int runlen, std::vector<int>& order, std::vector<int>& tasks,
+                   std::vector<int>& ptr) {
     std::vector<std::pair<int, int>> kb;
     for (int b : ids) {
       if (by_col && rows[b] == cols[b]) continue;
@@ -73,10 +81,10 @@ TileSet make_set(H2& h, const std::vector<int>& ids, const std::vector<int>& row
     for (size_t i = 0; i < kb.size();) {
       size_t e = i;
       while (e < kb.size() && kb[e].first == kb[i].first) ++e;
-      for (size_t c = i; c < e; c += size_t(run)) {
+      for (size_t c = i; c < e; c += size_t(runlen)) {
         tasks.push_back(kb[i].first);
         tasks.push_back(int(c));
-        tasks.push_back(int(std::min(e, c + size_t(run))));
+        tasks.push_back(int(std::min(e, c + size_t(runlen))));
         ptr[size_t(kb[i].first) + 1]++;
       }
       i = e;
@@ -85,16 +93,24 @@ TileSet make_set(H2& h, const std::vector<int>& ids, const std::vector<int>& row
     return int64_t(kb.size());
   };
   std::vector<int> ro, rt, rp, co, ct, cp;
-  build(false, ro, rt, rp);
-  ts.nctiles = build(true, co, ct, cp);
+  build(false, run, ro, rt, rp);
+  // read-once: one column slot per off-diagonal tile (runs of 1), no column tasks
+  ts.nctiles = build(true, dual ? 1 : run, co, ct, cp);
   ts.nrt = int(rt.size() / 3);
-  ts.nct = int(ct.size() / 3);
+  ts.nct = dual ? 0 : int(ct.size() / 3);
   ts.rorder = upload_owned(h, ro);
   ts.rtask = upload_owned(h, rt);
   ts.rtp = upload_owned(h, rp);
   ts.corder = upload_owned(h, co);
   ts.ctask = upload_owned(h, ct);
   ts.ctp = upload_owned(h, cp);
+  if (dual) {
+    std::vector<int> pos(size_t(*std::max_element(ids.begin(), ids.end())) + 1, -1);
+    for (size_t i = 0; i < co.size(); ++i) pos[size_t(co[i])] = int(i);
+    std::vector<int> slot(ro.size());
+    for (size_t i = 0; i < ro.size(); ++i) slot[i] = pos[size_t(ro[i])];
+    ts.rslot = upload_owned(h, slot);
+  }
   return ts;
 }
 
@@ -113,7 +129,8 @@ void ensure_partial(H2& h, int64_t elems) {
 void free_set(H2& h, TileSet& ts) {
   BlockWork& w = h.blk16;
   for (void* d : {static_cast<void*>(ts.rorder), static_cast<void*>(ts.rtask), static_cast<void*>(ts.rtp),
-                  static_cast<void*>(ts.corder), static_cast<void*>(ts.ctask), static_cast<void*>(ts.ctp)}) {
+                  static_cast<void*>(ts.corder), static_cast<void*>(ts.ctask), static_cast<void*>(ts.ctp),
+                  static_cast<void*>(ts.rslot)}) {
     auto it = std::find(w.owned.begin(), w.owned.end(), d);
     if (it != w.owned.end()) {
       w.owned.erase(it);
@@ -140,8 +157,9 @@ TileSet tuned_set(H2& h, int p, bool near, const void* x, void* out, const std::
                   const std::vector<int>& rows, const std::vector<int>& cols, int nrows_total, int row0,
                   int nrows, const int* brow, const int* bcol) {
   const int rr = near ? 64 : h.r;
+  const bool dual = use_dual(near ? 8 : h.T, rr);
   if (!h.autotune || ids.empty())
-    return make_set(h, ids, rows, cols, nrows_total, row0, nrows, brow, bcol, RUN);
+    return make_set(h, ids, rows, cols, nrows_total, row0, nrows, brow, bcol, RUN, dual);
   hipEvent_t e0, e1;
   hip_check(hipEventCreate(&e0), "event");
   hip_check(hipEventCreate(&e1), "event");
@@ -149,8 +167,8 @@ TileSet tuned_set(H2& h, int p, bool near, const void* x, void* out, const std::
   float best_ms = 0.0f;
   try {
     for (int run : RUNS) {
-      TileSet ts = make_set(h, ids, rows, cols, nrows_total, row0, nrows, brow, bcol, run);
-      const int64_t need = int64_t(ts.nrt + ts.nct) * rr * NR;
+      TileSet ts = make_set(h, ids, rows, cols, nrows_total, row0, nrows, brow, bcol, run, dual);
+      const int64_t need = ts.nslots() * rr * NR;
       size_t free_b = 0, total_b = 0;
       hip_check(hipMemGetInfo(&free_b, &total_b), "memory info");
       if (best.rtask && need > h.blk16.partial_elems && size_t(need) * sizeof(double) > free_b / 4) {
@@ -202,7 +220,7 @@ void ensure_block(H2& h, int p) {
       hip_check(hipMemsetAsync(w.xall, 0, size_t(h.ngid) * r * NR * sizeof(double), h.stream), "memset");
       w.fine = tuned_set(h, p, false, w.xall, w.yall, ids, h.blk_row_h, h.blk_col_h, h.ngid, row0,
                          h.ngid - row0, h.blk_row, h.blk_col);
-      ensure_partial(h, int64_t(w.fine.nrt + w.fine.nct) * r * NR);
+      ensure_partial(h, w.fine.nslots() * r * NR);
     }
     w.bx = static_cast<double*>(alloc_owned(h, size_t(h.n) * NR * sizeof(double)));
     w.by = static_cast<double*>(alloc_owned(h, size_t(h.n) * NR * sizeof(double)));
@@ -226,7 +244,7 @@ void ensure_block(H2& h, int p) {
                                  : p == P64 ? static_cast<const void*>(w.xc64) : static_cast<const void*>(w.xc32);
     w.near = tuned_set(h, p, true, xn, w.yc, ids, sn.brow_h, sn.bcol_h, sn.nchunk, 0, sn.nchunk, sn.blk_row,
                        sn.blk_col);
-    ensure_partial(h, int64_t(w.near.nrt + w.near.nct) * 64 * NR);
+    ensure_partial(h, w.near.nslots() * 64 * NR);
     w.near_ready = true;
   }
   if (h.mg_built && !w.coarse_ready && h.d_top >= 0) {
@@ -239,13 +257,13 @@ void ensure_block(H2& h, int p) {
       for (int b = h.p_first[d]; b < h.p_first[d] + h.p_count[d]; ++b) ids.push_back(b);
       w.coarse[d] = tuned_set(h, p, false, w.xall, w.yall, ids, h.blk_row_h, h.blk_col_h, h.ngid, row0,
                               (2 << d) - 1 - row0, h.blk_row, h.blk_col);
-      ensure_partial(h, int64_t(w.coarse[d].nrt + w.coarse[d].nct) * r * NR);
+      ensure_partial(h, w.coarse[d].nslots() * r * NR);
     }
     w.coarse_ready = true;
   }
   // partial sums for the largest chosen set only (tuning may have grown them)
   int64_t need = 0;
-  auto fit = [&](const TileSet& ts, int rr) { need = std::max(need, int64_t(ts.nrt + ts.nct) * rr * NR); };
+  auto fit = [&](const TileSet& ts, int rr) { need = std::max(need, ts.nslots() * rr * NR); };
   fit(w.fine, r);
   fit(w.near, 64);
   for (const TileSet& ts : w.coarse) fit(ts, r);
@@ -293,7 +311,9 @@ void apply_fine16(H2& h, int p, const void* X, void* out, double alpha, const vo
     int ev;
     h.time_begin(ev);
     launch_tgemm(h, P64, 8, w.near, sn.tiles, 64, xc, w.partial);
-    h.time_end(KS_NEAR16, ev, double(w.near.ntiles + w.near.nctiles) * 4096.0 * sizeof(double));
+    h.time_end(KS_NEAR16, ev, double(w.near.ntiles) * 4096.0 * sizeof(double));   // each stored tile once
+  } else if (near_stored_for(h, p)) {
+    launch_tgemm(h, P32, 8, w.near, sn.tiles32, 64, xc, w.partial);
   } else {
     launch_tgemm_eval(h, vprec(p), w.near, xc, w.partial);
   }
@@ -448,6 +468,217 @@ void mg16(H2& h, Work16& w, int k, int kind, int n_f, int n_c) {
   if (k == 1) launch_leaf_down16(h, p, w.et[k + 1], nullptr, w.et[k], 1.0, w.et[k], 1.0);
   else launch_transfer_down16(h, p, h.level_depth(k) - 1, w.et[k + 1], w.et[k], w.et[k]);
   cg16(h, w, k, w.r[k], w.et[k], false, nk);
+}
+
+// ------------------------------------------------------------ several problems per launch
+// The same cycle for a group of independent problems advancing in step: every
+// tile product of a step (couplings, projected blocks, near-field tiles) is
+// one launch over the task sets of all members (launch_tgemm_group), the
+// other steps are each member's own launches on the group's stream.  Each
+// member's arithmetic, and its order, is exactly that of its own solve, so
+// its iterates are bit for bit those of a solve of its own.  A member takes
+// part in a level's step only when that level exists for it (problems have
+// different depths); on its coarsest level it does the direct solve.
+struct GM {
+  H2* h;
+  Work16* w;
+};
+
+// Y_m = A_k X_m for every member (each at its own level k).
+void apply16_group(const std::vector<GM>& G, int p, int k, const std::vector<const void*>& X,
+                   const std::vector<void*>& Y, double alpha = 1.0, const std::vector<const void*>* add = nullptr,
+                   double beta = 0.0) {
+  if (G.empty()) return;
+  const hipStream_t st = G[0].h->stream;
+  const int vp = vprec(p);
+  std::vector<GroupTiles> tiles;
+  if (k == 1) {
+    std::vector<const void*> yhat(G.size(), nullptr);
+    for (size_t i = 0; i < G.size(); ++i) {
+      H2& h = *G[i].h;
+      BlockWork& w = h.blk16;
+      if (h.d_top < 0) continue;
+      launch_leaf_up16(h, p, X[i], at_depth(w.xall, p, h.L, h.r));
+      for (int d = h.L - 1; d >= h.d_top; --d)
+        launch_transfer_up16(h, p, d, at_depth(w.xall, p, d + 1, h.r), at_depth(w.xall, p, d, h.r));
+      tiles.push_back(GroupTiles{h.T, &w.fine, h.prec[p].blk, h.r, w.xall, w.partial});
+    }
+    launch_tgemm_group(st, p, tiles);
+    std::vector<const void*> xc(G.size());
+    for (size_t i = 0; i < G.size(); ++i) {
+      H2& h = *G[i].h;
+      BlockWork& w = h.blk16;
+      if (h.d_top >= 0) {
+        launch_reduce16(h, p, w.fine, h.r, w.partial, w.yall);
+        for (int d = h.d_top + 1; d <= h.L; ++d)
+          launch_transfer_down16(h, p, d - 1, at_depth(w.yall, p, d - 1, h.r), at_depth(w.yall, p, d, h.r),
+                                 at_depth(w.yall, p, d, h.r));
+        yhat[i] = at_depth(w.yall, p, h.L, h.r);
+      }
+      xc[i] = X[i];
+      if (!h.snear.identity) {
+        void* buf = p == P64 ? static_cast<void*>(w.xc64) : static_cast<void*>(w.xc32);
+        launch_near_pad16(h, p, X[i], buf);
+        xc[i] = buf;
+      }
+    }
+    tiles.clear();
+    std::vector<GroupTiles> tiles32;
+    std::vector<GroupEval> evals;
+    for (size_t i = 0; i < G.size(); ++i) {
+      H2& h = *G[i].h;
+      BlockWork& w = h.blk16;
+      if (p == P64 && h.snear.ready) tiles.push_back(GroupTiles{8, &w.near, h.snear.tiles, 64, xc[i], w.partial});
+      else if (near_stored_for(h, p)) tiles32.push_back(GroupTiles{8, &w.near, h.snear.tiles32, 64, xc[i], w.partial});
+      else evals.push_back(GroupEval{&h, &w.near, xc[i], w.partial});
+    }
+    launch_tgemm_group(st, P64, tiles);
+    launch_tgemm_group(st, P32, tiles32);
+    launch_tgemm_eval_group(st, vp, evals);
+    for (size_t i = 0; i < G.size(); ++i) {
+      H2& h = *G[i].h;
+      BlockWork& w = h.blk16;
+      launch_reduce16(h, p, w.near, 64, w.partial, w.yc);
+      launch_leaf_down16(h, p, yhat[i], w.yc, Y[i], alpha, add ? (*add)[i] : nullptr, beta);
+    }
+    return;
+  }
+  for (size_t i = 0; i < G.size(); ++i) {
+    H2& h = *G[i].h;
+    BlockWork& w = h.blk16;
+    const int r = h.r, d = h.level_depth(k);
+    launch_copy(h, vp, X[i], at_depth(w.xall, p, d, r), int64_t(1 << d) * r * NR);
+    for (int q = d - 1; q >= h.d_top; --q)
+      launch_transfer_up16(h, p, q, at_depth(w.xall, p, q + 1, r), at_depth(w.xall, p, q, r));
+    tiles.push_back(GroupTiles{h.T, &w.coarse[d], h.prec[p].blk, r, w.xall, w.partial});
+  }
+  launch_tgemm_group(st, p, tiles);
+  for (size_t i = 0; i < G.size(); ++i) {
+    H2& h = *G[i].h;
+    BlockWork& w = h.blk16;
+    const int r = h.r, d = h.level_depth(k);
+    launch_reduce16(h, p, w.coarse[d], r, w.partial, w.yall);
+    for (int q = h.d_top + 1; q <= d; ++q)
+      launch_transfer_down16(h, p, q - 1, at_depth(w.yall, p, q - 1, r), q == d ? Y[i] : at_depth(w.yall, p, q, r),
+                             at_depth(w.yall, p, q, r));
+    if (d == h.d_top) launch_copy(h, vp, at_depth(w.yall, p, d, r), Y[i], int64_t(1 << d) * r * NR);
+  }
+}
+
+// cg16 for every member: e = Iter(A_k, rhs, e0) on level k.
+void cg16_group(const std::vector<GM>& G, int k, bool e0_zero, int nsteps) {
+  if (G.empty()) return;
+  const int p = G[0].w->p, vp = vprec(p);
+  auto N = [&](const GM& m) { return m.h->level_size(k); };
+  std::vector<const void*> X(G.size());
+  std::vector<void*> Y(G.size());
+  for (const GM& m : G)
+    if (e0_zero) launch_zero(*m.h, vp, m.w->et[k], N(m) * NR);
+  if (nsteps <= 0) return;
+  if (!e0_zero) {
+    for (size_t i = 0; i < G.size(); ++i) {
+      X[i] = G[i].w->et[k];
+      Y[i] = G[i].w->q;
+    }
+    apply16_group(G, p, k, X, Y);
+  }
+  for (const GM& m : G) {
+    H2& h = *m.h;
+    Work16& w = *m.w;
+    const int64_t nf = N(m) * NR;
+    launch_copy(h, vp, w.r[k], w.s, nf);
+    if (!e0_zero) launch_axpby(h, vp, nf, -1.0, w.q, 1.0, w.s);
+    if (w.smoother == 1) {
+      launch_bj_apply16(h, p, k, w.s, w.z);
+      launch_copy(h, vp, w.z, w.pv, nf);
+      launch_dot16(h, vp, N(m), w.s, w.z, w.gpart(0));
+    } else {
+      launch_copy(h, vp, w.s, w.pv, nf);
+      launch_dot16(h, vp, N(m), w.s, w.s, w.gpart(0));
+    }
+  }
+  int cur = 0;
+  for (int it = 0; it < nsteps; ++it) {
+    for (size_t i = 0; i < G.size(); ++i) {
+      X[i] = G[i].w->pv;
+      Y[i] = G[i].w->q;
+    }
+    apply16_group(G, p, k, X, Y);
+    for (const GM& m : G) {
+      H2& h = *m.h;
+      Work16& w = *m.w;
+      const int64_t n = N(m);
+      void* e = w.et[k];
+      launch_dot16(h, vp, n, w.pv, w.q, w.dpart());
+      if (w.smoother == 1) {
+        launch_cg_update16(h, vp, n, e, w.pv, w.s, w.q, w.gpart(cur), w.dpart(), w.scratch());
+        launch_bj_apply16(h, p, k, w.s, w.z);
+        launch_dot16(h, vp, n, w.s, w.z, w.gpart(1 - cur));
+        if (it + 1 < nsteps) launch_cg_pupdate16(h, vp, n, w.pv, w.z, w.gpart(cur), w.gpart(1 - cur));
+      } else {
+        launch_cg_update16(h, vp, n, e, w.pv, w.s, w.q, w.gpart(cur), w.dpart(), w.gpart(1 - cur));
+        if (it + 1 < nsteps) launch_cg_pupdate16(h, vp, n, w.pv, w.s, w.gpart(cur), w.gpart(1 - cur));
+      }
+    }
+    cur = 1 - cur;
+  }
+}
+
+// mg16 for every member, level k down.
+void mg16_group(const std::vector<GM>& all, int k, int kind, int n_f, int n_c) {
+  std::vector<GM> G;
+  for (const GM& m : all) {
+    if (k == m.h->levels) coarse_solve16(*m.h, *m.w, m.w->r[k], m.w->et[k]);
+    else if (k < m.h->levels) G.push_back(m);
+  }
+  if (G.empty()) return;
+  const int p = G[0].w->p, vp = vprec(p);
+  const int nk = k == 1 ? n_f : n_c;
+  cg16_group(G, k, true, nk);
+  std::vector<const void*> X(G.size());
+  std::vector<void*> Y(G.size());
+  for (size_t i = 0; i < G.size(); ++i) {
+    X[i] = G[i].w->et[k];
+    Y[i] = G[i].w->tmp;
+  }
+  apply16_group(G, p, k, X, Y);
+  for (const GM& m : G) {
+    H2& h = *m.h;
+    Work16& w = *m.w;
+    launch_axpby(h, vp, h.level_size(k) * NR, 1.0, w.r[k], -1.0, w.tmp);
+    if (k == 1) launch_leaf_up16(h, p, w.tmp, w.r[k + 1]);
+    else launch_transfer_up16(h, p, h.level_depth(k) - 1, w.tmp, w.r[k + 1]);
+  }
+  mg16_group(G, k + 1, kind, n_f, n_c);
+  if (kind != CYCLE_V) {
+    std::vector<GM> sub;
+    for (const GM& m : G)
+      if (k + 1 < m.h->levels) sub.push_back(m);
+    if (!sub.empty()) {
+      std::vector<const void*> X1(sub.size());
+      std::vector<void*> Y1(sub.size());
+      for (size_t i = 0; i < sub.size(); ++i) {
+        H2& h = *sub[i].h;
+        Work16& w = *sub[i].w;
+        launch_copy(h, vp, w.et[k + 1], w.ec[k + 1], h.level_size(k + 1) * NR);
+        X1[i] = w.et[k + 1];
+        Y1[i] = w.tmp;
+      }
+      apply16_group(sub, p, k + 1, X1, Y1);
+      for (const GM& m : sub)
+        launch_axpby(*m.h, vp, m.h->level_size(k + 1) * NR, -1.0, m.w->tmp, 1.0, m.w->r[k + 1]);
+      mg16_group(sub, k + 1, kind == CYCLE_F ? CYCLE_V : CYCLE_W, n_f, n_c);
+      for (const GM& m : sub)
+        launch_axpby(*m.h, vp, m.h->level_size(k + 1) * NR, 1.0, m.w->ec[k + 1], 1.0, m.w->et[k + 1]);
+    }
+  }
+  for (const GM& m : G) {
+    H2& h = *m.h;
+    Work16& w = *m.w;
+    if (k == 1) launch_leaf_down16(h, p, w.et[k + 1], nullptr, w.et[k], 1.0, w.et[k], 1.0);
+    else launch_transfer_down16(h, p, h.level_depth(k) - 1, w.et[k + 1], w.et[k], w.et[k]);
+  }
+  cg16_group(G, k, false, nk);
 }
 
 // ------------------------------------------------------------ solve driver
@@ -761,6 +992,148 @@ h2mg_status solve_batch(int nprob, H2* const* hs, const int* nrhs, const double*
     (void)hipDeviceSynchronize();
     cleanup();
     return err == H2MG_ERR_OOM ? fail(err, "device allocation failed in the batched solve")
+                               : fail(err, "%s", message[0].c_str());
+  }
+  cleanup();
+  if (statuses)
+    for (int i = 0; i < nprob; ++i) statuses[i] = result[i];
+  for (int i = 0; i < nprob; ++i)
+    if (result[i] != H2MG_OK) return fail(result[i], "problem %d: %s", i, message[i].c_str());
+  return H2MG_OK;
+}
+
+h2mg_status solve_group(int nprob, H2* const* hs, const int* nrhs, const double* const* b, const int* ldb,
+                        double* const* x, const int* ldx, const SolveParams& sp, h2mg_solve_info* infos,
+                        h2mg_status* statuses, hipStream_t user) {
+  if (nprob < 1) return fail(H2MG_ERR_INVALID_ARG, "a group needs at least one problem");
+  for (int i = 0; i < nprob; ++i) {
+    if (!hs[i] || !b[i] || !x[i]) return fail(H2MG_ERR_INVALID_ARG, "null argument in problem %d", i);
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return fail(H2MG_ERR_INVALID_ARG, "problems %d and %d share a handle", j, i);
+    h2mg_status st = check_block_args(*hs[i], nrhs[i], ldb[i], ldx[i], sp);
+    if (st != H2MG_OK) return st;
+  }
+  std::vector<hipStream_t> saved(nprob);
+  for (int i = 0; i < nprob; ++i) saved[i] = hs[i]->stream;
+  std::vector<h2mg_status> result(nprob, H2MG_OK);
+  std::vector<std::string> message(nprob);
+  std::vector<std::unique_ptr<BlockSolve>> bs(nprob);
+  hipStream_t cap = nullptr;
+  CycleGraph graph;
+  std::vector<int> graph_set;          // members of the captured cycle
+  auto record = [&](int i, h2mg_status st) {
+    if (st != H2MG_OK && result[i] == H2MG_OK) {
+      result[i] = st;
+      message[i] = last_error_cstr();
+    }
+  };
+  auto cleanup = [&]() {
+    graph.reset();
+    for (auto& q : bs) q.reset();
+    for (int i = 0; i < nprob; ++i) hs[i]->stream = saved[i];
+    if (cap) (void)hipStreamDestroy(cap);
+  };
+  const int p = sp.precision == 0 ? P64 : sp.precision == 1 ? P32 : P16;
+  bool graphs = true;
+  for (int i = 0; i < nprob; ++i) graphs = graphs && hs[i]->graphs && !hs[i]->timing;
+  h2mg_status err = H2MG_OK;
+  try {
+    for (int i = 0; i < nprob; ++i) hs[i]->stream = user;
+    for (int i = 0; i < nprob; ++i) {
+      bs[i].reset(new BlockSolve);
+      const h2mg_status st = bs[i]->begin(*hs[i], nrhs[i], b[i], ldb[i], x[i], ldx[i], sp);
+      record(i, st);
+      if (st != H2MG_OK) bs[i].reset();
+    }
+    for (;;) {
+      std::vector<int> act;
+      for (int i = 0; i < nprob; ++i)
+        if (bs[i] && !bs[i]->done) act.push_back(i);
+      if (act.empty()) break;
+      // residuals R = B - A_H2 X of every active problem (FP64), one group product
+      std::vector<GM> G64;
+      std::vector<const void*> X, add;
+      std::vector<void*> Y;
+      for (int i : act) {
+        G64.push_back(GM{hs[i], &bs[i]->w64});
+        X.push_back(bs[i]->xt);
+        Y.push_back(bs[i]->w64.r[1]);
+        add.push_back(bs[i]->bt);
+      }
+      apply16_group(G64, P64, 1, X, Y, -1.0, &add, 1.0);
+      for (int i : act) {
+        launch_dot16(*hs[i], P64, hs[i]->n, bs[i]->w64.r[1], bs[i]->w64.r[1], bs[i]->npart);
+        bs[i]->read_async();
+      }
+      std::vector<int> next;
+      for (int i : act) {
+        hip_check(hipEventSynchronize(bs[i]->ev), "sync");
+        bs[i]->check();
+        record(i, bs[i]->status);
+        if (bs[i]->done) {
+          bs[i]->finish(infos ? infos + i : nullptr, nullptr);
+          bs[i].reset();
+        } else {
+          next.push_back(i);
+        }
+      }
+      if (next.empty()) break;
+      // one cycle of every remaining problem, the tile products of each step in one launch
+      auto body = [&]() {
+        std::vector<GM> G;
+        for (int i : next) G.push_back(GM{hs[i], p == P64 ? &bs[i]->w64 : &bs[i]->wlp});
+        if (p != P64)
+          for (int i : next)
+            launch_cast(*hs[i], P32, bs[i]->wlp.r[1], P64, bs[i]->w64.r[1], int64_t(hs[i]->n) * NR);
+        mg16_group(G, 1, sp.method, sp.n_fine, sp.n_coarse);
+        for (int i : next) {
+          H2& H = *hs[i];
+          const int64_t nf = int64_t(H.n) * NR;
+          if (p == P64) {
+            launch_axpby(H, P64, nf, 1.0, bs[i]->w64.et[1], 1.0, bs[i]->xt);
+          } else {
+            launch_cast(H, P64, bs[i]->w64.tmp, P32, bs[i]->wlp.et[1], nf);
+            launch_axpby(H, P64, nf, 1.0, bs[i]->w64.tmp, 1.0, bs[i]->xt);
+          }
+        }
+      };
+      if (graphs) {
+        if (graph_set != next) {
+          // the active set changed: record the cycle of the new set
+          graph.reset();
+          if (!cap) hip_check(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "stream create");
+          for (int i : next) hs[i]->stream = cap;
+          hip_check(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture");
+          try {
+            body();
+          } catch (...) {
+            hipGraph_t partial = nullptr;
+            (void)hipStreamEndCapture(cap, &partial);
+            if (partial) (void)hipGraphDestroy(partial);
+            for (int i : next) hs[i]->stream = user;
+            throw;
+          }
+          for (int i : next) hs[i]->stream = user;
+          hip_check(hipStreamEndCapture(cap, &graph.graph), "end capture");
+          hip_check(hipGraphInstantiate(&graph.exec, graph.graph, nullptr, nullptr, 0), "graph instantiate");
+          graph_set = next;
+        }
+        hip_check(hipGraphLaunch(graph.exec, user), "graph launch");
+      } else {
+        body();
+      }
+      for (int i : next) ++bs[i]->cycles;
+    }
+  } catch (const std::bad_alloc&) {
+    err = H2MG_ERR_OOM;
+  } catch (const std::exception& ex) {
+    err = H2MG_ERR_HIP;
+    message[0] = ex.what();
+  }
+  if (err != H2MG_OK) {
+    (void)hipDeviceSynchronize();
+    cleanup();
+    return err == H2MG_ERR_OOM ? fail(err, "device allocation failed in the group solve")
                                : fail(err, "%s", message[0].c_str());
   }
   cleanup();

@@ -187,10 +187,17 @@ __device__ inline float kernel_r2(const KernelParams& kp, float r2) {
 
 // Per-point scale s (on rows and columns) and diagonal d of the scaled form
 // diag(s) K diag(s) + diag(d), tree order; null pointers mean s = 1 and
-// d = the constant shift.
+// d = the constant shift.  Optional quadrature of the close entries: point i
+// carries nq sub-points qy[i] (nq x dim, row-major) with weights qu[i] (nq),
+// and the entry between distinct points i, j of a close leaf pair is
+// sum_p sum_q qu[i][p] qu[j][q] k(|qy[i][p] - qy[j][q]|) (the weights carry
+// any scaling; far blocks keep the point values).
 struct PointScale {
   const double* s;
   const double* d;
+  const double* qy;
+  const double* qu;
+  int nq;
 };
 
 // One entry of the scaled matrix from the kernel value k between tree
@@ -200,6 +207,35 @@ __device__ inline double scaled_entry(double k, int64_t i, int64_t j, bool self,
   if (ps.s) k *= ps.s[i] * ps.s[j];
   if (self) k += ps.d ? ps.d[i] : shift;
   return k;
+}
+
+// The close entry (i, j) of a leaf pair: the point kernel value (squared
+// distance r2 of the two points) in the scaled form, or the quadrature sum
+// when the close entries are given by quadrature (its diagonal is d or the
+// shift).
+__device__ inline double near_entry(const KernelParams& kp, const PointScale& ps, int dim, double r2,
+                                    int64_t i, int64_t j, bool self) {
+  if (!ps.qy) return scaled_entry(kernel_r2(kp, r2), i, j, self, ps, kp.shift);
+  if (self) return ps.d ? ps.d[i] : kp.shift;
+  const int nq = ps.nq;
+  const double* yi = ps.qy + i * nq * dim;
+  const double* yj = ps.qy + j * nq * dim;
+  const double* ui = ps.qu + i * nq;
+  const double* uj = ps.qu + j * nq;
+  double sum = 0.0;
+  for (int p = 0; p < nq; ++p) {
+    double part = 0.0;
+    for (int q = 0; q < nq; ++q) {
+      double d2 = 0.0;
+      for (int a = 0; a < dim; ++a) {
+        const double dx = yi[p * dim + a] - yj[q * dim + a];
+        d2 += dx * dx;
+      }
+      part += uj[q] * kernel_r2(kp, d2);
+    }
+    sum += ui[p] * part;
+  }
+  return sum;
 }
 
 // ---------------------------------------------------------------- shuffles

@@ -48,7 +48,7 @@ void apply_fine(H2& h, int p, const void* xt, void* out, double alpha, const voi
                            at_depth(yall, p, d, r));
   }
   // near field and leaf downsweep: y = D x + Q y_L
-  if (p == P64 && h.snear.ready) launch_near_stored(h, static_cast<const double*>(xt));
+  if (near_stored_for(h, p)) launch_near_stored(h, p, xt);
   else launch_near(h, p, xt);
   launch_fine_reduce(h, p, at_depth(yall, p, h.L, r), out, false, alpha, add, beta, xt);
 }

@@ -394,7 +394,7 @@ h2mg_status build_h2(const double* points_dev, int64_t n, int dim, const h2mg_ke
 
 h2mg_status build_derivative(H2& h, int which, H2** out) {
   if (which != 1 && which != 2) return fail(H2MG_ERR_INVALID_ARG, "derivative must be 1 or 2 (got %d)", which);
-  if (h.kp.kind == KER_LAPLACE || h.scale || h.diag)
+  if (h.kp.kind == KER_LAPLACE || h.scale || h.diag || h.nq > 0)
     return fail(H2MG_ERR_INVALID_ARG, "derivative kernels exist for the exp, Gauss and Matern kernels "
                                       "without per-point scale or diagonal");
   double* user = nullptr;
@@ -589,6 +589,8 @@ void plan_near(H2& h) {
 }
 
 h2mg_status store_near(H2& h, int enable) {
+  if (!enable && h.nq > 0)
+    return fail(H2MG_ERR_STATE, "close entries given by quadrature are applied from the stored tiles only");
   if (!enable) {
     hip_check(hipStreamSynchronize(h.stream), "store_near");
     release_stored_near(h);
@@ -624,6 +626,33 @@ h2mg_status store_near(H2& h, int enable) {
     return fail(H2MG_ERR_HIP, "%s", ex.what());
   }
   return H2MG_OK;
+}
+
+h2mg_status set_near_quadrature(H2& h, const double* qy_user, const double* qu_user, int nq) {
+  if (nq < 1 || nq > 64) return fail(H2MG_ERR_INVALID_ARG, "quadrature points per point must be 1..64 (got %d)", nq);
+  if (h.nq > 0) return fail(H2MG_ERR_STATE, "the close entries already have a quadrature");
+  if (h.mg_built || h.snear.ready || h.bj_built[P64] || h.blk16.ready)
+    return fail(H2MG_ERR_STATE, "set the quadrature of the close entries right after the build");
+  try {
+    h.qy = h.arena.make<double>(size_t(h.n) * nq * h.dim);
+    h.qu = h.arena.make<double>(size_t(h.n) * nq);
+    launch_gather_rows(h, nq * h.dim, qy_user, h.qy);
+    launch_gather_rows(h, nq, qu_user, h.qu);
+    hip_check(hipStreamSynchronize(h.stream), "quadrature");
+  } catch (const std::bad_alloc&) {
+    return fail(H2MG_ERR_OOM, "device allocation failed for the quadrature");
+  } catch (const std::exception& ex) {
+    return fail(H2MG_ERR_HIP, "%s", ex.what());
+  }
+  h.nq = nq;
+  const h2mg_status st = store_near(h, 1);
+  if (st != H2MG_OK) {
+    h.arena.release(h.qy);
+    h.arena.release(h.qu);
+    h.qy = h.qu = nullptr;
+    h.nq = 0;
+  }
+  return st;
 }
 
 h2mg_status setup_mg(H2& h, int precision_mask) {
@@ -703,6 +732,23 @@ h2mg_status setup_mg(H2& h, int precision_mask) {
       launch_cast_precision(h, p);
       hip_check(hipStreamSynchronize(h.stream), "cast");
       pd.ready = true;
+    }
+    // close entries by quadrature cannot be evaluated in the low-precision
+    // products: they read an FP32 copy of the stored tiles
+    if ((precision_mask & ((1 << P32) | (1 << P16))) && h.nq > 0 && h.snear.ready && !h.snear.tiles32) {
+      StoredNear& sn = h.snear;
+      sn.tiles32 = h.arena.make<float>(size_t(std::max<int64_t>(sn.nblocks, 1)) * tile_elems(8));
+      sn.owned.push_back(sn.tiles32);
+      if (!sn.identity) {
+        // the padding must stay zero (a padded tile column times a non-finite
+        // leftover would not vanish)
+        const size_t nvec = size_t(sn.nchunk) * 64;
+        sn.xc32 = h.arena.make<float>(nvec);
+        sn.owned.push_back(sn.xc32);
+        hip_check(hipMemsetAsync(sn.xc32, 0, nvec * sizeof(float), h.stream), "memset");
+      }
+      launch_cast_near_tiles(h);
+      hip_check(hipStreamSynchronize(h.stream), "cast near tiles");
     }
   } catch (const std::bad_alloc&) {
     return fail(H2MG_ERR_OOM, "device allocation failed while building the hierarchy");

@@ -10,6 +10,10 @@ h2mg_status build_h2(const double* points_dev, int64_t n, int dim, const h2mg_ke
                      const h2mg_build_opts* opts, hipStream_t stream, H2** out,
                      const double* scale_dev = nullptr, const double* diag_dev = nullptr);
 h2mg_status setup_mg(H2& h, int precision_mask);
+// Close entries by quadrature (user order: nq x dim sub-points and nq
+// weights per point); stores the near field, which every later product
+// reads (FP64, and an FP32 copy made by setup_mg for low precisions).
+h2mg_status set_near_quadrature(H2& h, const double* qy_user, const double* qu_user, int nq);
 // enable != 0: evaluate the close leaf blocks once and store them (FP64
 // tiles) for every later FP64 fine product; enable == 0: release them and
 // go back to evaluating the near field in every product.
@@ -80,5 +84,10 @@ h2mg_status solve_multi(H2& h, int nrhs, const double* b, int ldb, double* x, in
 h2mg_status solve_batch(int nprob, H2* const* hs, const int* nrhs, const double* const* b, const int* ldb,
                         double* const* x, const int* ldx, const SolveParams& sp, h2mg_solve_info* infos,
                         h2mg_status* statuses, int nstreams, hipStream_t user);
+// The same problems advancing cycle by cycle together on `user`: every tile
+// product of a cycle step is one launch over all active problems.
+h2mg_status solve_group(int nprob, H2* const* hs, const int* nrhs, const double* const* b, const int* ldb,
+                        double* const* x, const int* ldx, const SolveParams& sp, h2mg_solve_info* infos,
+                        h2mg_status* statuses, hipStream_t user);
 
 }  // namespace h2mg

@@ -111,6 +111,8 @@ struct StoredNear {
   int* row_task_ptr = nullptr;         // device: nchunk + 1
   int* col_ptr = nullptr;              // device: nchunk + 1
   double* tiles = nullptr;             // nblocks tiles of 64 x 64 (T = 8 layout)
+  float* tiles32 = nullptr;            // FP32 copy (close entries by quadrature only)
+  float* xc32 = nullptr;               // nchunk * 64 padded FP32 input (zero padding; null when identity)
   double* partial = nullptr;           // ntasks * 64
   double* colpart = nullptr;           // nslot * 64
   double* xc = nullptr;                // nchunk * 64 (padded input; null when identity)
@@ -140,6 +142,13 @@ struct TileSet {
   double tuned_ms = 0.0;               // measured product + reduce time (tuned sets)
   int64_t ntiles = 0;                  // tiles in the set (each read by the row pass)
   int64_t nctiles = 0;                 // off-diagonal tiles (read again by the column pass)
+  // read-once form: no column-pass tasks; each row task also writes the
+  // transposed product of its off-diagonal tiles to slot rslot[i] (i: place
+  // in rorder; -1 for diagonal tiles), slots ordered by block column (ctp
+  // counts tiles, corder lists them)
+  bool dual = false;
+  int* rslot = nullptr;                // device
+  int64_t nslots() const { return int64_t(nrt) + (dual ? nctiles : nct); }
 };
 
 // Buffers and task sets of the products and cycles on blocks of MULTI_NR
@@ -193,6 +202,11 @@ struct H2 {
   double* scale = nullptr;             // per point s (tree order), or null: s = 1
   double* diag = nullptr;              // per point d (tree order), or null: d = shift
   double* R = nullptr;                 // per gid r x r (setup only, freed after)
+  // close entries by quadrature (tree order; null: point kernel values):
+  // nq sub-points per point (nq x dim) and their weights
+  double* qy = nullptr;
+  double* qu = nullptr;
+  int nq = 0;
 
   // stored blocks: S of depth d in [s_first[d], s_first[d] + s_count[d]),
   // Pi of depth d in [p_first[d], p_first[d] + p_count[d])
@@ -269,6 +283,14 @@ struct H2 {
   int level_depth(int k) const { return L - k + 2; }
 };
 
+// The per-point data of the close entries (scale, diagonal, quadrature).
+inline PointScale near_scale(const H2& h) { return PointScale{h.scale, h.diag, h.qy, h.qu, h.nq}; }
+// Whether the fine product in precision p reads the stored near-field tiles
+// (FP64 tiles when stored; the FP32 copy exists only for quadrature).
+inline bool near_stored_for(const H2& h, int p) {
+  return h.snear.ready && (p == P64 || h.snear.tiles32 != nullptr);
+}
+
 // ------------------------------------------------------------ setup kernels
 void launch_leaf_basis_qr(H2& h);                 // Q (FP64), R of leaves
 void launch_transfer_qr(H2& h, int d);            // E of depth d+1, R of depth d
@@ -301,8 +323,13 @@ void launch_transfer_down(H2& h, int p, int d, const void* ypar, void* ychild,
                           const void* addend);
 void launch_leaf_up(H2& h, int p, const void* xtree, void* xhat);
 void launch_near(H2& h, int p, const void* xtree);
-// Stored near field (FP64): snear.yc = D x over the chunk-padded layout.
-void launch_near_stored(H2& h, const double* xtree);
+// Stored near field: snear.yc = D x over the chunk-padded layout, FP64
+// tiles and vectors (p = P64) or the FP32 tile copy with FP32 vectors.
+void launch_near_stored(H2& h, int p, const void* xtree);
+// FP32 copy of the stored near-field tiles (snear.tiles32).
+void launch_cast_near_tiles(H2& h);
+// tree[i, :] = user[perm[i], :] for rows of `width` doubles.
+void launch_gather_rows(H2& h, int width, const double* user, double* tree);
 // out = alpha * Q yhat + beta * add (tree order).
 void launch_leaf_down(H2& h, int p, const void* yhat, void* out, double alpha, const void* add,
                       double beta);
@@ -326,6 +353,71 @@ void launch_tgemm(H2& h, int tp, int T, const TileSet& ts, const void* tiles, in
 // chunk plan of h.snear; vectors of precision p, chunk-padded).
 void launch_tgemm_eval(H2& h, int p, const TileSet& ts, const void* x, void* partial);
 void launch_reduce16(H2& h, int p, const TileSet& ts, int rr, const void* partial, void* out);
+
+// Tile products of several independent problems in one launch (kernel
+// arguments; member m owns blocks [start[m], start[m+1]) of the grid).
+constexpr int GROUP_MAX = 16;
+struct TgemmMember {
+  const int* rtask;
+  const int* rorder;
+  const int* ctask;
+  const int* corder;
+  const void* tiles;
+  const int* brow;
+  const int* bcol;
+  const void* x;
+  void* partial;
+  const int* rslot;
+  int nrt;
+  int rr;
+};
+struct TgemmGroup {
+  int n;
+  int start[GROUP_MAX + 1];
+  TgemmMember m[GROUP_MAX];
+};
+struct TevalMember {
+  const int* rtask;
+  const int* rorder;
+  const int* ctask;
+  const int* corder;
+  const int* brow;
+  const int* bcol;
+  const int* chunk_start;
+  const int* chunk_n;
+  const double* pts;
+  const void* x;
+  void* partial;
+  const int* rslot;
+  PointScale ps;
+  KernelParams kp;
+  int nrt;
+  int dim;
+};
+struct TevalGroup {
+  int n;
+  int start[GROUP_MAX + 1];
+  TevalMember m[GROUP_MAX];
+};
+// One problem's share of a group launch: its task set over stored tiles of
+// width T (precision tp of the launch), or over near-field tiles evaluated
+// from its points.
+struct GroupTiles {
+  int T;
+  const TileSet* ts;
+  const void* tiles;
+  int rr;
+  const void* x;
+  void* partial;
+};
+struct GroupEval {
+  const H2* h;
+  const TileSet* ts;
+  const void* x;
+  void* partial;
+};
+void launch_tgemm_group(hipStream_t st, int tp, const std::vector<GroupTiles>& items);
+void launch_tgemm_eval_group(hipStream_t st, int p, const std::vector<GroupEval>& items);
 void launch_gather16(H2& h, int nrhs, const double* user, int ldu, double* tree);
 void launch_scatter16(H2& h, int nrhs, const double* tree, double* user, int ldu);
 void launch_leaf_up16(H2& h, int p, const void* x, void* xhat);
@@ -348,6 +440,10 @@ void launch_chol_solve16(H2& h, const double* L, int64_t N, double* x);   // in 
 // s = sqrt(area), diagonal d = self-potential / (4 pi).
 void launch_bem_panels(hipStream_t st, int64_t nt, const double* V, const int64_t* T, double* y,
                        double* s, double* d);
+// Radon's seven-point rule per triangle: points qy (nt x 7 x 3) and weights
+// qu (nt x 7) times sqrt(area), for the quadrature of the close entries.
+void launch_bem_quadrature7(hipStream_t st, int64_t nt, const double* V, const int64_t* T, double* qy,
+                            double* qu);
 // f_i = s_i / (4 pi |y_i - x0|) (x0: 3 host doubles).
 void launch_bem_rhs(hipStream_t st, int64_t n, const double* y, const double* x0, const double* s,
                     double* f);

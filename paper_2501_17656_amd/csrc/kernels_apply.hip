@@ -193,6 +193,18 @@ __global__ __launch_bounds__(256) void k_near_gemv(const int* __restrict__ tasks
                                          colpart, 64);
 }
 
+// The same over FP32 copies of the tiles (close entries given by quadrature,
+// which the FP32 products cannot evaluate on the fly).
+__global__ __launch_bounds__(256) void k_near_gemv32(const int* __restrict__ tasks, int ntasks,
+                                                     const float* __restrict__ tiles,
+                                                     const int* __restrict__ blk_col,
+                                                     const int* __restrict__ blk_slot,
+                                                     const float* __restrict__ x,
+                                                     float* __restrict__ partial,
+                                                     float* __restrict__ colpart) {
+  bsr_gemv_wave<8, true, float, float>(tasks, ntasks, tiles, blk_col, blk_slot, x, partial, colpart, 64);
+}
+
 // Sources of one depth for the reduce: task partials of the row (contiguous
 // in the launch) and column contributions (contiguous slots).
 struct RedDepth {
@@ -534,13 +546,14 @@ __global__ __launch_bounds__(256) void k_leaf_down(const int* __restrict__ leaf_
 // xc[chunk_base[leaf] * 64 + i] = x[leaf_off[leaf] + i]: the tree-order
 // vector in the chunk-padded layout of the stored near field (padding
 // entries are never written and stay zero).
+template <typename Tv>
 __global__ __launch_bounds__(256) void k_near_pad(const int* __restrict__ leaf_off,
                                                   const int* __restrict__ chunk_base,
-                                                  const double* __restrict__ x,
-                                                  double* __restrict__ xc) {
+                                                  const Tv* __restrict__ x,
+                                                  Tv* __restrict__ xc) {
   const int leaf = blockIdx.x;
   const int s0 = leaf_off[leaf], n = leaf_off[leaf + 1] - s0;
-  double* dst = xc + int64_t(chunk_base[leaf]) * 64;
+  Tv* dst = xc + int64_t(chunk_base[leaf]) * 64;
   for (int i = threadIdx.x; i < n; i += 256) dst[i] = x[s0 + i];
 }
 
@@ -690,6 +703,7 @@ void launch_leaf_up(H2& h, int p, const void* xtree, void* xhat) {
 }
 
 void launch_near(H2& h, int p, const void* xtree) {
+  if (h.nq > 0) throw std::runtime_error("close entries by quadrature are applied from the stored tiles only");
   if (h.near.ntasks == 0) return;
   int ev;
   h.time_begin(ev);
@@ -712,22 +726,10 @@ void launch_near(H2& h, int p, const void* xtree) {
   h.time_end(p == P64 ? KS_NEAR64 : KS_NEAR32, ev, double(h.near_evals));
 }
 
-void launch_near_stored(H2& h, const double* xtree) {
+void launch_near_stored(H2& h, int p, const void* xtree) {
   StoredNear& sn = h.snear;
   if (sn.nblocks == 0) return;
-  const double* xc = xtree;
-  if (!sn.identity) {
-    hipLaunchKernelGGL(k_near_pad, dim3(h.nleaf), dim3(256), 0, h.stream, h.leaf_off,
-                       sn.chunk_base, xtree, sn.xc);
-    check_launch("near_pad");
-    xc = sn.xc;
-  }
-  int ev;
-  h.time_begin(ev);
-  hipLaunchKernelGGL(k_near_gemv, dim3(grid_waves(sn.ntasks)), dim3(256), 0, h.stream, sn.task,
-                     sn.ntasks, sn.tiles, sn.blk_col, sn.blk_slot, xc, sn.partial, sn.colpart);
-  check_launch("near_gemv");
-  h.time_end(KS_NEARST64, ev, double(sn.nblocks) * 64.0 * 64.0 * sizeof(double));
+  if (p != P64 && !sn.tiles32) throw std::runtime_error("no FP32 copy of the stored near field");
   RedArgs A{};
   A.ndep = 1;
   A.nrows = sn.nchunk;
@@ -739,8 +741,41 @@ void launch_near_stored(H2& h, const double* xtree) {
   D.nsrc = 1;
   D.row0 = 0;
   D.out_off = 0;
-  hipLaunchKernelGGL(k_reduce<double>, dim3(grid_waves(sn.nchunk)), dim3(256), 0, h.stream, A,
-                     sn.partial, sn.colpart, sn.yc, static_cast<double*>(nullptr), 64);
+  if (p == P64) {
+    const double* xc = static_cast<const double*>(xtree);
+    if (!sn.identity) {
+      hipLaunchKernelGGL(k_near_pad<double>, dim3(h.nleaf), dim3(256), 0, h.stream, h.leaf_off,
+                         sn.chunk_base, xc, sn.xc);
+      check_launch("near_pad");
+      xc = sn.xc;
+    }
+    int ev;
+    h.time_begin(ev);
+    hipLaunchKernelGGL(k_near_gemv, dim3(grid_waves(sn.ntasks)), dim3(256), 0, h.stream, sn.task,
+                       sn.ntasks, sn.tiles, sn.blk_col, sn.blk_slot, xc, sn.partial, sn.colpart);
+    check_launch("near_gemv");
+    h.time_end(KS_NEARST64, ev, double(sn.nblocks) * 64.0 * 64.0 * sizeof(double));
+    hipLaunchKernelGGL(k_reduce<double>, dim3(grid_waves(sn.nchunk)), dim3(256), 0, h.stream, A,
+                       sn.partial, sn.colpart, sn.yc, static_cast<double*>(nullptr), 64);
+  } else {
+    // FP32 partials and output in the first half of the FP64 buffers; the
+    // padded input has a zero-padded FP32 buffer of its own
+    const float* xc = static_cast<const float*>(xtree);
+    if (!sn.identity) {
+      hipLaunchKernelGGL(k_near_pad<float>, dim3(h.nleaf), dim3(256), 0, h.stream, h.leaf_off,
+                         sn.chunk_base, xc, sn.xc32);
+      check_launch("near_pad");
+      xc = sn.xc32;
+    }
+    float* part = reinterpret_cast<float*>(sn.partial);
+    float* cpart = reinterpret_cast<float*>(sn.colpart);
+    hipLaunchKernelGGL(k_near_gemv32, dim3(grid_waves(sn.ntasks)), dim3(256), 0, h.stream, sn.task,
+                       sn.ntasks, sn.tiles32, sn.blk_col, sn.blk_slot, xc, part, cpart);
+    check_launch("near_gemv32");
+    hipLaunchKernelGGL(k_reduce<float>, dim3(grid_waves(sn.nchunk)), dim3(256), 0, h.stream, A,
+                       static_cast<const float*>(part), static_cast<const float*>(cpart),
+                       reinterpret_cast<float*>(sn.yc), static_cast<float*>(nullptr), 64);
+  }
   check_launch("near_reduce");
 }
 
@@ -748,7 +783,7 @@ void launch_fine_reduce(H2& h, int p, const void* yhat, void* out, bool to_user,
                         const void* add, double beta, const void* xin) {
   const dim3 g(h.nleaf), b(256);
   const int64_t* perm = to_user ? h.perm : nullptr;
-  const bool stored = p == P64 && h.snear.ready;
+  const bool stored = near_stored_for(h, p);
   const double* dg = stored ? nullptr : h.diag;     // stored tiles hold the diagonal
   if (p == P64)
     hipLaunchKernelGGL((k_fine_reduce<double, double>), g, b, 0, h.stream, h.leaf_off,
@@ -763,7 +798,7 @@ void launch_fine_reduce(H2& h, int p, const void* yhat, void* out, bool to_user,
                        h.r, h.near.row_task_ptr, h.near.col_ptr, h.near.col_pair,
                        reinterpret_cast<const float*>(h.near_partial),
                        reinterpret_cast<const float*>(h.near_colpart), h.near.ld,
-                       static_cast<const float*>(nullptr), h.snear.chunk_base, dg,
+                       stored ? reinterpret_cast<const float*>(h.snear.yc) : nullptr, h.snear.chunk_base, dg,
                        static_cast<const float*>(xin), perm, static_cast<float*>(out), alpha,
                        static_cast<const float*>(add), beta);
   else
@@ -772,7 +807,7 @@ void launch_fine_reduce(H2& h, int p, const void* yhat, void* out, bool to_user,
                        h.r, h.near.row_task_ptr, h.near.col_ptr, h.near.col_pair,
                        reinterpret_cast<const float*>(h.near_partial),
                        reinterpret_cast<const float*>(h.near_colpart), h.near.ld,
-                       static_cast<const float*>(nullptr), h.snear.chunk_base, dg,
+                       stored ? reinterpret_cast<const float*>(h.snear.yc) : nullptr, h.snear.chunk_base, dg,
                        static_cast<const float*>(xin), perm, static_cast<float*>(out), alpha,
                        static_cast<const float*>(add), beta);
   check_launch("fine_reduce");

@@ -62,6 +62,40 @@ __global__ __launch_bounds__(NT) void k_bem_panels(int64_t nt, const double* __r
   d[i] = INV_4PI * (edge_term(a, b, g) + edge_term(b, c, g) + edge_term(c, a, g));
 }
 
+// Radon's seven-point rule on triangle i (exact for polynomials of degree
+// <= 5): the centroid with weight 9/40 and the two orbits of barycentric
+// points (a, a, 1 - 2a), a = (6 -+ sqrt 15) / 21, with weights
+// (155 -+ sqrt 15) / 1200; the weights are multiplied by the area w_i and
+// divided by s_i = sqrt(w_i) (the symmetric form's scaling), so
+// u_ip = sqrt(w_i) * rule weight.  qy: 7 points of 3 coordinates.
+__global__ __launch_bounds__(NT) void k_bem_quadrature7(int64_t nt, const double* __restrict__ V,
+                                                        const int64_t* __restrict__ T,
+                                                        double* __restrict__ qy, double* __restrict__ qu) {
+  const int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x;
+  if (i >= nt) return;
+  const V3 a = load(V, T[3 * i]), b = load(V, T[3 * i + 1]), c = load(V, T[3 * i + 2]);
+  const double w = 0.5 * norm(cross(sub(b, a), sub(c, a)));
+  const double sw = sqrt(w);
+  const double r15 = sqrt(15.0);
+  const double orb[2] = {(6.0 - r15) / 21.0, (6.0 + r15) / 21.0};
+  const double wt[2] = {(155.0 - r15) / 1200.0, (155.0 + r15) / 1200.0};
+  double* py = qy + i * 21;
+  double* pu = qu + i * 7;
+  auto put = [&](int k, double la, double lb, double lc, double weight) {
+    py[3 * k] = la * a.x + lb * b.x + lc * c.x;
+    py[3 * k + 1] = la * a.y + lb * b.y + lc * c.y;
+    py[3 * k + 2] = la * a.z + lb * b.z + lc * c.z;
+    pu[k] = sw * weight;
+  };
+  put(0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 3.0, 9.0 / 40.0);
+  for (int o = 0; o < 2; ++o) {
+    const double t = orb[o], u = 1.0 - 2.0 * t;
+    put(1 + 3 * o, u, t, t, wt[o]);
+    put(2 + 3 * o, t, u, t, wt[o]);
+    put(3 + 3 * o, t, t, u, wt[o]);
+  }
+}
+
 __global__ __launch_bounds__(NT) void k_bem_rhs(int64_t n, const double* __restrict__ y,
                                                 double x0, double x1, double x2,
                                                 const double* __restrict__ s, double* __restrict__ f) {
@@ -108,6 +142,13 @@ void launch_bem_panels(hipStream_t st, int64_t nt, const double* V, const int64_
   if (nt == 0) return;
   hipLaunchKernelGGL(k_bem_panels, dim3(blocks(nt)), dim3(NT), 0, st, nt, V, T, y, s, d);
   check_launch("bem_panels");
+}
+
+void launch_bem_quadrature7(hipStream_t st, int64_t nt, const double* V, const int64_t* T, double* qy,
+                            double* qu) {
+  if (nt == 0) return;
+  hipLaunchKernelGGL(k_bem_quadrature7, dim3(blocks(nt)), dim3(NT), 0, st, nt, V, T, qy, qu);
+  check_launch("bem_quadrature7");
 }
 
 void launch_bem_rhs(hipStream_t st, int64_t n, const double* y, const double* x0, const double* s,

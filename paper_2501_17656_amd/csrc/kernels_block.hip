@@ -102,28 +102,35 @@ template <> struct Mfma<float> {
 // writes entry (i, j) through put(i, j, value).  When Stage::PREFETCH, the
 // loads of the next tile are issued as soon as the current one is in LDS, so
 // they overlap its products; the operand rows are loaded before staging.
+// DUAL (MODE_LIST, no column-pass tasks): each staged off-diagonal tile also
+// gives its transposed product B^T X_s, with X_s the task's block-row
+// operand, written as the rr x 16 column contribution of slot rslot[it]
+// (the tile's place among the off-diagonal tiles ordered by column) after
+// the nrt row partials: every tile is read once instead of twice.
 enum { MODE_LIST = 0, MODE_UP = 1, MODE_DOWN = 2 };
 
-template <int T, int MODE, typename Tv, typename Stage>
-__device__ __forceinline__ void tgemm_body(const int* __restrict__ rtask, int nrt,
+template <int T, int MODE, typename Tv, typename Stage, bool DUAL = false>
+__device__ __forceinline__ void tgemm_body(int blk, const int* __restrict__ rtask, int nrt,
                                            const int* __restrict__ rorder,
                                            const int* __restrict__ ctask,
                                            const int* __restrict__ corder,
                                            const int* __restrict__ brow,
                                            const int* __restrict__ bcol, int base, int rr,
                                            const Tv* __restrict__ x, Tv* out_base, const Tv* addend,
-                                           Tv* lds, const Stage& stage) {
+                                           Tv* lds, const Stage& stage,
+                                           const int* __restrict__ rslot = nullptr) {
   constexpr int RP = 8 * T, NKB = RP / 4;
   constexpr int EB = int(sizeof(Tv));
   using M = Mfma<Tv>;
-  const int blk = blockIdx.x;
   bool tr;
   int i0, i1;
   const int* order = nullptr;
   const int* other = nullptr;
+  int task_row = 0;
   if constexpr (MODE == MODE_LIST) {
     tr = blk >= nrt;
     const int* task = tr ? ctask + 3 * (blk - nrt) : rtask + 3 * blk;
+    task_row = task[0];
     order = tr ? corder : rorder;
     other = tr ? brow : bcol;
     i0 = task[1];
@@ -164,6 +171,16 @@ __device__ __forceinline__ void tgemm_body(const int* __restrict__ rtask, int nr
     typename Stage::Regs regs;
     int b = tile_of(i0);
     if constexpr (Stage::PREFETCH) stage.load(b, regs);
+    // DUAL: operand of the transposed products (the task's own block row)
+    Tv xs[DUAL ? NKB : 1];
+    if constexpr (DUAL) {
+      const Tv* xso = x + int64_t(task_row) * rr * NR;
+#pragma unroll
+      for (int kb = 0; kb < NKB; ++kb) {
+        const int kr = 4 * kb + q;
+        xs[kb] = kr < rr ? xso[kr * NR + p] : Tv(0);
+      }
+    }
     for (int it = i0; it < i1; ++it) {
       const int o = other_of(it, b);
       const Tv* xo = x + int64_t(o) * rr * NR;
@@ -184,6 +201,23 @@ __device__ __forceinline__ void tgemm_body(const int* __restrict__ rtask, int nr
 #pragma unroll
       for (int kb = 0; kb < NKB; ++kb)
         if (kb < nkb) mma_step(kb, xr[kb]);
+      if constexpr (DUAL && !TR) {
+        const int slot = rslot[it];
+        if (slot >= 0) {
+          typename M::acc_t at = typename M::acc_t{Tv(0), Tv(0), Tv(0), Tv(0)};
+#pragma unroll
+          for (int kb = 0; kb < NKB; ++kb) {
+            const int kr = 4 * kb + q;
+            if (kb < nkb) at = M::mma(lds[kr * RP + (slab ^ swz<RP, EB>(kr))], xs[kb], at);
+          }
+          Tv* oc = out_base + int64_t(nrt + slot) * rr * NR;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int row = 16 * w + M::row(t, q);
+            if (row < rr) oc[row * NR + p] = at[t];
+          }
+        }
+      }
     }
   };
   if (tr) run(std::integral_constant<bool, true>{});
@@ -242,7 +276,7 @@ struct StageStored {
   }
 };
 
-template <int T, typename Te, typename Tv>
+template <int T, typename Te, typename Tv, bool DUAL>
 __global__ __launch_bounds__(32 * T) void k_tgemm(const int* __restrict__ rtask, int nrt,
                                                   const int* __restrict__ rorder,
                                                   const int* __restrict__ ctask,
@@ -250,10 +284,12 @@ __global__ __launch_bounds__(32 * T) void k_tgemm(const int* __restrict__ rtask,
                                                   const Te* __restrict__ tiles,
                                                   const int* __restrict__ brow,
                                                   const int* __restrict__ bcol, int rr,
-                                                  const Tv* __restrict__ x, Tv* __restrict__ partial) {
+                                                  const Tv* __restrict__ x, Tv* __restrict__ partial,
+                                                  const int* __restrict__ rslot) {
   __shared__ Tv lds[64 * T * T];
-  tgemm_body<T, MODE_LIST>(rtask, nrt, rorder, ctask, corder, brow, bcol, 0, rr, x, partial,
-                           static_cast<const Tv*>(nullptr), lds, StageStored<T, Te, Tv>{tiles});
+  tgemm_body<T, MODE_LIST, Tv, StageStored<T, Te, Tv>, DUAL>(
+      blockIdx.x, rtask, nrt, rorder, ctask, corder, brow, bcol, 0, rr, x, partial,
+      static_cast<const Tv*>(nullptr), lds, StageStored<T, Te, Tv>{tiles}, rslot);
 }
 
 // Transfers between depth d + 1 (children, gids base + c) and depth d.
@@ -261,8 +297,8 @@ template <int T, int MODE, typename Te, typename Tv>
 __global__ __launch_bounds__(32 * T) void k_transfer16(const Te* __restrict__ E, int base, int r,
                                                        const Tv* __restrict__ x, Tv* out, const Tv* addend) {
   __shared__ Tv lds[64 * T * T];
-  tgemm_body<T, MODE>(nullptr, 0, nullptr, nullptr, nullptr, nullptr, nullptr, base, r, x, out, addend, lds,
-                      StageStored<T, Te, Tv>{E});
+  tgemm_body<T, MODE>(blockIdx.x, nullptr, 0, nullptr, nullptr, nullptr, nullptr, nullptr, base, r, x, out,
+                      addend, lds, StageStored<T, Te, Tv>{E});
 }
 
 // Near-field tiles evaluated from the points: lane (a, b) of wave w
@@ -332,7 +368,7 @@ struct StageEval {
 // kernel s_i k(|p_i - p_j|) s_j plus the diagonal (the per-point d, else the
 // shift) where a point meets itself, zero outside the chunks.  Coordinate
 // differences are formed in FP64, the rest in the vector precision.
-template <typename Tv, int KIND, int DERIV>
+template <typename Tv, int KIND, int DERIV, bool DUAL>
 __global__ __launch_bounds__(256) void k_tgemm_eval(const int* __restrict__ rtask, int nrt,
                                                     const int* __restrict__ rorder,
                                                     const int* __restrict__ ctask,
@@ -343,11 +379,42 @@ __global__ __launch_bounds__(256) void k_tgemm_eval(const int* __restrict__ rtas
                                                     const int* __restrict__ chunk_n,
                                                     const double* __restrict__ pts, int dim,
                                                     KernelParams kp, PointScale ps,
-                                                    const Tv* __restrict__ x, Tv* __restrict__ partial) {
+                                                    const Tv* __restrict__ x, Tv* __restrict__ partial,
+                                                    const int* __restrict__ rslot) {
   __shared__ Tv lds[64 * 64];
-  tgemm_body<8, MODE_LIST>(rtask, nrt, rorder, ctask, corder, brow, bcol, 0, 64, x, partial,
-                           static_cast<const Tv*>(nullptr), lds,
-                           StageEval<Tv, KIND, DERIV>{brow, bcol, chunk_start, chunk_n, pts, dim, kp, ps});
+  tgemm_body<8, MODE_LIST, Tv, StageEval<Tv, KIND, DERIV>, DUAL>(
+      blockIdx.x, rtask, nrt, rorder, ctask, corder, brow, bcol, 0, 64, x, partial,
+      static_cast<const Tv*>(nullptr), lds,
+      StageEval<Tv, KIND, DERIV>{brow, bcol, chunk_start, chunk_n, pts, dim, kp, ps}, rslot);
+}
+
+// ------------------------------------------------------------ several problems in one launch
+// The tile products of up to GROUP_MAX independent problems in one grid:
+// member m owns the blocks [start[m], start[m + 1]) and runs them exactly as
+// its own launch would (same tasks, same per-block arithmetic), so each
+// problem's partial sums are bit for bit those of a launch of its own.
+template <int T, typename Te, typename Tv, bool DUAL>
+__global__ __launch_bounds__(32 * T) void k_tgemm_group(TgemmGroup G) {
+  __shared__ Tv lds[64 * T * T];
+  int m = 0;
+  while (m + 1 < G.n && G.start[m + 1] <= int(blockIdx.x)) ++m;
+  const TgemmMember& M = G.m[m];
+  tgemm_body<T, MODE_LIST, Tv, StageStored<T, Te, Tv>, DUAL>(
+      int(blockIdx.x) - G.start[m], M.rtask, M.nrt, M.rorder, M.ctask, M.corder, M.brow, M.bcol, 0, M.rr,
+      static_cast<const Tv*>(M.x), static_cast<Tv*>(M.partial), static_cast<const Tv*>(nullptr), lds,
+      StageStored<T, Te, Tv>{static_cast<const Te*>(M.tiles)}, M.rslot);
+}
+
+template <typename Tv, int KIND, int DERIV, bool DUAL>
+__global__ __launch_bounds__(256) void k_tgemm_eval_group(TevalGroup G) {
+  __shared__ Tv lds[64 * 64];
+  int m = 0;
+  while (m + 1 < G.n && G.start[m + 1] <= int(blockIdx.x)) ++m;
+  const TevalMember& M = G.m[m];
+  tgemm_body<8, MODE_LIST, Tv, StageEval<Tv, KIND, DERIV>, DUAL>(
+      int(blockIdx.x) - G.start[m], M.rtask, M.nrt, M.rorder, M.ctask, M.corder, M.brow, M.bcol, 0, 64,
+      static_cast<const Tv*>(M.x), static_cast<Tv*>(M.partial), static_cast<const Tv*>(nullptr), lds,
+      StageEval<Tv, KIND, DERIV>{M.brow, M.bcol, M.chunk_start, M.chunk_n, M.pts, M.dim, M.kp, M.ps}, M.rslot);
 }
 
 // out[row] (rr x 16) = the row-pass partials [rtp[row], rtp[row+1]) plus the
@@ -658,6 +725,12 @@ int parts16(int64_t nrows) {
   return int(b < 1 ? 1 : b > 256 ? 256 : b);
 }
 
+template <typename F>
+void dispatch_dual(bool dual, F&& f) {
+  if (dual) f(std::true_type{});
+  else f(std::false_type{});
+}
+
 void launch_tgemm(H2& h, int tp, int T, const TileSet& ts, const void* tiles, int rr, const void* x,
                   void* partial) {
   const int nb = ts.nrt + ts.nct;
@@ -667,9 +740,12 @@ void launch_tgemm(H2& h, int tp, int T, const TileSet& ts, const void* tiles, in
     dispatch_prec(tp, [&](auto tv, auto te) {
       using Tv = decltype(tv);
       using Te = decltype(te);
-      hipLaunchKernelGGL((k_tgemm<TT, Te, Tv>), dim3(nb), dim3(32 * TT), 0, h.stream, ts.rtask, ts.nrt,
-                         ts.rorder, ts.ctask, ts.corder, static_cast<const Te*>(tiles), ts.brow, ts.bcol,
-                         rr, static_cast<const Tv*>(x), static_cast<Tv*>(partial));
+      dispatch_dual(ts.dual, [&](auto dc) {
+        constexpr bool D = decltype(dc)::value;
+        hipLaunchKernelGGL((k_tgemm<TT, Te, Tv, D>), dim3(nb), dim3(32 * TT), 0, h.stream, ts.rtask, ts.nrt,
+                           ts.rorder, ts.ctask, ts.corder, static_cast<const Te*>(tiles), ts.brow, ts.bcol,
+                           rr, static_cast<const Tv*>(x), static_cast<Tv*>(partial), ts.rslot);
+      });
     });
   });
   check_launch("tgemm");
@@ -678,20 +754,109 @@ void launch_tgemm(H2& h, int tp, int T, const TileSet& ts, const void* tiles, in
 void launch_tgemm_eval(H2& h, int p, const TileSet& ts, const void* x, void* partial) {
   const int nb = ts.nrt + ts.nct;
   if (nb == 0) return;
+  if (h.nq > 0) throw std::runtime_error("close entries by quadrature are applied from the stored tiles only");
   const StoredNear& sn = h.snear;
-  const PointScale ps{h.scale, h.diag};
+  const PointScale ps{h.scale, h.diag, nullptr, nullptr, 0};
   dispatch_kernel(h.kp.kind, h.kp.deriv, [&](auto kc, auto dc) {
     constexpr int KIND = decltype(kc)::value, DERIV = decltype(dc)::value;
-    if (p == P64)
-      hipLaunchKernelGGL((k_tgemm_eval<double, KIND, DERIV>), dim3(nb), dim3(256), 0, h.stream, ts.rtask, ts.nrt,
-                         ts.rorder, ts.ctask, ts.corder, ts.brow, ts.bcol, sn.chunk_start, sn.chunk_n, h.pts,
-                         h.dim, h.kp, ps, static_cast<const double*>(x), static_cast<double*>(partial));
-    else
-      hipLaunchKernelGGL((k_tgemm_eval<float, KIND, DERIV>), dim3(nb), dim3(256), 0, h.stream, ts.rtask, ts.nrt,
-                         ts.rorder, ts.ctask, ts.corder, ts.brow, ts.bcol, sn.chunk_start, sn.chunk_n, h.pts,
-                         h.dim, h.kp, ps, static_cast<const float*>(x), static_cast<float*>(partial));
+    dispatch_dual(ts.dual, [&](auto duc) {
+      constexpr bool D = decltype(duc)::value;
+      if (p == P64)
+        hipLaunchKernelGGL((k_tgemm_eval<double, KIND, DERIV, D>), dim3(nb), dim3(256), 0, h.stream, ts.rtask,
+                           ts.nrt, ts.rorder, ts.ctask, ts.corder, ts.brow, ts.bcol, sn.chunk_start, sn.chunk_n,
+                           h.pts, h.dim, h.kp, ps, static_cast<const double*>(x), static_cast<double*>(partial),
+                           ts.rslot);
+      else
+        hipLaunchKernelGGL((k_tgemm_eval<float, KIND, DERIV, D>), dim3(nb), dim3(256), 0, h.stream, ts.rtask,
+                           ts.nrt, ts.rorder, ts.ctask, ts.corder, ts.brow, ts.bcol, sn.chunk_start, sn.chunk_n,
+                           h.pts, h.dim, h.kp, ps, static_cast<const float*>(x), static_cast<float*>(partial),
+                           ts.rslot);
+    });
   });
   check_launch("tgemm_eval");
+}
+
+void launch_tgemm_group(hipStream_t st, int tp, const std::vector<GroupTiles>& items) {
+  // one launch per tile width and pass form, at most GROUP_MAX members each
+  for (int T : {2, 4, 8})
+    for (bool dual : {false, true}) {
+      std::vector<const GroupTiles*> sel;
+      for (const GroupTiles& it : items)
+        if (it.T == T && it.ts->dual == dual && it.ts->nrt + it.ts->nct > 0) sel.push_back(&it);
+      for (size_t c0 = 0; c0 < sel.size(); c0 += GROUP_MAX) {
+        TgemmGroup G{};
+        G.n = int(std::min<size_t>(GROUP_MAX, sel.size() - c0));
+        int64_t total = 0;
+        for (int m = 0; m < G.n; ++m) {
+          const GroupTiles& it = *sel[c0 + m];
+          G.start[m] = int(total);
+          G.m[m] = TgemmMember{it.ts->rtask, it.ts->rorder, it.ts->ctask, it.ts->corder, it.tiles, it.ts->brow,
+                               it.ts->bcol, it.x, it.partial, it.ts->rslot, it.ts->nrt, it.rr};
+          total += it.ts->nrt + it.ts->nct;
+        }
+        G.start[G.n] = int(total);
+        if (total > INT32_MAX) throw std::runtime_error("tile-product group grid too large");
+        dispatch_T16(T, [&](auto Tc) {
+          constexpr int TT = decltype(Tc)::value;
+          dispatch_prec(tp, [&](auto tv, auto te) {
+            using Tv = decltype(tv);
+            using Te = decltype(te);
+            dispatch_dual(dual, [&](auto dc) {
+              constexpr bool D = decltype(dc)::value;
+              hipLaunchKernelGGL((k_tgemm_group<TT, Te, Tv, D>), dim3(unsigned(total)), dim3(32 * TT), 0, st, G);
+            });
+          });
+        });
+        check_launch("tgemm_group");
+      }
+    }
+}
+
+void launch_tgemm_eval_group(hipStream_t st, int p, const std::vector<GroupEval>& items) {
+  // one launch per kernel family and pass form, at most GROUP_MAX members each
+  std::vector<bool> done(items.size(), false);
+  for (size_t i0 = 0; i0 < items.size(); ++i0) {
+    if (done[i0]) continue;
+    std::vector<const GroupEval*> sel;
+    if (items[i0].h->nq > 0)
+      throw std::runtime_error("close entries by quadrature are applied from the stored tiles only");
+    const bool dual = items[i0].ts->dual;
+    for (size_t i = i0; i < items.size(); ++i)
+      if (!done[i] && items[i].h->kp.kind == items[i0].h->kp.kind && items[i].h->kp.deriv == items[i0].h->kp.deriv &&
+          items[i].ts->dual == dual) {
+        done[i] = true;
+        if (items[i].ts->nrt + items[i].ts->nct > 0) sel.push_back(&items[i]);
+      }
+    for (size_t c0 = 0; c0 < sel.size(); c0 += GROUP_MAX) {
+      TevalGroup G{};
+      G.n = int(std::min<size_t>(GROUP_MAX, sel.size() - c0));
+      int64_t total = 0;
+      for (int m = 0; m < G.n; ++m) {
+        const GroupEval& it = *sel[c0 + m];
+        const H2& h = *it.h;
+        G.start[m] = int(total);
+        G.m[m] = TevalMember{it.ts->rtask, it.ts->rorder, it.ts->ctask, it.ts->corder, it.ts->brow, it.ts->bcol,
+                             h.snear.chunk_start, h.snear.chunk_n, h.pts, it.x, it.partial, it.ts->rslot,
+                             PointScale{h.scale, h.diag, nullptr, nullptr, 0}, h.kp, it.ts->nrt, h.dim};
+        total += it.ts->nrt + it.ts->nct;
+      }
+      G.start[G.n] = int(total);
+      if (total > INT32_MAX) throw std::runtime_error("near-field group grid too large");
+      dispatch_kernel(sel[c0]->h->kp.kind, sel[c0]->h->kp.deriv, [&](auto kc, auto dc) {
+        constexpr int KIND = decltype(kc)::value, DERIV = decltype(dc)::value;
+        dispatch_dual(dual, [&](auto duc) {
+          constexpr bool D = decltype(duc)::value;
+          if (p == P64)
+            hipLaunchKernelGGL((k_tgemm_eval_group<double, KIND, DERIV, D>), dim3(unsigned(total)), dim3(256), 0,
+                               st, G);
+          else
+            hipLaunchKernelGGL((k_tgemm_eval_group<float, KIND, DERIV, D>), dim3(unsigned(total)), dim3(256), 0,
+                               st, G);
+        });
+      });
+      check_launch("tgemm_eval_group");
+    }
+  }
 }
 
 void launch_reduce16(H2& h, int p, const TileSet& ts, int rr, const void* partial, void* out) {

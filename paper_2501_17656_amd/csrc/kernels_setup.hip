@@ -348,7 +348,7 @@ __global__ __launch_bounds__(NT) void k_pi_leaf(
           const double dx = pi[a] - pt[j * dim + a];
           r2 += dx * dx;
         }
-        const double k = scaled_entry(kernel_r2(kp, r2), s0 + i, t0 + j, diag && i == j, ps, kp.shift);
+        const double k = near_entry(kp, ps, dim, r2, s0 + i, t0 + j, diag && i == j);
         const double* qrow = Qr + size_t(t0 + j) * r + c0;
 #pragma unroll
         for (int q = 0; q < 32; ++q)
@@ -453,7 +453,7 @@ __global__ __launch_bounds__(NT) void k_assemble_kernel_dense(
     const double dx = pts[i * dim + a] - pts[j * dim + a];
     r2 += dx * dx;
   }
-  A[i + j * n] = scaled_entry(kernel_r2(kp, r2), i, j, i == j, ps, kp.shift);
+  A[i + j * n] = near_entry(kp, ps, dim, r2, i, j, i == j);
 }
 
 // ------------------------------------------------------------ Cholesky (lower, blocked)
@@ -590,7 +590,7 @@ __global__ __launch_bounds__(NT) void k_bj_inv_fine(const int* __restrict__ leaf
       const double dx = pts[int64_t(s0 + i) * dim + a] - pts[int64_t(s0 + j) * dim + a];
       r2 += dx * dx;
     }
-    A[idx] = scaled_entry(kernel_r2(kp, r2), s0 + i, s0 + j, i == j, ps, kp.shift);
+    A[idx] = near_entry(kp, ps, dim, r2, s0 + i, s0 + j, i == j);
   }
   gauss_jordan_spd(A, n, fk, flag);
   double* o = out + int64_t(leaf) * ld * ld;
@@ -678,8 +678,8 @@ __global__ __launch_bounds__(NT) void k_near_tiles(int64_t nblocks, const int* _
         const double dx = pi[u][q] - pj[v0 + w][q];
         r2 += dx * dx;
       }
-      const double k = scaled_entry(kernel_r2(kp, r2), s0 + min(i, ns - 1), t0 + min(j, nt - 1),
-                                    cs == ct && i == j, ps, kp.shift);
+      const double k = near_entry(kp, ps, dim, r2, s0 + min(i, ns - 1), t0 + min(j, nt - 1),
+                                  cs == ct && i == j);
       val[w] = (i < ns && j < nt) ? k : 0.0;
     }
     double2 out;
@@ -737,8 +737,32 @@ void launch_near_tiles(H2& h) {
   const int64_t groups = (sn.nblocks + 3) / 4;
   hipLaunchKernelGGL(k_near_tiles, dim3(unsigned(groups)), dim3(NT), 0, h.stream, sn.nblocks,
                      sn.blk_row, sn.blk_col, sn.chunk_start, sn.chunk_n, h.pts, h.dim, h.kp,
-                     PointScale{h.scale, h.diag}, sn.tiles);
+                     near_scale(h), sn.tiles);
   check_launch("near_tiles");
+}
+
+void launch_cast_near_tiles(H2& h) {
+  StoredNear& sn = h.snear;
+  if (sn.nblocks == 0) return;
+  hipLaunchKernelGGL(k_cast_tiles<float>, dim3(unsigned(sn.nblocks)), dim3(NT), 0, h.stream, sn.tiles,
+                     sn.tiles32, int64_t(0), 64, 8);
+  check_launch("cast_near_tiles");
+}
+
+__global__ __launch_bounds__(NT) void k_gather_rows(int64_t n, int width, const int64_t* __restrict__ perm,
+                                                    const double* __restrict__ user, double* __restrict__ tree) {
+  const int64_t idx = int64_t(blockIdx.x) * NT + threadIdx.x;
+  if (idx >= n * width) return;
+  const int64_t i = idx / width, c = idx % width;
+  tree[idx] = user[perm[i] * width + c];
+}
+
+void launch_gather_rows(H2& h, int width, const double* user, double* tree) {
+  const int64_t total = int64_t(h.n) * width;
+  if (total == 0) return;
+  hipLaunchKernelGGL(k_gather_rows, dim3(unsigned((total + NT - 1) / NT)), dim3(NT), 0, h.stream, int64_t(h.n),
+                     width, h.perm, user, tree);
+  check_launch("gather_rows");
 }
 
 void launch_pi_leaf(H2& h) {
@@ -747,7 +771,7 @@ void launch_pi_leaf(H2& h) {
   allow_lds(k_pi_leaf, lds);
   hipLaunchKernelGGL(k_pi_leaf, dim3(h.p_count[h.L]), dim3(NT), lds, h.stream, h.p_first[h.L],
                      h.blk_row, h.blk_col, h.nleaf - 1, h.leaf_off, h.pts, h.dim, h.r, h.T, h.kp,
-                     PointScale{h.scale, h.diag}, static_cast<const double*>(h.prec[P64].Qr),
+                     near_scale(h), static_cast<const double*>(h.prec[P64].Qr),
                      static_cast<double*>(h.prec[P64].blk));
   check_launch("pi_leaf");
 }
@@ -779,7 +803,7 @@ void launch_assemble_dense(H2& h, double* A, int64_t lda) {
 void launch_assemble_kernel_dense(H2& h, double* A, int64_t lda) {
   const int64_t nn = int64_t(h.n) * h.n;
   hipLaunchKernelGGL(k_assemble_kernel_dense, dim3((nn + NT - 1) / NT), dim3(NT), 0, h.stream,
-                     h.pts, h.dim, int64_t(h.n), h.kp, PointScale{h.scale, h.diag}, A);
+                     h.pts, h.dim, int64_t(h.n), h.kp, near_scale(h), A);
   (void)lda;
   check_launch("assemble_kernel_dense");
 }
@@ -804,7 +828,7 @@ void launch_bj_inverse_fine(H2& h, double* out, int ld) {
   const size_t lds = (size_t(n) * n + n) * sizeof(double);
   allow_lds(k_bj_inv_fine, lds);
   hipLaunchKernelGGL(k_bj_inv_fine, dim3(h.nleaf), dim3(NT), lds, h.stream, h.leaf_off, h.pts,
-                     h.dim, h.kp, PointScale{h.scale, h.diag}, out, ld, h.flags);
+                     h.dim, h.kp, near_scale(h), out, ld, h.flags);
   check_launch("bj_inv_fine");
 }
 

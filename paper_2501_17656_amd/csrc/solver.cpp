@@ -41,40 +41,61 @@ struct Work {
   double* dpart = nullptr;
 };
 
-Work make_work(H2& h, int p, bool second_corrections = false) {
+// Where a solve's vectors come from: the handle's allocator.
+struct VecSource {
+  H2* h = nullptr;
+  void* get(size_t bytes) { return h->arena.alloc(bytes); }
+  void put(void* p) {
+    if (p) h->arena.release(p);
+  }
+};
+
+Work make_work(H2& h, int p, bool second_corrections, VecSource& src) {
   Work w;
   const size_t vb = vbytes(p);
   w.r.resize(h.levels + 1);
   w.et.resize(h.levels + 1);
   w.ec.assign(h.levels + 1, nullptr);
   for (int k = 1; k <= h.levels; ++k) {
-    w.r[k] = h.arena.alloc(size_t(h.level_size(k)) * vb);
-    w.et[k] = h.arena.alloc(size_t(h.level_size(k)) * vb);
+    w.r[k] = src.get(size_t(h.level_size(k)) * vb);
+    w.et[k] = src.get(size_t(h.level_size(k)) * vb);
     if (second_corrections && k >= 2 && k < h.levels)
-      w.ec[k] = h.arena.alloc(size_t(h.level_size(k)) * vb);
+      w.ec[k] = src.get(size_t(h.level_size(k)) * vb);
   }
-  w.s = h.arena.alloc(size_t(h.n) * vb);
-  w.pv = h.arena.alloc(size_t(h.n) * vb);
-  w.q = h.arena.alloc(size_t(h.n) * vb);
-  w.tmp = h.arena.alloc(size_t(h.n) * vb);
-  w.z = h.arena.alloc(size_t(h.n) * vb);
+  w.s = src.get(size_t(h.n) * vb);
+  w.pv = src.get(size_t(h.n) * vb);
+  w.q = src.get(size_t(h.n) * vb);
+  w.tmp = src.get(size_t(h.n) * vb);
+  w.z = src.get(size_t(h.n) * vb);
   w.gpart[0] = h.dot_part + 512;
   w.gpart[1] = h.dot_part + 1024;
   w.dpart = h.dot_part + 1536;
   return w;
 }
 
-void release_work(H2& h, Work& w) {
+Work make_work(H2& h, int p, bool second_corrections = false) {
+  VecSource src;
+  src.h = &h;
+  return make_work(h, p, second_corrections, src);
+}
+
+void release_work(H2& h, Work& w, VecSource& src) {
   for (int k = 1; k <= h.levels; ++k) {
-    h.arena.release(w.r[k]);
-    h.arena.release(w.et[k]);
-    if (w.ec[k]) h.arena.release(w.ec[k]);
+    src.put(w.r[k]);
+    src.put(w.et[k]);
+    src.put(w.ec[k]);
   }
-  h.arena.release(w.s);
-  h.arena.release(w.pv);
-  h.arena.release(w.q);
-  h.arena.release(w.tmp);
-  h.arena.release(w.z);
+  src.put(w.s);
+  src.put(w.pv);
+  src.put(w.q);
+  src.put(w.tmp);
+  src.put(w.z);
+}
+
+void release_work(H2& h, Work& w) {
+  VecSource src;
+  src.h = &h;
+  release_work(h, w, src);
 }
 
 void zero(H2& h, void* v, int64_t n, int p) { launch_zero(h, p, v, n); }
@@ -305,15 +326,19 @@ h2mg_status ensure_block_jacobi(H2& h, int p) {
   return H2MG_OK;
 }
 
-h2mg_status solve(H2& h, const double* b, double* x, const SolveParams& sp, h2mg_solve_info* info) {
+namespace {
+
+// The solve (arena vectors, optional graphs).
+h2mg_status solve_impl(H2& h, const double* b, double* x, const SolveParams& sp, h2mg_solve_info* info) {
   const auto t0 = std::chrono::steady_clock::now();
   h.history.clear();
   const int p = sp.precision == 0 ? P64 : sp.precision == 1 ? P32 : P16;
   const bool plain = sp.method == 3;
   if (plain && p != P64) return fail(H2MG_ERR_INVALID_ARG, "CG on A_H2 alone runs in FP64 only");
+  const bool need_mg = !(plain && sp.smoother == 0);
   // plain CG needs the hierarchy only for the block-Jacobi inverses, which
   // are formed for all levels together
-  h2mg_status st = plain && sp.smoother == 0 ? H2MG_OK : setup_mg(h, p == P64 ? 0 : (1 << p));
+  h2mg_status st = need_mg ? setup_mg(h, p == P64 ? 0 : (1 << p)) : H2MG_OK;
   if (st != H2MG_OK) return st;
   if (sp.smoother == 1) {
     try {
@@ -325,6 +350,10 @@ h2mg_status solve(H2& h, const double* b, double* x, const SolveParams& sp, h2mg
     }
     if (st != H2MG_OK) return st;
   }
+  const bool second = sp.method == CYCLE_W || sp.method == CYCLE_F;
+  const int64_t n = h.n;
+  VecSource src;
+  src.h = &h;
   Work w64, wlp;
   bool have_lp = false;
   h2mg_status result = H2MG_OK;
@@ -332,18 +361,22 @@ h2mg_status solve(H2& h, const double* b, double* x, const SolveParams& sp, h2mg
   bool converged = false;
   double rel = 0.0;
   try {
-    const bool second = sp.method == CYCLE_W || sp.method == CYCLE_F;
-    w64 = make_work(h, P64, second && p == P64);
+    w64 = make_work(h, P64, second && p == P64, src);
     w64.smoother = sp.smoother;
     if (p != P64) {
-      wlp = make_work(h, p, second);
+      wlp = make_work(h, p, second, src);
       wlp.smoother = sp.smoother;
       have_lp = true;
     }
-    const int64_t n = h.n;
-    double* bt = static_cast<double*>(h.arena.alloc(size_t(n) * 8));
-    double* xt = static_cast<double*>(h.arena.alloc(size_t(n) * 8));
+    double* bt = static_cast<double*>(src.get(size_t(n) * 8));
+    double* xt = static_cast<double*>(src.get(size_t(n) * 8));
     double* res = static_cast<double*>(w64.r[1]);
+    auto release_all = [&]() {
+      src.put(bt);
+      src.put(xt);
+      release_work(h, w64, src);
+      if (have_lp) release_work(h, wlp, src);
+    };
     launch_gather(h, b, bt);
     if (sp.use_x0) launch_gather(h, x, xt);
     else zero(h, xt, n, P64);
@@ -352,10 +385,7 @@ h2mg_status solve(H2& h, const double* b, double* x, const SolveParams& sp, h2mg
     int f[4];
     read_flags(h, f);
     if (f[1]) {
-      h.arena.release(bt);
-      h.arena.release(xt);
-      release_work(h, w64);
-      if (have_lp) release_work(h, wlp);
+      release_all();
       return fail(H2MG_ERR_INVALID_ARG, "b contains a non-finite value");
     }
     const double nb = host_norm(h, bt, n);
@@ -411,10 +441,7 @@ h2mg_status solve(H2& h, const double* b, double* x, const SolveParams& sp, h2mg
     }
     launch_scatter(h, xt, x);
     hip_check(hipStreamSynchronize(h.stream), "solve");
-    h.arena.release(bt);
-    h.arena.release(xt);
-    release_work(h, w64);
-    if (have_lp) release_work(h, wlp);
+    release_all();
   } catch (const std::bad_alloc&) {
     return fail(H2MG_ERR_OOM, "device allocation failed in the solve");
   } catch (const std::exception& ex) {
@@ -429,6 +456,12 @@ h2mg_status solve(H2& h, const double* b, double* x, const SolveParams& sp, h2mg
     info->history_len = int(h.history.size());
   }
   return result;
+}
+
+}  // namespace
+
+h2mg_status solve(H2& h, const double* b, double* x, const SolveParams& sp, h2mg_solve_info* info) {
+  return solve_impl(h, b, x, sp, info);
 }
 
 h2mg_status smooth_once(H2& h, int level, const double* r, double* e, int nsteps, int smoother,

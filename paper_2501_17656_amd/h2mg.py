@@ -164,6 +164,17 @@ class H2Matrix:
         check(lib().h2mg_matvec_multi(self._h, nrhs, xp, nrhs, yp, nrhs, _stream()))
         return Y
 
+    def set_near_quadrature(self, qy, qu) -> None:
+        """Close entries by quadrature: qy (n, nq, dim) sub-points and qu (n, nq)
+        weights per point (float64, GPU, user order); stores the near field."""
+        if qy.dim() != 3 or qy.shape[0] != self.n or qy.shape[2] != self.dim:
+            raise ValueError("qy must have shape (n, nq, dim)")
+        nq = int(qy.shape[1])
+        if tuple(qu.shape) != (self.n, nq):
+            raise ValueError(f"qu must have shape ({self.n}, {nq})")
+        check(lib().h2mg_set_near_quadrature(self._h, _dev_f64(qy, name="qy"), _dev_f64(qu, name="qu"), nq,
+                                             _stream()))
+
     def store_near(self, enable: bool = True) -> None:
         """Store the close leaf blocks as FP64 tiles (enable) or release them;
         FP64 fine-level products then stream the tiles."""
@@ -242,16 +253,23 @@ class H2Matrix:
 
     def solve(self, b, rtol: float = 1e-8, n_fine: int = 1, n_coarse: int = 40,
               max_cycles: int = 500, precision: str = "fp64", x0=None, raise_on_error: bool = True,
-              smoother: str = "cg", method: str = "v"):
+              smoother: str = "cg", method: str = "v", out=None):
         """Solve A_H2 x = b by V-, W- or F-cycles, or by CG alone (method
-        "cg"; max_cycles then counts CG iterations).  Returns (x, info)."""
+        "cg"; max_cycles then counts CG iterations).  Returns (x, info).
+        out: write x there (with x0, out holds the initial guess on entry)."""
         import torch
-        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        if out is None:
+            x = torch.zeros_like(b) if x0 is None else x0.clone()
+        else:
+            x = out
+            if x0 is not None and x0.data_ptr() != out.data_ptr():
+                x.copy_(x0)
         o = self._opts(rtol, n_fine, n_coarse, max_cycles, precision, x0 is not None, smoother,
                        method)
         info = _lib.SolveInfo()
-        st = lib().h2mg_solve(self._h, _dev_f64(b, self.n, "b"), _dev_f64(x, self.n, "x"),
-                              ctypes.byref(o), ctypes.byref(info), _stream())
+        fn = lib().h2mg_solve
+        st = fn(self._h, _dev_f64(b, self.n, "b"), _dev_f64(x, self.n, "x"),
+                ctypes.byref(o), ctypes.byref(info), _stream())
         msg = _lib.last_error() if st != 0 else ""
         out = _info_dict(self, info, st, msg)
         if st != 0 and raise_on_error:
@@ -324,6 +342,13 @@ class H2Matrix:
                                       ctypes.byref(ms), ctypes.byref(work)))
         return {"launches": n.value, "ms": ms.value, "work": work.value}
 
+    def gemv_launch_info(self, level: int) -> dict:
+        """Waves and stored blocks of the block-GEMV launch of level `level`'s
+        product (1: the fine couplings)."""
+        t, b = ctypes.c_int64(), ctypes.c_int64()
+        check(lib().h2mg_gemv_launch_info(self._h, level, ctypes.byref(t), ctypes.byref(b)))
+        return {"tasks": t.value, "blocks": b.value, "grid": (t.value + 3) // 4}
+
     def memory_bytes(self) -> int:
         v = ctypes.c_int64()
         check(lib().h2mg_memory_bytes(self._h, ctypes.byref(v)))
@@ -343,10 +368,15 @@ class H2Matrix:
 
 def solve_batch(problems, rtol: float = 1e-8, n_fine: int = 1, n_coarse: int = 40, max_cycles: int = 500,
                 precision: str = "fp64", smoother: str = "cg", method: str = "v", nstreams: int = 0,
-                raise_on_error: bool = True):
+                raise_on_error: bool = True, mode: str = "streams"):
     """Solve independent problems together: `problems` is a list of
     (H2Matrix, B) with B of shape (n_i, nrhs_i), nrhs_i <= 16 (distinct
-    matrices).  Returns (list of X, list of info dicts)."""
+    matrices).  mode "streams": each problem on one of `nstreams` streams
+    (h2mg_solve_batch); "group": all problems cycle together and every tile
+    product step is one launch over all of them (h2mg_solve_group).
+    Returns (list of X, list of info dicts)."""
+    if mode not in ("streams", "group"):
+        raise ValueError(f"unknown mode {mode!r}")
     import torch
     k = len(problems)
     hs = (ctypes.c_void_p * k)()
@@ -366,8 +396,11 @@ def solve_batch(problems, rtol: float = 1e-8, n_fine: int = 1, n_coarse: int = 4
     o = H2Matrix._opts(rtol, n_fine, n_coarse, max_cycles, precision, 0, smoother, method)
     infos = (_lib.SolveInfo * k)()
     stats = (ctypes.c_int32 * k)()
-    st = lib().h2mg_solve_batch(k, hs, nr, bp, nr, xp, nr, ctypes.byref(o), infos, stats, int(nstreams),
-                                _stream())
+    if mode == "group":
+        st = lib().h2mg_solve_group(k, hs, nr, bp, nr, xp, nr, ctypes.byref(o), infos, stats, _stream())
+    else:
+        st = lib().h2mg_solve_batch(k, hs, nr, bp, nr, xp, nr, ctypes.byref(o), infos, stats, int(nstreams),
+                                    _stream())
     msg = _lib.last_error() if st != 0 else ""
     out = [_info_dict(g, infos[i], stats[i], msg if stats[i] else "") for i, (g, _) in enumerate(problems)]
     if st != 0 and raise_on_error:
@@ -376,6 +409,21 @@ def solve_batch(problems, rtol: float = 1e-8, n_fine: int = 1, n_coarse: int = 4
 
 
 # ---------------------------------------------------------------- boundary elements
+def bem_quadrature7(vertices, triangles):
+    """Radon's seven-point rule per triangle: points (nt, 7, 3) and weights
+    times sqrt(area) (nt, 7), for H2Matrix.set_near_quadrature."""
+    import torch
+    nt = int(triangles.shape[0])
+    if triangles.dtype != torch.int64 or not triangles.is_cuda or not triangles.is_contiguous():
+        raise TypeError("triangles must be a contiguous int64 tensor on the GPU")
+    qy = torch.empty((nt, 7, 3), dtype=torch.float64, device=vertices.device)
+    qu = torch.empty((nt, 7), dtype=torch.float64, device=vertices.device)
+    check(lib().h2mg_bem_quadrature7(_dev_f64(vertices), int(vertices.shape[0]),
+                                     ctypes.c_void_p(triangles.data_ptr()), nt, _dev_f64(qy), _dev_f64(qu),
+                                     _stream()))
+    return qy, qu
+
+
 def bem_panels(vertices, triangles):
     """Centroids (nt x 3), scale sqrt(area) and diagonal I_i / (4 pi) of a
     triangle mesh (device float64 vertices nv x 3, int64 triangles nt x 3)."""

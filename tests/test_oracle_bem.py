@@ -224,3 +224,106 @@ def test_point_source_rhs_mean_value_property():
     y = x0 + np.array([[1.0, 0, 0], [2.0, 0, 0], [0, 0, 4.0]])
     v = point_source_rhs(y, x0)
     assert np.all(v > 0) and np.allclose(v, 1 / (4 * np.pi * np.array([1.0, 2.0, 4.0])), rtol=1e-15)
+
+
+def test_radon7_is_exact_to_degree_five():
+    """Radon's rule integrates x^a y^b over the unit right triangle exactly
+    (a! b! / (a + b + 2)!) for a + b <= 5, and is not exact at degree 6."""
+    from math import factorial
+
+    from oracle.bem import quadrature7, radon7
+    bary, w = radon7()
+    assert w.sum() == pytest.approx(1.0, abs=1e-15) and np.all(w > 0) and np.all(bary > 0)
+    V = np.array([[0.0, 0, 0], [1.0, 0, 0], [0.0, 1, 0]])
+    pts, om = quadrature7(V, np.array([[0, 1, 2]]))
+    x, y = pts[0, :, 0], pts[0, :, 1]
+    for deg in range(6):
+        for a in range(deg + 1):
+            b = deg - a
+            exact = factorial(a) * factorial(b) / factorial(a + b + 2)
+            assert om[0] @ (x ** a * y ** b) == pytest.approx(exact, rel=1e-14, abs=1e-16)
+    worst = max(abs(om[0] @ (x ** a * y ** (6 - a)) - factorial(a) * factorial(6 - a) / factorial(8))
+                for a in range(7))
+    assert worst > 1e-6
+
+
+def test_quadrature7_weights_and_points():
+    """Weights sum to the triangle's area; points lie inside the triangle."""
+    from oracle.bem import quadrature7
+    V, T = synth.bumpy_torus_mesh(16, 8)
+    y, w, _ = panels(V, T)
+    pts, om = quadrature7(V, T)
+    np.testing.assert_allclose(om.sum(axis=1), w, rtol=1e-14)
+    np.testing.assert_allclose(pts.mean(axis=1), y, atol=1e-15)     # the rule is symmetric
+    a, b, c = V[T[:, 0]], V[T[:, 1]], V[T[:, 2]]
+    n = np.cross(b - a, c - a)
+    for k in range(7):
+        p = pts[:, k, :]
+        for u, v in ((a, b), (b, c), (c, a)):
+            assert np.all(np.einsum("ij,ij->i", np.cross(v - u, p - u), n) > 0)
+
+
+def _refined(V3, level):
+    """A triangle split into 4^level similar sub-triangles."""
+    tris = [V3]
+    for _ in range(level):
+        nxt = []
+        for a, b, c in tris:
+            ab, bc, ca = (a + b) / 2, (b + c) / 2, (c + a) / 2
+            nxt += [np.array([a, ab, ca]), np.array([ab, b, bc]), np.array([ca, bc, c]), np.array([ab, bc, ca])]
+        tris = nxt
+    return np.array(tris)
+
+
+def test_near_quadrature7_double_integral_of_separated_panels():
+    """For two panels a few diameters apart the seven-point rule on both
+    triangles gives the double integral of 1/(4 pi |x - y|) to its
+    degree-5 accuracy: compared with the same rule on 4^3 sub-triangles of
+    each (converged to about 1e-12 here), within 1e-6 relative; and the
+    one-point entry differs by about 1e-3, so the rule is doing work."""
+    from oracle.bem import near_quadrature7, quadrature7
+    A = np.array([[0.0, 0, 0], [0.1, 0, 0], [0.02, 0.09, 0.01]])
+    B = A + np.array([0.25, 0.05, 0.03])
+    V = np.vstack([A, B])
+    T = np.array([[0, 1, 2], [3, 4, 5]])
+    qy, qu = near_quadrature7(V, T)
+    s = np.sqrt(panels(V, T)[1])
+    r = np.linalg.norm(qy[0][:, None, :] - qy[1][None, :, :], axis=-1)
+    S01 = float(qu[0] @ (1 / (4 * np.pi * r)) @ qu[1])
+    ref = 0.0
+    sa, sb = _refined(A, 3), _refined(B, 3)
+    Vs = np.vstack([sa.reshape(-1, 3), sb.reshape(-1, 3)])
+    Ts = np.arange(len(Vs)).reshape(-1, 3)
+    pts, om = quadrature7(Vs, Ts)
+    na = len(sa)
+    pa, wa = pts[:na].reshape(-1, 3), om[:na].reshape(-1)
+    pb, wb = pts[na:].reshape(-1, 3), om[na:].reshape(-1)
+    for i0 in range(0, len(pa), 512):
+        d = np.linalg.norm(pa[i0:i0 + 512, None, :] - pb[None, :, :], axis=-1)
+        ref += float(wa[i0:i0 + 512] @ (1 / (4 * np.pi * d)) @ wb)
+    ref /= s[0] * s[1]
+    one = s[0] * s[1] / (4 * np.pi * np.linalg.norm(panels(V, T)[0][0] - panels(V, T)[0][1]))
+    assert abs(S01 - ref) <= 5e-6 * ref
+    assert abs(one - ref) >= 1e-3 * ref
+
+
+def test_near_quadrature_reduces_to_the_scaled_form_and_is_spd():
+    """With one quadrature point per panel (its centroid, u = s) the
+    quadrature near field is exactly the scaled one-point form; with
+    Radon's rule on a small bumpy torus the matrix (far blocks compressed)
+    is symmetric and positive definite."""
+    from oracle.bem import near_quadrature7
+    V, T = synth.bumpy_torus_mesh(24, 12)
+    y, s, d = symmetric_scaling(V, T)
+    lap = make_kernel("laplace", 1.0)
+    base = H2(y, lap, 0.0, 32, 0.7, 3, scale=s, diag=d)
+    one = H2(y, lap, 0.0, 32, 0.7, 3, scale=s, diag=d, near_quad=(y[:, None, :], s[:, None]))
+    np.testing.assert_allclose(one.dense(), base.dense(), rtol=1e-14, atol=1e-15)
+    q7 = H2(y, lap, 0.0, 32, 0.7, 3, scale=s, diag=d, near_quad=near_quadrature7(V, T))
+    A7 = q7.dense()
+    assert np.abs(A7 - A7.T).max() <= 1e-15 * np.abs(A7).max()
+    lam = np.linalg.eigvalsh(A7)
+    assert lam[0] > 0
+    # the close entries move, the far ones do not
+    D = A7 - base.dense()
+    assert np.abs(D).max() > 1e-4 * np.abs(A7).max()

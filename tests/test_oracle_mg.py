@@ -15,7 +15,7 @@ import synth
 from oracle.cg import NotSPD, block_jacobi, cg, cg_solve, pcg
 from oracle.galerkin import Hierarchy, galerkin
 from oracle.h2 import H2
-from oracle.ir import ir_solve, round_bf16, round_fp32
+from oracle.ir import ir_solve, lowered, near_mask, round_bf16, round_fp32, vcycle_fp32
 from oracle.ortho import coarse_basis, qr_pos
 from oracle.vcycle import coarsest_factor, mg_cycle, solve, vcycle
 
@@ -226,6 +226,50 @@ def test_refinement_fixed_point_is_the_fp64_solution(small, prec):
     A = H.ops[0]
     assert res.converged
     assert np.linalg.norm(b - A @ res.x) < 1e-8 * np.linalg.norm(b)
+
+
+def test_near_mask_is_the_close_leaf_blocks(small):
+    """The mask covers exactly the close leaf pairs: its blocks are the
+    oracle's near blocks (their entries come from the kernel, not from the
+    bases), it is symmetric and holds every diagonal block; outside it,
+    A_H2 is the sum of the far blocks U S U^T."""
+    h, H = small
+    M = near_mask(H)
+    assert np.array_equal(M, M.T)
+    L = h.L
+    for j in range(2 ** L):
+        rj = h.rows(L, j)
+        assert M[rj, rj].all()
+    near_entries = sum((h.rows(L, s).stop - h.rows(L, s).start) * (h.rows(L, t).stop - h.rows(L, t).start)
+                       for s, t in h.part.near[L])
+    assert int(M.sum()) == near_entries
+    far = np.zeros_like(H.ops[0])
+    for d in range(L + 1):
+        for s, t in h.part.far[d]:
+            far[h.rows(d, s), h.rows(d, t)] = h.basis(d, s) @ h.coupling(d, s, t) @ h.basis(d, t).T
+    np.testing.assert_array_equal(np.where(M, 0.0, H.ops[0]), np.where(M, 0.0, far))
+
+
+def test_lowered_policy_and_fp32_arithmetic_cycle(small):
+    """lowered(H, "bf16") rounds the fine operator's close blocks to FP32 and
+    everything else to BF16; the FP32-arithmetic cycle returns FP32 values
+    and stays within FP32 rounding (amplified by the cycle) of the FP64
+    arithmetic cycle on the same operators."""
+    h, H = small
+    M = near_mask(H)
+    Hl = lowered(H, "bf16")
+    A = H.ops[0]
+    np.testing.assert_array_equal(Hl.ops[0][M], round_fp32(A[M]))
+    np.testing.assert_array_equal(Hl.ops[0][~M], round_bf16(A[~M]))
+    for k in range(1, H.levels - 1):
+        np.testing.assert_array_equal(Hl.ops[k], round_bf16(H.ops[k]))
+    np.testing.assert_array_equal(Hl.ops[-1], H.ops[-1])
+    b = synth.normal_vector(h.n, 15)
+    d32 = vcycle_fp32(H, b, "fp32", 1, 2)
+    np.testing.assert_array_equal(d32, round_fp32(d32))
+    d = vcycle(lowered(H, "fp32"), np.zeros_like(b), b, 1, 2)
+    rel = np.linalg.norm(d32 - d) / np.linalg.norm(d)
+    assert 0 < rel < 1e-4
 
 
 # ---------------------------------------------------------------- W/F-cycles, plain CG
