@@ -463,6 +463,30 @@ h2mg_status h2mg_vcycle(h2mg_h2_t h, const double* x0_dev, const double* b_dev,
 h2mg_status h2mg_solve(h2mg_h2_t h, const double* b_dev, double* x_dev,
                        const h2mg_solve_opts* opts, h2mg_solve_info* info,
                        hipStream_t stream);
+
+/* Bytes of the fixed device scratch region of h2mg_solve_noalloc. */
+#define H2MG_SOLVE_SCRATCH_BYTES (256ull * 1024ull * 1024ull)
+
+/* h2mg_solve for callers that cannot allocate device memory (tight serving
+ * loops, code that must not call hipMalloc): the same solve, arguments and
+ * results, with no device allocation or free in the call.  Its vectors (the
+ * per-level residuals and corrections, the CG temporaries, tree-ordered b
+ * and x) are carved from a fixed region of H2MG_SOLVE_SCRATCH_BYTES in
+ * device memory that the library holds on every GPU it runs on until the
+ * process ends; cycles are launched kernel by kernel (no graphs).  The
+ * region needs about 8 (2 sum_k N_k + 7 n) bytes in FP64 plus half that
+ * again for a mixed precision (N = 2^20: about 130 MB); a larger problem is
+ * INVALID_ARG, with the bytes it needs in the message.  Everything a solve
+ * builds on first use must already exist: h2mg_setup_mg with the
+ * precision's bit, and for the block smoother its inverses (built by one
+ * h2mg_solve with that smoother and precision); otherwise STATE.  Every
+ * call on one GPU uses the same region, which keeps the previous call's
+ * contents (no vector is read before the solve writes it): calls that
+ * overlap on one GPU, from any handle or stream, race and must be
+ * serialised by the caller.  Other errors as h2mg_solve. */
+h2mg_status h2mg_solve_noalloc(h2mg_h2_t h, const double* b_dev, double* x_dev,
+                               const h2mg_solve_opts* opts, h2mg_solve_info* info,
+                               hipStream_t stream);
 /* Relative residual before each cycle of the last solve, then at exit
  * (host array of at least `capacity` doubles; copies min(capacity, len)). */
 h2mg_status h2mg_solve_history(h2mg_h2_t h, double* history_host, int32_t capacity);

@@ -67,6 +67,8 @@ SIGNATURES = {
     "h2mg_vcycle": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(SolveOpts), c_void_p]),
     "h2mg_solve": (c_int32, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(SolveOpts),
                              ctypes.POINTER(SolveInfo), c_void_p]),
+    "h2mg_solve_noalloc": (c_int32, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(SolveOpts),
+                                     ctypes.POINTER(SolveInfo), c_void_p]),
     "h2mg_solve_history": (c_int32, [c_void_p, P_double, c_int32]),
     "h2mg_memory_bytes": (c_int32, [c_void_p, P_int64]),
     "h2mg_gemv_launch_info": (c_int32, [c_void_p, c_int32, P_int64, P_int64]),

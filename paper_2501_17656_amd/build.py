@@ -19,7 +19,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libh2mg.so")
 
 HIP_SOURCES = ["kernels_setup.hip", "kernels_apply.hip", "kernels_solve.hip", "kernels_bem.hip",
-               "kernels_block.hip"]
+               "kernels_block.hip", "noalloc.hip"]
 CPP_SOURCES = ["plan.cpp", "h2_build.cpp", "h2_apply.cpp", "block.cpp", "solver.cpp", "abi.cpp"]
 ARCH = os.environ.get("H2MG_ARCH", "gfx950")
 

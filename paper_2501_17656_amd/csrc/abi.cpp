@@ -388,6 +388,16 @@ h2mg_status h2mg_solve(h2mg_h2_t hh, const double* b, double* x, const h2mg_solv
   });
 }
 
+h2mg_status h2mg_solve_noalloc(h2mg_h2_t hh, const double* b, double* x, const h2mg_solve_opts* opts,
+                               h2mg_solve_info* info, hipStream_t stream) {
+  return guarded([&] {
+    if (!hh || !b || !x) return fail(H2MG_ERR_INVALID_ARG, "null argument");
+    if (!valid_solve_opts(opts)) return fail(H2MG_ERR_INVALID_ARG, "invalid solve options");
+    hh->h->stream = stream;
+    return solve_noalloc(*hh->h, b, x, to_params(opts), info);
+  });
+}
+
 h2mg_status h2mg_solve_history(h2mg_h2_t hh, double* hist, int32_t cap) {
   return guarded([&] {
     if (!hh || (!hist && cap > 0)) return fail(H2MG_ERR_INVALID_ARG, "null argument");

@@ -61,6 +61,14 @@ struct SolveParams {
 };
 // Solve A_H2 x = b; b, x device, user order.  Fills info.
 h2mg_status solve(H2& h, const double* b, double* x, const SolveParams& sp, h2mg_solve_info* info);
+// The same solve with every vector carved from the fixed device scratch
+// region (no allocation, no graphs); STATE unless the hierarchy, the
+// precision's operators and, for the block smoother, its inverses exist.
+h2mg_status solve_noalloc(H2& h, const double* b, double* x, const SolveParams& sp,
+                          h2mg_solve_info* info);
+// Device address of the current device's fixed scratch region and its size
+// in bytes (noalloc.hip; throws if the address cannot be obtained).
+void* solve_scratch(size_t* bytes);
 // e = Iter(A_level, r, e0): nsteps of the smoother in FP64 (level 1 in user
 // order, coarser levels in coefficient order); e0 = e on entry when use_e0.
 h2mg_status smooth_once(H2& h, int level, const double* r, double* e, int nsteps, int smoother,

@@ -41,12 +41,24 @@ struct Work {
   double* dpart = nullptr;
 };
 
-// Where a solve's vectors come from: the handle's allocator.
+// Where a solve's vectors come from: the handle's allocator, consecutive
+// 256-byte aligned pieces of a fixed device region (the entry point that
+// allocates nothing), or nowhere (COUNT: only the bytes are added up).
 struct VecSource {
+  enum Mode { ARENA, CARVE, COUNT } mode = ARENA;
   H2* h = nullptr;
-  void* get(size_t bytes) { return h->arena.alloc(bytes); }
+  char* region = nullptr;
+  size_t cap = 0, used = 0;
+  void* get(size_t bytes) {
+    if (mode == ARENA) return h->arena.alloc(bytes);
+    const size_t off = (used + 255) & ~size_t(255);
+    used = off + bytes;
+    if (mode == COUNT) return nullptr;
+    if (used > cap) throw std::length_error("solve scratch exhausted");
+    return region + off;
+  }
   void put(void* p) {
-    if (p) h->arena.release(p);
+    if (mode == ARENA && p) h->arena.release(p);
   }
 };
 
@@ -328,14 +340,26 @@ h2mg_status ensure_block_jacobi(H2& h, int p) {
 
 namespace {
 
-// The solve (arena vectors, optional graphs).
-h2mg_status solve_impl(H2& h, const double* b, double* x, const SolveParams& sp, h2mg_solve_info* info) {
+// The solve of `solve` (arena vectors, optional graphs) and of `solve_noalloc`
+// (vectors carved from the device scratch region, no graphs, nothing built
+// on demand).
+h2mg_status solve_impl(H2& h, const double* b, double* x, const SolveParams& sp, h2mg_solve_info* info,
+                       bool noalloc) {
   const auto t0 = std::chrono::steady_clock::now();
   h.history.clear();
   const int p = sp.precision == 0 ? P64 : sp.precision == 1 ? P32 : P16;
   const bool plain = sp.method == 3;
   if (plain && p != P64) return fail(H2MG_ERR_INVALID_ARG, "CG on A_H2 alone runs in FP64 only");
   const bool need_mg = !(plain && sp.smoother == 0);
+  if (noalloc) {
+    // everything a solve would otherwise build on its first call must exist
+    if (need_mg && (!h.mg_built || (p != P64 && !h.prec[p].ready)))
+      return fail(H2MG_ERR_STATE, "the solve that allocates nothing needs h2mg_setup_mg with the %s "
+                  "precision bit first", p == P64 ? "FP64" : p == P32 ? "FP32" : "BF16");
+    if (sp.smoother == 1 && (!h.bj_built[P64] || (p != P64 && !h.bj_built[P32])))
+      return fail(H2MG_ERR_STATE, "the solve that allocates nothing needs the block smoother's "
+                  "inverses: run one h2mg_solve with this smoother and precision first");
+  }
   // plain CG needs the hierarchy only for the block-Jacobi inverses, which
   // are formed for all levels together
   h2mg_status st = need_mg ? setup_mg(h, p == P64 ? 0 : (1 << p)) : H2MG_OK;
@@ -354,6 +378,28 @@ h2mg_status solve_impl(H2& h, const double* b, double* x, const SolveParams& sp,
   const int64_t n = h.n;
   VecSource src;
   src.h = &h;
+  if (noalloc) {
+    // bytes of every vector below, then the fixed region they are carved from
+    VecSource cnt;
+    cnt.mode = VecSource::COUNT;
+    make_work(h, P64, second && p == P64, cnt);
+    if (p != P64) make_work(h, p, second, cnt);
+    cnt.get(size_t(n) * 8);
+    cnt.get(size_t(n) * 8);
+    size_t cap = 0;
+    void* region = nullptr;
+    try {
+      region = solve_scratch(&cap);
+    } catch (const std::exception& ex) {
+      return fail(H2MG_ERR_HIP, "%s", ex.what());
+    }
+    if (cnt.used > cap)
+      return fail(H2MG_ERR_INVALID_ARG, "this solve needs %zu bytes of scratch; the fixed region "
+                  "holds %zu (H2MG_SOLVE_SCRATCH_BYTES)", cnt.used, cap);
+    src.mode = VecSource::CARVE;
+    src.region = static_cast<char*>(region);
+    src.cap = cap;
+  }
   Work w64, wlp;
   bool have_lp = false;
   h2mg_status result = H2MG_OK;
@@ -401,8 +447,9 @@ h2mg_status solve_impl(H2& h, const double* b, double* x, const SolveParams& sp,
       if (!h.history.empty()) h.history.back() = rel;
     } else {
       // event timing records events between launches, so it runs the cycle
-      // launch by launch
-      const bool use_graph = h.graphs && !h.timing;
+      // launch by launch; the entry point that allocates nothing does too
+      // (instantiating a graph allocates)
+      const bool use_graph = h.graphs && !h.timing && !noalloc;
       CycleGraph cg_graph;
       for (int cyc = 0;; ++cyc) {
         // res = b - A_H2 x (FP64)
@@ -461,7 +508,12 @@ h2mg_status solve_impl(H2& h, const double* b, double* x, const SolveParams& sp,
 }  // namespace
 
 h2mg_status solve(H2& h, const double* b, double* x, const SolveParams& sp, h2mg_solve_info* info) {
-  return solve_impl(h, b, x, sp, info);
+  return solve_impl(h, b, x, sp, info, false);
+}
+
+h2mg_status solve_noalloc(H2& h, const double* b, double* x, const SolveParams& sp,
+                          h2mg_solve_info* info) {
+  return solve_impl(h, b, x, sp, info, true);
 }
 
 h2mg_status smooth_once(H2& h, int level, const double* r, double* e, int nsteps, int smoother,

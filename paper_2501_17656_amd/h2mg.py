@@ -253,9 +253,12 @@ class H2Matrix:
 
     def solve(self, b, rtol: float = 1e-8, n_fine: int = 1, n_coarse: int = 40,
               max_cycles: int = 500, precision: str = "fp64", x0=None, raise_on_error: bool = True,
-              smoother: str = "cg", method: str = "v", out=None):
+              smoother: str = "cg", method: str = "v", noalloc: bool = False, out=None):
         """Solve A_H2 x = b by V-, W- or F-cycles, or by CG alone (method
         "cg"; max_cycles then counts CG iterations).  Returns (x, info).
+        noalloc: h2mg_solve_noalloc, which allocates no device memory (its
+        vectors live in the library's fixed scratch region; the hierarchy in
+        this precision, and the block smoother's inverses, must exist).
         out: write x there (with x0, out holds the initial guess on entry)."""
         import torch
         if out is None:
@@ -267,7 +270,7 @@ class H2Matrix:
         o = self._opts(rtol, n_fine, n_coarse, max_cycles, precision, x0 is not None, smoother,
                        method)
         info = _lib.SolveInfo()
-        fn = lib().h2mg_solve
+        fn = lib().h2mg_solve_noalloc if noalloc else lib().h2mg_solve
         st = fn(self._h, _dev_f64(b, self.n, "b"), _dev_f64(x, self.n, "x"),
                 ctypes.byref(o), ctypes.byref(info), _stream())
         msg = _lib.last_error() if st != 0 else ""
