@@ -19,6 +19,7 @@
 #include <cmath>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 
 #include "h2_impl.h"
 
@@ -27,6 +28,8 @@ namespace h2mg {
 namespace {
 
 constexpr int NT = 256;   // threads per workgroup of the setup kernels
+
+typedef double d4 __attribute__((ext_vector_type(4)));
 
 __device__ double block_sum(double v, double* red) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -263,167 +266,228 @@ __global__ __launch_bounds__(NT) void k_transfer_qr(
   }
 }
 
-// ------------------------------------------------------------ couplings
-__global__ __launch_bounds__(NT) void k_coupling(
-    int b0, const int* __restrict__ blk_row, const int* __restrict__ blk_col, int dim,
+// ------------------------------------------------------------ Galerkin products
+// Couplings, projected close leaf blocks and projected upper blocks are all
+//   out[mu][nu] = sum_i sum_j QS(i, mu) K(i, j) QT(j, nu)       (r x r)
+// for an inner matrix K and two thin factors:
+//   * coupling of a far pair (s, t): K = k(xi_s, xi_t) on the Chebyshev nodes,
+//     QS(i, mu) = R_s[mu][i], QT(j, nu) = R_t[nu][j]  (out = R_s K R_t^T);
+//   * close leaf pair: K = the kernel entries of the two leaves (shift on a
+//     diagonal pair's diagonal), QS = Q_s, QT = Q_t (out = Q_s^T K Q_t);
+//   * close pair above the leaves: K = the 2 x 2 arrangement of the stored
+//     child blocks M_cc' (i = child a * RM + row, j likewise), QS and QT the
+//     stacked child transfers [E_c1; E_c2] (out = sum E_c^T M_cc' E_c').
+// One wave per output tile, on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; result element t of lane l is D[4 t + l / 16][l % 16]).
+// The rows i are taken 16 at a time: W = K[i0 : i0 + 16, :] QT is formed in
+// RS accumulators (RS = RM / 16 column slabs of 16, RM = max(16, 8T)), the
+// kernel entries computed (or loaded) by the lane that supplies them, and
+// then folded into out += QS[i0 : i0 + 16, :]^T W; a W accumulator holds,
+// in element t, exactly the B operand of the fold's k-step t, so the fold
+// needs no data movement.  Entries outside the matrices (i, j beyond the
+// point or node count, mu, nu >= r) are zero.
+template <int RS, typename Acc>
+__device__ __forceinline__ void galerkin_wave(const Acc& acc, int ni, int nj, d4 (&out)[RS][RS]) {
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int a = 0; a < RS; ++a)
+#pragma unroll
+    for (int b = 0; b < RS; ++b) out[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int i0 = 0; i0 < ni; i0 += 16) {
+    const auto row = acc.row(i0 + li);
+    d4 w[RS];
+#pragma unroll
+    for (int c = 0; c < RS; ++c) w[c] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int j0 = 0; j0 < nj; j0 += 4) {
+      const int j = j0 + lk;
+      const double a = acc.k(row, i0 + li, j);
+#pragma unroll
+      for (int c = 0; c < RS; ++c)
+        w[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, acc.qt(j, c * 16 + li), w[c], 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int i = i0 + 4 * t + lk;
+#pragma unroll
+      for (int mu = 0; mu < RS; ++mu) {
+        const double q = acc.qs(i, mu * 16 + li);
+#pragma unroll
+        for (int nu = 0; nu < RS; ++nu)
+          out[mu][nu] = __builtin_amdgcn_mfma_f64_16x16x4f64(q, w[nu][t], out[mu][nu], 0, 0, 0);
+      }
+    }
+  }
+}
+
+template <int RS>
+__device__ __forceinline__ void store_galerkin(const d4 (&out)[RS][RS], int r, int T, double* tile) {
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int mu = 0; mu < RS; ++mu)
+#pragma unroll
+    for (int nu = 0; nu < RS; ++nu)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int i = mu * 16 + 4 * t + lk, j = nu * 16 + li;
+        if (i < r && j < r) tile[tile_offset<double>(i, j, T)] = out[mu][nu][t];
+      }
+}
+
+__device__ inline int wave_id() {
+  return __builtin_amdgcn_readfirstlane(int((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+}
+
+// Couplings of a far pair: K on the two node sets, QS / QT from the R factors
+// of the direct bases (row-major r x r, upper triangular).
+struct CouplingAcc {
+  const double* cs; const double* hs; const double* ct; const double* ht;
+  const double* tn; const double* Rs; const double* Rt;
+  KernelParams kp; int m, dim, r;
+  struct Row { double x[3]; };
+  __device__ __forceinline__ Row row(int i) const {
+    Row p{{0.0, 0.0, 0.0}};
+    if (i < r) {
+      int nu = i;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        if (a < dim) {
+          p.x[a] = cs[a] + hs[a] * tn[nu % m];
+          nu /= m;
+        }
+    }
+    return p;
+  }
+  __device__ __forceinline__ double k(const Row& p, int i, int j) const {
+    if (i >= r || j >= r) return 0.0;
+    double r2 = 0.0;
+    int nu = j;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      if (a < dim) {
+        const double dx = p.x[a] - (ct[a] + ht[a] * tn[nu % m]);
+        nu /= m;
+        r2 += dx * dx;
+      }
+    return kernel_r2(kp, r2);
+  }
+  __device__ __forceinline__ double qs(int i, int mu) const { return i < r && mu < r ? Rs[size_t(mu) * r + i] : 0.0; }
+  __device__ __forceinline__ double qt(int j, int nu) const { return j < r && nu < r ? Rt[size_t(nu) * r + j] : 0.0; }
+};
+
+template <int RS>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_coupling(
+    int b0, int nb, const int* __restrict__ blk_row, const int* __restrict__ blk_col, int dim,
     const double* __restrict__ cbox, const double* __restrict__ hbox,
     const double* __restrict__ nodes, int m, int r, int T, KernelParams kp,
     const double* __restrict__ Rall, double* __restrict__ blk) {
-  extern __shared__ double smem[];
-  const int tid = threadIdx.x;
-  const int b = b0 + blockIdx.x;
+  const int w = wave_id();
+  if (w >= nb) return;
+  const int b = b0 + w;
   const int gs = blk_row[b], gt = blk_col[b];
-  double* S = smem;                  // r x r row-major
-  double* T1 = S + size_t(r) * r;
-  double* tn = T1 + size_t(r) * r;
-  if (tid < m) tn[tid] = nodes[tid];
-  __syncthreads();
-  const double* cs = cbox + size_t(gs) * dim;
-  const double* hs = hbox + size_t(gs) * dim;
-  const double* ct = cbox + size_t(gt) * dim;
-  const double* ht = hbox + size_t(gt) * dim;
-  for (int idx = tid; idx < r * r; idx += NT) {
-    const int nu = idx / r, mu = idx % r;
-    double xs[3], xt[3];
-    node_coord(cs, hs, tn, m, dim, nu, xs);
-    node_coord(ct, ht, tn, m, dim, mu, xt);
-    double r2 = 0.0;
-    for (int a = 0; a < dim; ++a) {
-      const double dx = xs[a] - xt[a];
-      r2 += dx * dx;
-    }
-    S[idx] = kernel_r2(kp, r2);
-  }
-  __syncthreads();
-  const double* Rs = Rall + size_t(gs) * r * r;
-  const double* Rt = Rall + size_t(gt) * r * r;
-  for (int idx = tid; idx < r * r; idx += NT) {     // T1 = S Rt^T
-    const int nu = idx / r, q = idx % r;
-    double s = 0.0;
-    for (int mu = q; mu < r; ++mu) s += S[size_t(nu) * r + mu] * Rt[size_t(q) * r + mu];
-    T1[idx] = s;
-  }
-  __syncthreads();
-  double* out = tile_ptr(blk, b, T);
-  for (int idx = tid; idx < r * r; idx += NT) {     // Rs T1
-    const int i = idx / r, q = idx % r;
-    double s = 0.0;
-    for (int nu = i; nu < r; ++nu) s += Rs[size_t(i) * r + nu] * T1[size_t(nu) * r + q];
-    out[tile_offset<double>(i, q, T)] = s;
-  }
+  const CouplingAcc acc{cbox + size_t(gs) * dim, hbox + size_t(gs) * dim, cbox + size_t(gt) * dim,
+                        hbox + size_t(gt) * dim, nodes, Rall + size_t(gs) * r * r,
+                        Rall + size_t(gt) * r * r, kp, m, dim, r};
+  d4 out[RS][RS];
+  galerkin_wave<RS>(acc, (r + 15) & ~15, (r + 3) & ~3, out);
+  store_galerkin<RS>(out, r, T, tile_ptr(blk, b, T));
 }
 
-// ------------------------------------------------------------ projected leaf blocks
-// Pi = Q_s^T K_st Q_t for a close leaf pair (K with the shift on the diagonal
-// of a diagonal pair).
-__global__ __launch_bounds__(NT) void k_pi_leaf(
-    int b0, const int* __restrict__ blk_row, const int* __restrict__ blk_col, int gid0,
+// Projected close leaf blocks: K = the kernel (shift on the diagonal of a
+// diagonal pair), QS / QT the orthonormal leaf bases (row-major, per point).
+struct LeafAcc {
+  const double* pts; const double* Qr;
+  KernelParams kp; PointScale ps;
+  int s0, ns, t0, nt, dim, r;
+  bool diag;
+  struct Row { double x[3]; };
+  __device__ __forceinline__ Row row(int i) const {
+    Row p{{0.0, 0.0, 0.0}};
+    if (i < ns) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        if (a < dim) p.x[a] = pts[size_t(s0 + i) * dim + a];
+    }
+    return p;
+  }
+  __device__ __forceinline__ double k(const Row& p, int i, int j) const {
+    if (i >= ns || j >= nt) return 0.0;
+    double r2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      if (a < dim) {
+        const double dx = p.x[a] - pts[size_t(t0 + j) * dim + a];
+        r2 += dx * dx;
+      }
+    return near_entry(kp, ps, dim, r2, s0 + i, t0 + j, diag && i == j);
+  }
+  __device__ __forceinline__ double qs(int i, int mu) const { return i < ns && mu < r ? Qr[size_t(s0 + i) * r + mu] : 0.0; }
+  __device__ __forceinline__ double qt(int j, int nu) const { return j < nt && nu < r ? Qr[size_t(t0 + j) * r + nu] : 0.0; }
+};
+
+template <int RS>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_pi_leaf(
+    int b0, int nb, const int* __restrict__ blk_row, const int* __restrict__ blk_col, int gid0,
     const int* __restrict__ leaf_off, const double* __restrict__ pts, int dim, int r, int T,
     KernelParams kp, PointScale ps, const double* __restrict__ Qr, double* __restrict__ blk) {
-  extern __shared__ double smem[];
-  const int tid = threadIdx.x;
-  const int b = b0 + blockIdx.x;
+  const int w = wave_id();
+  if (w >= nb) return;
+  const int b = b0 + w;
   const int ls = blk_row[b] - gid0, lt = blk_col[b] - gid0;
-  const int s0 = leaf_off[ls], ns = leaf_off[ls + 1] - s0;
-  const int t0 = leaf_off[lt], nt = leaf_off[lt + 1] - t0;
-  const bool diag = ls == lt;
-  double* Tm = smem;                      // ns x r row-major
-  double* pt = Tm + size_t(ns) * r;       // nt x dim
-  for (int idx = tid; idx < nt * dim; idx += NT) pt[idx] = pts[size_t(t0) * dim + idx];
-  __syncthreads();
-  const int half = (r + 1) / 2;
-  for (int i0 = 0; i0 < ns; i0 += 128) {
-    const int i = i0 + (tid & 127);
-    const int c0 = (tid >> 7) * half;
-    const int c1 = min(r, c0 + half);
-    double acc[32];
-#pragma unroll
-    for (int q = 0; q < 32; ++q) acc[q] = 0.0;
-    if (i < ns) {
-      double pi[3];
-      for (int a = 0; a < dim; ++a) pi[a] = pts[size_t(s0 + i) * dim + a];
-      for (int j = 0; j < nt; ++j) {
-        double r2 = 0.0;
-        for (int a = 0; a < dim; ++a) {
-          const double dx = pi[a] - pt[j * dim + a];
-          r2 += dx * dx;
-        }
-        const double k = near_entry(kp, ps, dim, r2, s0 + i, t0 + j, diag && i == j);
-        const double* qrow = Qr + size_t(t0 + j) * r + c0;
-#pragma unroll
-        for (int q = 0; q < 32; ++q)
-          if (c0 + q < c1) acc[q] += k * qrow[q];
-      }
-#pragma unroll
-      for (int q = 0; q < 32; ++q)
-        if (c0 + q < c1) Tm[size_t(i) * r + c0 + q] = acc[q];
-    }
-  }
-  __syncthreads();
-  double* out = tile_ptr(blk, b, T);
-  for (int idx = tid; idx < r * r; idx += NT) {
-    const int mu = idx / r, nu = idx % r;
-    double s = 0.0;
-    for (int i = 0; i < ns; ++i) s += Qr[size_t(s0 + i) * r + mu] * Tm[size_t(i) * r + nu];
-    out[tile_offset<double>(mu, nu, T)] = s;
-  }
+  const int s0 = leaf_off[ls], t0 = leaf_off[lt];
+  const LeafAcc acc{pts, Qr, kp, ps, s0, leaf_off[ls + 1] - s0, t0, leaf_off[lt + 1] - t0, dim, r, ls == lt};
+  d4 out[RS][RS];
+  galerkin_wave<RS>(acc, (acc.ns + 15) & ~15, (acc.nt + 3) & ~3, out);
+  store_galerkin<RS>(out, r, T, tile_ptr(blk, b, T));
 }
 
-// ------------------------------------------------------------ projected upper blocks
-// Pi_st = sum over child pairs (c, c') of E_c^T M_cc' E_c', M = stored child
-// block (Pi or S), transposed when the child pair is below the diagonal.
-__global__ __launch_bounds__(NT) void k_pi_upper(
-    int b0, const int* __restrict__ blk_row, const int* __restrict__ blk_col,
+// Projected blocks above the leaves: K = [M_11 M_12; M_21 M_22] over the
+// child pairs (a stored child block, transposed when the child pair is below
+// the diagonal: child_map entry -id - 1), rows and columns of child a at
+// a * RM; QS / QT the children's transfer tiles.
+struct UpperAcc {
+  const double* blk; const double* E;
+  const int* map;            // the four child block ids (negative: transposed)
+  int gcs0, gct0, r, T, RM;
+  struct Row { int id0, id1; };
+  __device__ __forceinline__ Row row(int i) const {
+    const int a = i >= RM;
+    return Row{map[2 * a], map[2 * a + 1]};
+  }
+  __device__ __forceinline__ double k(const Row& p, int i, int j) const {
+    const int a = i >= RM, b = j >= RM;
+    const int ii = i - a * RM, jj = j - b * RM;
+    if (ii >= r || jj >= r) return 0.0;
+    const int id = b ? p.id1 : p.id0;
+    return id >= 0 ? blk[int64_t(id) * tile_elems(T) + tile_offset<double>(ii, jj, T)]
+                   : blk[int64_t(-id - 1) * tile_elems(T) + tile_offset<double>(jj, ii, T)];
+  }
+  __device__ __forceinline__ double qs(int i, int mu) const {
+    const int a = i >= RM, ii = i - a * RM;
+    return ii < r && mu < r ? E[int64_t(gcs0 + a) * tile_elems(T) + tile_offset<double>(ii, mu, T)] : 0.0;
+  }
+  __device__ __forceinline__ double qt(int j, int nu) const {
+    const int b = j >= RM, jj = j - b * RM;
+    return jj < r && nu < r ? E[int64_t(gct0 + b) * tile_elems(T) + tile_offset<double>(jj, nu, T)] : 0.0;
+  }
+};
+
+template <int RS>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_pi_upper(
+    int b0, int nb, const int* __restrict__ blk_row, const int* __restrict__ blk_col,
     const int* __restrict__ child_map, int r, int T, const double* __restrict__ E,
     double* __restrict__ blk) {
-  extern __shared__ double smem[];
-  const int tid = threadIdx.x;
-  const int b = b0 + blockIdx.x;
-  const int gs = blk_row[b], gt = blk_col[b];
-  double* Mb = smem;
-  double* Eb = Mb + size_t(r) * r;
-  double* W = Eb + size_t(r) * r;
-  double* acc = W + size_t(r) * r;       // r x r accumulator
-  for (int idx = tid; idx < r * r; idx += NT) acc[idx] = 0.0;
-  for (int ab = 0; ab < 4; ++ab) {
-    const int a = ab >> 1, bb = ab & 1;
-    const int id = child_map[4 * blockIdx.x + ab];
-    const bool trans = id < 0;
-    const int cid = trans ? -id - 1 : id;
-    const double* Mt = blk + int64_t(cid) * tile_elems(T);
-    const int gcs = 2 * gs + 1 + a, gct = 2 * gt + 1 + bb;   // child gids
-    const double* Et = E + int64_t(gct) * tile_elems(T);
-    __syncthreads();
-    for (int idx = tid; idx < r * r; idx += NT) {
-      const int i = idx / r, j = idx % r;
-      Mb[idx] = trans ? Mt[tile_offset<double>(j, i, T)] : Mt[tile_offset<double>(i, j, T)];
-      Eb[idx] = Et[tile_offset<double>(i, j, T)];
-    }
-    __syncthreads();
-    for (int idx = tid; idx < r * r; idx += NT) {     // W = M E_c'
-      const int i = idx / r, j = idx % r;
-      double s = 0.0;
-      for (int q = 0; q < r; ++q) s += Mb[size_t(i) * r + q] * Eb[size_t(q) * r + j];
-      W[idx] = s;
-    }
-    __syncthreads();
-    const double* Es = E + int64_t(gcs) * tile_elems(T);
-    for (int idx = tid; idx < r * r; idx += NT) {
-      const int i = idx / r, j = idx % r;
-      Eb[idx] = Es[tile_offset<double>(i, j, T)];
-    }
-    __syncthreads();
-    for (int idx = tid; idx < r * r; idx += NT) {     // acc += E_c^T W
-      const int mu = idx / r, nu = idx % r;
-      double s = 0.0;
-      for (int i = 0; i < r; ++i) s += Eb[size_t(i) * r + mu] * W[size_t(i) * r + nu];
-      acc[idx] += s;
-    }
-  }
-  __syncthreads();
-  double* out = blk + int64_t(b) * tile_elems(T);
-  for (int idx = tid; idx < r * r; idx += NT)
-    out[tile_offset<double>(idx / r, idx % r, T)] = acc[idx];
+  const int w = wave_id();
+  if (w >= nb) return;
+  const int b = b0 + w;
+  constexpr int RM = RS * 16;
+  const UpperAcc acc{blk, E, child_map + 4 * w,
+               2 * blk_row[b] + 1, 2 * blk_col[b] + 1, r, T, RM};
+  d4 out[RS][RS];
+  galerkin_wave<RS>(acc, 2 * RM, 2 * RM, out);
+  store_galerkin<RS>(out, r, T, tile_ptr(blk, b, T));
 }
 
 // ------------------------------------------------------------ dense coarsest operator
@@ -722,12 +786,24 @@ void launch_transfer_qr(H2& h, int d) {
   check_launch("transfer_qr");
 }
 
+// The Galerkin kernels take RS = 16-column slabs of the padded rank.
+template <typename F>
+void with_slabs(int T, F&& f) {
+  if (T <= 2) f(std::integral_constant<int, 1>{});
+  else if (T == 4) f(std::integral_constant<int, 2>{});
+  else f(std::integral_constant<int, 4>{});
+}
+
+inline dim3 wave_grid(int nb) { return dim3(unsigned((nb + NT / 64 - 1) / (NT / 64))); }
+
 void launch_couplings(H2& h, int d) {
   if (h.s_count[d] == 0) return;
-  const size_t lds = (size_t(2) * h.r * h.r + 64) * sizeof(double);
-  hipLaunchKernelGGL(k_coupling, dim3(h.s_count[d]), dim3(NT), lds, h.stream, h.s_first[d],
-                     h.blk_row, h.blk_col, h.dim, h.cbox, h.hbox, h.nodes1d, h.m, h.r, h.T, h.kp,
-                     h.R, static_cast<double*>(h.prec[P64].blk));
+  with_slabs(h.T, [&](auto rs) {
+    constexpr int RS = decltype(rs)::value;
+    hipLaunchKernelGGL(k_coupling<RS>, wave_grid(h.s_count[d]), dim3(NT), 0, h.stream, h.s_first[d],
+                       h.s_count[d], h.blk_row, h.blk_col, h.dim, h.cbox, h.hbox, h.nodes1d, h.m, h.r,
+                       h.T, h.kp, h.R, static_cast<double*>(h.prec[P64].blk));
+  });
   check_launch("coupling");
 }
 
@@ -766,23 +842,27 @@ void launch_gather_rows(H2& h, int width, const double* user, double* tree) {
 }
 
 void launch_pi_leaf(H2& h) {
-  if (h.p_count[h.L] == 0) return;
-  const size_t lds = (size_t(h.leaf_max) * h.r + size_t(h.leaf_max) * h.dim) * sizeof(double);
-  allow_lds(k_pi_leaf, lds);
-  hipLaunchKernelGGL(k_pi_leaf, dim3(h.p_count[h.L]), dim3(NT), lds, h.stream, h.p_first[h.L],
-                     h.blk_row, h.blk_col, h.nleaf - 1, h.leaf_off, h.pts, h.dim, h.r, h.T, h.kp,
-                     near_scale(h), static_cast<const double*>(h.prec[P64].Qr),
-                     static_cast<double*>(h.prec[P64].blk));
+  const int nb = h.p_count[h.L];
+  if (nb == 0) return;
+  with_slabs(h.T, [&](auto rs) {
+    constexpr int RS = decltype(rs)::value;
+    hipLaunchKernelGGL(k_pi_leaf<RS>, wave_grid(nb), dim3(NT), 0, h.stream, h.p_first[h.L], nb,
+                       h.blk_row, h.blk_col, h.nleaf - 1, h.leaf_off, h.pts, h.dim, h.r, h.T, h.kp,
+                       near_scale(h), static_cast<const double*>(h.prec[P64].Qr),
+                       static_cast<double*>(h.prec[P64].blk));
+  });
   check_launch("pi_leaf");
 }
 
 void launch_pi_upper(H2& h, int d, const int* child_map) {
-  if (h.p_count[d] == 0) return;
-  const size_t lds = size_t(4) * h.r * h.r * sizeof(double);
-  allow_lds(k_pi_upper, lds);
-  hipLaunchKernelGGL(k_pi_upper, dim3(h.p_count[d]), dim3(NT), lds, h.stream, h.p_first[d],
-                     h.blk_row, h.blk_col, child_map, h.r, h.T,
-                     static_cast<const double*>(h.prec[P64].E), static_cast<double*>(h.prec[P64].blk));
+  const int nb = h.p_count[d];
+  if (nb == 0) return;
+  with_slabs(h.T, [&](auto rs) {
+    constexpr int RS = decltype(rs)::value;
+    hipLaunchKernelGGL(k_pi_upper<RS>, wave_grid(nb), dim3(NT), 0, h.stream, h.p_first[d], nb,
+                       h.blk_row, h.blk_col, child_map, h.r, h.T,
+                       static_cast<const double*>(h.prec[P64].E), static_cast<double*>(h.prec[P64].blk));
+  });
   check_launch("pi_upper");
 }
 
