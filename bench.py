@@ -107,6 +107,8 @@ def parse(argv=None):
     ap.add_argument("--bem-grid", type=int, nargs=2, default=[1000, 500],
                     help="torus parameter grid (panels = 2 * a * b)")
     ap.add_argument("--json-out", default="")
+    ap.add_argument("--setup-only", action="store_true",
+                    help="run only the build and hierarchy setup of the timed workload")
     ap.add_argument("--block-product", action="store_true",
                     help="run only the 16-vector block product on the headline matrix")
     ap.add_argument("--batched", action="store_true",
@@ -313,20 +315,40 @@ def lanczos_probe(args, torch, synth, H2Matrix):
     by Lanczos on the library's FP64 matvec, with full reorthogonalisation
     (the Lanczos vectors stay in device memory).  The shift only adds s * I,
     so lambda(A_H2 + (s' - s) I) = lambda(A_H2) + s' - s: one run gives the
-    smallest eigenvalue for every shift.  Ritz values bound lambda_min from
-    above; for the smallest Ritz pair the true residual ||A y - theta y||
-    (one more product) bounds the distance from theta to some eigenvalue, so
-    theta + residual < 0 certifies that A_H2 is indefinite.  Items n:steps."""
+    smallest eigenvalue for every shift.  A Ritz value is the Rayleigh
+    quotient of its Ritz vector, so it bounds lambda_min from above (a
+    negative one certifies that A_H2 is indefinite); the true residual
+    ||A y - theta y|| (one more product) bounds the distance from theta to
+    some eigenvalue.  Items
+    n:steps[:cycles]: with cycles > 0 the start vector is the iterate of that
+    many FP64 V-cycles (CG smoother) on A_H2 x = b from x0 = 0, which grows
+    along the eigenvectors the cycle cannot reduce (a negative or near-zero
+    eigenvalue); otherwise a random vector."""
     import scipy.linalg
     base = synth.workload(args.headline or "matern3d_1m")
     for item in args.lanczos.split(","):
-        n, steps = (int(v) for v in item.split(":"))
+        parts = [int(v) for v in item.split(":")]
+        n, steps = parts[0], parts[1]
+        cycles = parts[2] if len(parts) > 2 else 0
         w = base.scaled(n)
         P = w.make_points()
         pts = torch.from_numpy(P).cuda()
         g = H2Matrix(pts, w.kernel, w.length_scale, w.shift, w.leaf, w.eta, w.cheb_m)
+        start = {"kind": "random (seed 11)"}
+        if cycles > 0:
+            g.setup()
+            b = torch.from_numpy(w.make_rhs()).cuda()
+            v, info = g.solve(b, rtol=1e-8, max_cycles=cycles, raise_on_error=False)
+            av = g.matvec(v)
+            torch.cuda.synchronize()
+            start = {"kind": f"iterate of {cycles} FP64 V-cycles (CG smoother) on A x = b",
+                     "status": info["status"], "rel_residual": info["rel_residual"],
+                     "rayleigh": float((v @ av) / (v @ v))}
+            log(f"lanczos start: {start}")
+            del b, av
+        else:
+            v = torch.from_numpy(synth.normal_vector(n, 11)).cuda()
         V = torch.empty((steps + 1, n), dtype=torch.float64, device="cuda")
-        v = torch.from_numpy(synth.normal_vector(n, 11)).cuda()
         V[0] = v / v.norm()
         alpha, beta = [], []
         rows = []
@@ -359,10 +381,22 @@ def lanczos_probe(args, torch, synth, H2Matrix):
         ay = g.matvec(y)
         rq = float(y @ ay)
         resid = float((ay - rq * y).norm())
-        out = {"lanczos": w.name, "n": n, "steps": steps, "shift": w.shift,
+        ritz = []
+        for k in range(min(4, steps)):
+            sk = torch.from_numpy(np.ascontiguousarray(S[:, k])).cuda()
+            yk = V[:steps].T @ sk
+            yk /= yk.norm()
+            ayk = g.matvec(yk)
+            tk = float(yk @ ayk)
+            ritz.append({"theta": tk, "residual": float((ayk - tk * yk).norm())})
+        out = {"lanczos": w.name, "n": n, "steps": steps, "shift": w.shift, "start": start,
+               "smallest_ritz_pairs": ritz,
                "ritz_min": float(th[0]), "ritz_max": float(th[-1]),
                "ritz_vector_rayleigh": rq, "ritz_vector_residual": resid,
-               "certified_indefinite": bool(rq + resid < 0),
+               # a Rayleigh quotient bounds lambda_min from above: rq < 0 proves
+               # an eigenvalue below zero; [rq - resid, rq + resid] holds one
+               "certified_indefinite": bool(rq < 0),
+               "eigenvalue_interval": [rq - resid, rq + resid],
                "smallest_shift_estimate": w.shift - rq,
                "history": rows, "seconds": round(time.perf_counter() - t0, 1)}
         print(json.dumps(out), flush=True)
@@ -437,6 +471,58 @@ def many_rhs_solve(args, torch, g, w, single_s):
     log(f"16 right-hand sides at once ({args.mixed}+fp64 refinement): {dt:.2f} s, {info['cycles']} cycles, "
         f"{info['status']}, {16 * single_s / dt:.2f}x the throughput of single solves")
     del X, B
+    return out
+
+
+def galerkin_flops(P, leaf, eta, m, dim):
+    """Algorithmic FP64 flops of the setup's Galerkin products on the tree of
+    P (2 flops per multiply-add, zero padding not counted): the couplings
+    R_s K R_t^T of the far pairs (4 r^3 each), the projected close leaf blocks
+    Q_s^T K_st Q_t (2 r n_s n_t + 2 r^2 n_s), and the projected blocks above
+    the leaves, [E_c]^T [M_cc'] [E_c'] over the 2 x 2 child blocks (12 r^3)."""
+    from paper_2501_17656_amd.h2mg import Plan
+    plan = Plan(P, leaf, eta, m)
+    r = m ** dim
+    L = plan.depth
+    out = {"coupling": 0.0, "pi_leaf": 0.0, "pi_upper": 0.0, "far_blocks": 0, "leaf_blocks": 0,
+           "upper_blocks": 0}
+    for d in range(L + 1):
+        far = plan.pairs(d, True)
+        near = plan.pairs(d, False)
+        far_u = int(np.sum(far[:, 0] < far[:, 1])) if len(far) else 0
+        near_u = near[near[:, 0] <= near[:, 1]] if len(near) else near
+        out["far_blocks"] += far_u
+        out["coupling"] += far_u * 4.0 * r ** 3
+        if d == L:
+            sz = np.diff(plan.offsets(L)).astype(np.float64)
+            ns, nt = sz[near_u[:, 0]], sz[near_u[:, 1]]
+            out["pi_leaf"] = float(np.sum(2.0 * r * ns * nt + 2.0 * r * r * ns))
+            out["leaf_blocks"] = int(len(near_u))
+        elif plan.d_top >= 0 and d >= plan.d_top:
+            out["upper_blocks"] += int(len(near_u))
+            out["pi_upper"] += len(near_u) * 12.0 * r ** 3
+    return out
+
+
+def setup_only(args, torch, synth, H2Matrix):
+    """Build and hierarchy setup of the timed workload, timed, with the
+    algorithmic flops of the Galerkin products (for profiling the setup
+    kernels)."""
+    w = synth.workload(args.workload)
+    P = w.make_points()
+    pts = torch.from_numpy(P).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = H2Matrix(pts, w.kernel, w.length_scale, w.shift, w.leaf, w.eta, w.cheb_m)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g.setup(("fp64", args.mixed))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out = {"workload": w.name, "n": w.n, "rank": w.rank, "build_s": round(t1 - t0, 3),
+           "setup_s": round(t2 - t1, 3), "levels": g.levels,
+           "galerkin_flops": galerkin_flops(P, w.leaf, w.eta, w.cheb_m, w.dim)}
+    g.close()
     return out
 
 
@@ -1077,6 +1163,9 @@ def main(argv=None):
         return
     if args.error_components:
         error_components(args, torch, synth, H2Matrix)
+        return
+    if args.setup_only:
+        print(json.dumps({"setup": setup_only(args, torch, synth, H2Matrix)}), flush=True)
         return
     if args.block_product:
         print(json.dumps({"block_product": block_product_only(args, torch, synth, H2Matrix)}), flush=True)

@@ -7,7 +7,6 @@
 #include <cmath>
 #include <new>
 #include <stdexcept>
-#include <unordered_map>
 
 #include "h2_build.h"
 
@@ -660,38 +659,49 @@ h2mg_status setup_mg(H2& h, int precision_mask) {
     if (!h.mg_built) {
       if (h.d_top >= 0) {
         launch_pi_leaf(h);
-        // child block lookup: (row gid, col gid) -> block id, per depth
-        for (int d = h.L - 1; d >= h.d_top; --d) {
-          std::unordered_map<int64_t, int> idx;
-          auto key = [](int a, int b) { return (int64_t(a) << 32) | uint32_t(b); };
-          for (int pass = 0; pass < 2; ++pass) {
-            const int f = pass == 0 ? h.s_first[d + 1] : h.p_first[d + 1];
-            const int c = pass == 0 ? h.s_count[d + 1] : h.p_count[d + 1];
-            for (int b = f; b < f + c; ++b) idx[key(h.blk_row_h[b], h.blk_col_h[b])] = b;
+        // child block lookup: (row gid, col gid) -> block id.  The coupling
+        // and close blocks of a depth are each sorted by (row, column) (the
+        // plan sorts its pair lists), so a binary search finds a child.
+        auto key = [](int a, int b) { return (int64_t(a) << 32) | uint32_t(b); };
+        auto find_block = [&](int first, int count, int64_t k) {
+          int lo = first, hi = first + count;
+          while (lo < hi) {
+            const int mid = lo + (hi - lo) / 2;
+            if (key(h.blk_row_h[mid], h.blk_col_h[mid]) < k) lo = mid + 1;
+            else hi = mid;
           }
-          std::vector<int> cmap;
+          return lo < first + count && key(h.blk_row_h[lo], h.blk_col_h[lo]) == k ? lo : -1;
+        };
+        // all maps first (host work that may throw), then the launches
+        std::vector<std::vector<int>> host_maps;   // alive until the copies are done
+        for (int d = h.L - 1; d >= h.d_top; --d) {
+          auto child = [&](int cs, int ct) {
+            const int64_t k = key(cs, ct);
+            int b = find_block(h.s_first[d + 1], h.s_count[d + 1], k);
+            if (b < 0) b = find_block(h.p_first[d + 1], h.p_count[d + 1], k);
+            if (b < 0) throw std::runtime_error("child block not found");
+            return b;
+          };
+          host_maps.emplace_back();
+          std::vector<int>& cmap = host_maps.back();
           cmap.reserve(size_t(h.p_count[d]) * 4);
           for (int b = h.p_first[d]; b < h.p_first[d] + h.p_count[d]; ++b) {
             const int gs = h.blk_row_h[b], gt = h.blk_col_h[b];
             for (int a = 0; a < 2; ++a)
               for (int bb = 0; bb < 2; ++bb) {
                 const int cs = 2 * gs + 1 + a, ct = 2 * gt + 1 + bb;
-                if (cs <= ct) {
-                  auto it = idx.find(key(cs, ct));
-                  if (it == idx.end()) throw std::runtime_error("child block not found");
-                  cmap.push_back(it->second);
-                } else {
-                  auto it = idx.find(key(ct, cs));
-                  if (it == idx.end()) throw std::runtime_error("child block not found");
-                  cmap.push_back(-it->second - 1);
-                }
+                cmap.push_back(cs <= ct ? child(cs, ct) : -child(ct, cs) - 1);
               }
           }
-          int* dmap = upload(h, cmap);
-          launch_pi_upper(h, d, dmap);
-          hip_check(hipStreamSynchronize(h.stream), "pi_upper");
-          h.arena.release(dmap);
         }
+        std::vector<int*> maps;
+        for (int d = h.L - 1, k = 0; d >= h.d_top; --d, ++k) {
+          maps.push_back(upload(h, host_maps[k]));
+          // stream order: depth d reads the blocks depth d + 1 wrote
+          launch_pi_upper(h, d, maps.back());
+        }
+        hip_check(hipStreamSynchronize(h.stream), "pi_upper");
+        for (int* m : maps) h.arena.release(m);
         h.Nl = int64_t(1 << h.d_top) * h.r;
         h.levels = h.L - h.d_top + 2;
       } else {

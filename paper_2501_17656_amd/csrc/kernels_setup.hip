@@ -300,12 +300,23 @@ __device__ __forceinline__ void galerkin_wave(const Acc& acc, int ni, int nj, d4
     d4 w[RS];
 #pragma unroll
     for (int c = 0; c < RS; ++c) w[c] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int j0 = 0; j0 < nj; j0 += 4) {
-      const int j = j0 + lk;
-      const double a = acc.k(row, i0 + li, j);
+    // operands of k-step j0 + 4 are fetched (and K evaluated) while the
+    // matrix cores run k-step j0
+    double a = acc.k(row, i0 + li, lk), q[RS];
 #pragma unroll
-      for (int c = 0; c < RS; ++c)
-        w[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, acc.qt(j, c * 16 + li), w[c], 0, 0, 0);
+    for (int c = 0; c < RS; ++c) q[c] = acc.qt(lk, c * 16 + li);
+    for (int j0 = 0; j0 < nj; j0 += 4) {
+      const int jn = j0 + 4 + lk;
+      const bool more = j0 + 4 < nj;
+      const double an = more ? acc.k(row, i0 + li, jn) : 0.0;
+      double qn[RS];
+#pragma unroll
+      for (int c = 0; c < RS; ++c) qn[c] = more ? acc.qt(jn, c * 16 + li) : 0.0;
+#pragma unroll
+      for (int c = 0; c < RS; ++c) w[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, q[c], w[c], 0, 0, 0);
+      a = an;
+#pragma unroll
+      for (int c = 0; c < RS; ++c) q[c] = qn[c];
     }
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -397,6 +408,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
 
 // Projected close leaf blocks: K = the kernel (shift on the diagonal of a
 // diagonal pair), QS / QT the orthonormal leaf bases (row-major, per point).
+// KIND >= 0: the kernel fixed at compile time (point values, no derivative);
+// KIND < 0: the general close entry (derivative kernels, quadrature).
+template <int KIND>
 struct LeafAcc {
   const double* pts; const double* Qr;
   KernelParams kp; PointScale ps;
@@ -421,13 +435,18 @@ struct LeafAcc {
         const double dx = p.x[a] - pts[size_t(t0 + j) * dim + a];
         r2 += dx * dx;
       }
-    return near_entry(kp, ps, dim, r2, s0 + i, t0 + j, diag && i == j);
+    const bool self = diag && i == j;
+    if constexpr (KIND >= 0)
+      return scaled_entry(kernel_fixed<KIND, DER_NONE, double>(kp.inv_l, kp.inv_2l2, r2), s0 + i, t0 + j,
+                          self, ps, kp.shift);
+    else
+      return near_entry(kp, ps, dim, r2, s0 + i, t0 + j, self);
   }
   __device__ __forceinline__ double qs(int i, int mu) const { return i < ns && mu < r ? Qr[size_t(s0 + i) * r + mu] : 0.0; }
   __device__ __forceinline__ double qt(int j, int nu) const { return j < nt && nu < r ? Qr[size_t(t0 + j) * r + nu] : 0.0; }
 };
 
-template <int RS>
+template <int RS, int KIND>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_pi_leaf(
     int b0, int nb, const int* __restrict__ blk_row, const int* __restrict__ blk_col, int gid0,
     const int* __restrict__ leaf_off, const double* __restrict__ pts, int dim, int r, int T,
@@ -437,7 +456,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
   const int b = b0 + w;
   const int ls = blk_row[b] - gid0, lt = blk_col[b] - gid0;
   const int s0 = leaf_off[ls], t0 = leaf_off[lt];
-  const LeafAcc acc{pts, Qr, kp, ps, s0, leaf_off[ls + 1] - s0, t0, leaf_off[lt + 1] - t0, dim, r, ls == lt};
+  const LeafAcc<KIND> acc{pts, Qr, kp, ps, s0, leaf_off[ls + 1] - s0, t0, leaf_off[lt + 1] - t0, dim, r,
+                          ls == lt};
   d4 out[RS][RS];
   galerkin_wave<RS>(acc, (acc.ns + 15) & ~15, (acc.nt + 3) & ~3, out);
   store_galerkin<RS>(out, r, T, tile_ptr(blk, b, T));
@@ -844,12 +864,17 @@ void launch_gather_rows(H2& h, int width, const double* user, double* tree) {
 void launch_pi_leaf(H2& h) {
   const int nb = h.p_count[h.L];
   if (nb == 0) return;
+  const PointScale ps = near_scale(h);
+  auto go = [&](auto rs, auto kc) {
+    constexpr int RS = decltype(rs)::value, KIND = decltype(kc)::value;
+    hipLaunchKernelGGL((k_pi_leaf<RS, KIND>), wave_grid(nb), dim3(NT), 0, h.stream, h.p_first[h.L], nb,
+                       h.blk_row, h.blk_col, h.nleaf - 1, h.leaf_off, h.pts, h.dim, h.r, h.T, h.kp, ps,
+                       static_cast<const double*>(h.prec[P64].Qr), static_cast<double*>(h.prec[P64].blk));
+  };
   with_slabs(h.T, [&](auto rs) {
-    constexpr int RS = decltype(rs)::value;
-    hipLaunchKernelGGL(k_pi_leaf<RS>, wave_grid(nb), dim3(NT), 0, h.stream, h.p_first[h.L], nb,
-                       h.blk_row, h.blk_col, h.nleaf - 1, h.leaf_off, h.pts, h.dim, h.r, h.T, h.kp,
-                       near_scale(h), static_cast<const double*>(h.prec[P64].Qr),
-                       static_cast<double*>(h.prec[P64].blk));
+    using I = int;
+    if (ps.qy || h.kp.deriv != DER_NONE) go(rs, std::integral_constant<I, -1>{});
+    else dispatch_kernel(h.kp.kind, DER_NONE, [&](auto kc, auto) { go(rs, kc); });
   });
   check_launch("pi_leaf");
 }
