@@ -70,6 +70,8 @@ def parse(argv=None):
     ap.add_argument("--spd-probe", default="",
                     help="n:cycles:shift,... run FP64 V-cycles of the headline shape and report "
                          "the Rayleigh quotient of the final iterate")
+    ap.add_argument("--shift-scan", default="",
+                    help="s1,s2,...: time-to-1e-8 of the headline shape at these diagonal shifts")
     ap.add_argument("--lanczos", default="",
                     help="n:steps,... Lanczos on the library's matvec of the headline matrix: "
                          "extreme Ritz values of A_H2")
@@ -310,6 +312,45 @@ def spd_probe(args, torch, synth, H2Matrix):
         torch.cuda.empty_cache()
 
 
+def shift_scan(args, torch, synth, H2Matrix):
+    """Time-to-1e-8 of the headline shape at other diagonal shifts: for each
+    shift, build and hierarchy setup, then the mixed-precision and the FP64
+    solve with the block smoother (at most --max-cycles cycles each), with
+    status, cycles, time and, for an iterate that did not converge, its
+    Rayleigh quotient (negative: A_H2 is indefinite at that shift)."""
+    import dataclasses
+    base = synth.workload(args.headline or "matern3d_1m")
+    for shift in (float(v) for v in args.shift_scan.split(",")):
+        w = dataclasses.replace(base, shift=shift)
+        pts = torch.from_numpy(w.make_points()).cuda()
+        b = torch.from_numpy(w.make_rhs()).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = H2Matrix(pts, w.kernel, w.length_scale, w.shift, w.leaf, w.eta, w.cheb_m)
+        g.setup(("fp64", args.mixed))
+        torch.cuda.synchronize()
+        out = {"shift_scan": w.name, "n": w.n, "shift": shift,
+               "build_and_setup_s": round(time.perf_counter() - t0, 2)}
+        for prec in (args.mixed, "fp64"):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            x, info = g.solve(b, rtol=1e-8, max_cycles=args.max_cycles, precision=prec,
+                              smoother="bj", raise_on_error=False)
+            torch.cuda.synchronize()
+            row = {"status": info["status"], "cycles": info["cycles"],
+                   "rel_residual": info["rel_residual"], "s": round(time.perf_counter() - t1, 2),
+                   "history_every_5": [round(v, 5) for v in info["history"][::5]]}
+            if not info["converged"] and bool(torch.isfinite(x).all()) and float(x.norm()) > 0:
+                ax = g.matvec(x)
+                row["rayleigh"] = float((x @ ax) / (x @ x))
+            out[prec] = row
+            log(f"shift {shift} {prec}: {row['status']} {row['cycles']} cycles {row['s']} s")
+        print(json.dumps(out), flush=True)
+        g.close()
+        del pts, b
+        torch.cuda.empty_cache()
+
+
 def lanczos_probe(args, torch, synth, H2Matrix):
     """Extreme eigenvalues of A_H2 for the headline shape (shift as specified)
     by Lanczos on the library's FP64 matvec, with full reorthogonalisation
@@ -434,12 +475,22 @@ def block_product(args, torch, g, w, single_ms):
     flops = tile_bytes / 8.0 * 4.0 * 16.0
     g.set_timing(False)
     tuning = g.block_tuning()
+    # every tile also reads its column's 64 x 16 operand block and, off the
+    # diagonal, writes a 64 x 16 column contribution (FP64): the pass moves
+    # tiles + 8 KiB per tile + 8 KiB per off-diagonal tile (the diagonal
+    # tiles are those of a 64-point chunk with itself, n / 64 of them)
+    ntiles = tile_bytes / 32768.0
+    vec_bytes = 64 * 16 * 8.0 * (2.0 * ntiles - g.n / 64.0)
     return {"ms": round(ms, 3), "ms_per_vector": round(ms / 16, 3),
             "speedup_vs_16_single_products": round(16 * single_ms / ms, 2),
             "tile_runs": {k: v["run"] for k, v in tuning.items()},
             "near_tile_products_ms": round(near_ms, 3),
             "near_tiles_algorithmic_gbs": round(tile_bytes / (near_ms * 1e-3) / 1e9, 1),
             "near_tiles_frac_of_hbm_peak": round(tile_bytes / (near_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3),
+            "near_pass_bytes_with_vectors_gb": round((tile_bytes + vec_bytes) / 1e9, 2),
+            "near_pass_with_vectors_gbs": round((tile_bytes + vec_bytes) / (near_ms * 1e-3) / 1e9, 1),
+            "near_pass_with_vectors_frac_of_hbm_peak":
+                round((tile_bytes + vec_bytes) / (near_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3),
             "near_mfma_tflops": round(flops / (near_ms * 1e-3) / 1e12, 2),
             "near_mfma_frac_of_fp64_peak": round(flops / (near_ms * 1e-3) / 1e12 / 78.6, 3)}
 
@@ -1154,6 +1205,9 @@ def main(argv=None):
         return
     if args.lanczos:
         lanczos_probe(args, torch, synth, H2Matrix)
+        return
+    if args.shift_scan:
+        shift_scan(args, torch, synth, H2Matrix)
         return
     if args.growth:
         growth_scan(args, torch, synth, H2Matrix)

@@ -97,8 +97,9 @@ __device__ inline int reduced_index(int a) {
 // FULL: r == 8T (no padding, no guards).  Each iteration requests its tile
 // first, then the coefficients of its column (the next column index is
 // prefetched by a scalar load), so one tile is in flight per wave while the
-// previous is consumed; FP32/BF16 tiles use non-temporal loads (measured
-// faster there, slower for FP64 tiles).
+// previous is consumed.  Every tile is read once per launch, with
+// non-temporal loads (measured faster than ordinary loads for FP64, FP32 and
+// BF16 tiles alike on the same machine and run).
 template <int T, bool FULL, typename Tb, typename Tv>
 __device__ __forceinline__ void bsr_gemv_wave(const int* __restrict__ tasks, int ntasks,
                                               const Tb* __restrict__ blk,
@@ -106,7 +107,7 @@ __device__ __forceinline__ void bsr_gemv_wave(const int* __restrict__ tasks, int
                                               const int* __restrict__ blk_slot,
                                               const Tv* __restrict__ x, Tv* __restrict__ partial,
                                               Tv* __restrict__ colpart, int r) {
-  constexpr bool NTL = sizeof(Tb) < 8;
+  constexpr bool NTL = true;
   const int wave = __builtin_amdgcn_readfirstlane(int((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   if (wave >= ntasks) return;
   const int lane = threadIdx.x & 63;
