@@ -109,6 +109,9 @@ def parse(argv=None):
     ap.add_argument("--bem-grid", type=int, nargs=2, default=[1000, 500],
                     help="torus parameter grid (panels = 2 * a * b)")
     ap.add_argument("--json-out", default="")
+    ap.add_argument("--extras-only", action="store_true",
+                    help="run only the requested extras that build matrices of their own "
+                         "(--c1, --diff, --bem, --batched-first, --part-a), not the timed workload")
     ap.add_argument("--setup-only", action="store_true",
                     help="run only the build and hierarchy setup of the timed workload")
     ap.add_argument("--block-product", action="store_true",
@@ -1233,6 +1236,13 @@ def main(argv=None):
         return
 
     extras = extras_requested(args)
+    if args.extras_only:
+        out = run_extras_alone(args, extras, torch, synth, H2Matrix)
+        print(json.dumps(out), flush=True)
+        if args.json_out:
+            with open(args.json_out, "w") as f:
+                f.write(json.dumps(out) + "\n")
+        return
     deadline = T_START + args.budget_s
     # seconds kept after the timed solves: instrumented steps, oracle baseline
     reserve = 12.0 + (0.0 if args.no_cpu else args.cpu_seconds + 25.0)
