@@ -140,10 +140,12 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def profiled_traffic(kind):
-    """HBM bytes per launch of the block GEMV measured by rocprofv3 counters
-    (profiles/gemv_counters_*.md), or None when the kernel source changed
-    since the counters were taken."""
+def profiled_traffic(kind, avg_bytes):
+    """HBM bytes (read + write) per launch of the block GEMV, from the
+    rocprofv3 counters in profiles/gemv_counters_*.md: their ratio of HBM to
+    algorithmic bytes applied to this run's algorithmic bytes per launch
+    (the same kernels, another mix of launches).  None when the kernel source
+    changed since the counters were taken."""
     import glob
     import hashlib
     import re
@@ -156,9 +158,10 @@ def profiled_traffic(kind):
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "gemv_counters_*.md"))):
         with open(path) as fh:
             for line in fh:
-                m = re.match(r"\s*traffic (\S+) src=(\S+) per_launch_bytes=(\S+)", line)
+                m = re.match(r"\s*traffic (\S+) src=(\S+) per_launch_bytes=(\S+) alg_per_launch_bytes=(\S+)",
+                             line)
                 if m and m.group(1) == kind and m.group(2) == cur:
-                    return float(m.group(3))
+                    return round(avg_bytes * float(m.group(3)) / float(m.group(4)))
     return None
 
 
@@ -171,7 +174,7 @@ def block_gemv_roofline(g, kind, bytes_per_sec_peak=HBM_PEAK_GBS):
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": bytes_per_sec_peak,
             "unit": "GB/s", "frac": round(achieved / bytes_per_sec_peak, 4),
-            "traffic": profiled_traffic(kind),
+            "traffic": profiled_traffic(kind, avg_bytes),
             "kernel": "k_near_gemv" if kind.startswith("near") else f"k_bsr_gemv ({kind})",
             "launches": st["launches"],
             "avg_launch_ms": round(avg_ms, 4), "avg_bytes_per_launch": avg_bytes}
@@ -1308,6 +1311,8 @@ def main(argv=None):
             raise_on_error=False)
     rl64 = block_gemv_roofline(g, "gemv_fp64")
     g.set_timing(False)
+    log(f"instrumented steps: {args.mixed} GEMV {(rlm or {}).get('frac')}, "
+        f"fp64 GEMV {(rl64 or {}).get('frac')} of HBM peak")
 
     extra = run_extras(args, extras, torch, synth, H2Matrix, g, w, b_d, mixed_s)
     dx = float((xm - x64).norm() / x64.norm())
