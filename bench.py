@@ -843,7 +843,7 @@ def growth_scan(args, torch, synth, H2Matrix):
     V-cycles (paper CG smoother and block smoother) next to the comparison
     solver, CG (and block-Jacobi PCG) on A_H2 alone.  FP64; the near field is
     stored when it fits, which speeds up every fine-level product alike."""
-    base = synth.workload("matern3d_1m_spd")
+    base = synth.workload("matern3d_1m_shift1")
     for n in [int(v) for v in args.growth.split(",")]:
         w = base.scaled(n)
         pts = torch.from_numpy(w.make_points()).cuda()
@@ -926,7 +926,7 @@ def differentiation(args, torch, synth, H2Matrix):
 def smoothing_sweep(args, torch, synth, H2Matrix):
     """Time-to-1e-8 against the smoothing counts (n_f, n_c) on the shift-1
     Matern problem at 2^20: each item smoother:precision:n_f:n_c."""
-    w = synth.workload("matern3d_1m_spd")
+    w = synth.workload("matern3d_1m_shift1")
     pts = torch.from_numpy(w.make_points()).cuda()
     b = torch.from_numpy(w.make_rhs()).cuda()
     g = H2Matrix(pts, w.kernel, w.length_scale, w.shift, w.leaf, w.eta, w.cheb_m)
@@ -1339,7 +1339,8 @@ def main(argv=None):
         "config": {
             "workload": (f"{w.name}: N={w.n} points uniform in [0,1)^{w.dim} (seed {w.point_seed}), "
                          f"{w.kernel} l={w.length_scale} + {w.shift}*I (shift raised from 1e-3: the "
-                         f"rank-64 Chebyshev approximation of the 1e-3 matrix is indefinite), leaf "
+                         f"rank-64 Chebyshev approximation has eigenvalues down to -0.0936 at this size, "
+                         f"so shifts below 0.095 are indefinite), leaf "
                          f"{w.leaf}, eta {w.eta}, Chebyshev {w.cheb_m}^{w.dim} (rank {w.rank}), "
                          f"b ~ N(0,1) (seed {w.rhs_seed}), x0 = 0, rtol 1e-8, n_f=1, n_c=40, smoother "
                          f"{args.smoother} ({'CG preconditioned by the diagonal blocks' if args.smoother == 'bj' else 'plain CG'}); "

@@ -152,10 +152,15 @@ WORKLOADS = {
     "matern3d_1m": Workload("matern3d_1m", 1 << 20, 3, "matern32", 0.2, 1e-3,
                             128, 0.7, 4),
     # the same points, kernel and H2 parameters with the diagonal shift raised
-    # to 1: the rank-64 Chebyshev approximation of the 1e-3-shift matrix is
-    # indefinite at this size, this one stays positive definite
-    "matern3d_1m_spd": Workload("matern3d_1m_spd", 1 << 20, 3, "matern32", 0.2, 1.0,
+    # to 0.3: the rank-64 Chebyshev approximation of the 1e-3-shift matrix has
+    # eigenvalues down to -0.0936 at this size, so every shift below 0.095 is
+    # indefinite; at 0.1 (smallest eigenvalue about 0.005) the V-cycle needs
+    # hundreds of cycles, at 0.3 it converges in about 25
+    "matern3d_1m_spd": Workload("matern3d_1m_spd", 1 << 20, 3, "matern32", 0.2, 0.3,
                                 128, 0.7, 4),
+    # the same with the shift raised to 1 (solver growth and smoothing sweeps)
+    "matern3d_1m_shift1": Workload("matern3d_1m_shift1", 1 << 20, 3, "matern32", 0.2, 1.0,
+                                   128, 0.7, 4),
     # Gaussian-kernel problem on Gaussian-mixture clouds (rank 27, leaf 64)
     "gauss3d_gmm": Workload("gauss3d_gmm", 65536, 3, "gauss", 0.1, 1e-2, 64,
                             0.7, 3, points="gmm"),

@@ -6,8 +6,8 @@ block rows of one leaf) costs O(n_leaf * n), so rows of a few leaves can be
 checked at any size.  Checked here, in the launch configuration the
 benchmark times:
   * matvec rows, near field evaluated and near field stored (1e-12 relative);
-  * after the FP64 solve and the mixed-precision solve of the shift-1
-    variant, the residual rows b - A_H2 x recomputed by the oracle: small (the
+  * after the FP64 solve and the mixed-precision solve of the timed
+    workload (diagonal shift 0.3), the residual rows b - A_H2 x recomputed by the oracle: small (the
     solve's 1e-8 target, with a margin for sampling a few rows) and equal to
     the library's own residual rows up to rounding.
 """
@@ -62,8 +62,9 @@ def test_matvec_rows_at_full_size():
 
 
 def test_solution_residual_rows_at_full_size():
-    """FP64 solve and FP32-refinement solve of the shift-1 variant (the timed
-    workload) on one build; for both, the oracle's residual rows."""
+    """FP64 solve and FP32-refinement solve of the timed workload (the headline
+    shape with the diagonal shift raised to 0.3) on one build; for both, the
+    oracle's residual rows."""
     from paper_2501_17656_amd import H2Matrix
     w = synth.workload("matern3d_1m_spd")
     P, b = w.make_points(), w.make_rhs()
