@@ -106,3 +106,34 @@ def test_timed_solves_respect_the_budget():
     FakeG.calls = 0
     warm, times, infos, x = bench.timed_solves(args, FakeTorch, FakeG(), None, _t.perf_counter() + 3600)
     assert warm == 5 and len(times) == 20 and FakeG.calls == 25
+
+
+def test_galerkin_flop_count_matches_the_oracle_partition():
+    """The setup profile's flop counts (bench.galerkin_flops, from the
+    library's plan) against the same formulas over the oracle's own tree and
+    partition: 4 r^3 per far pair, 2 r n_s n_t + 2 r^2 n_s per close leaf
+    pair, 12 r^3 per close pair above the leaves, upper triangles only."""
+    sys.path.insert(0, ROOT)
+    import bench
+    import synth
+    from oracle.partition import build_partition
+    from oracle.tree import build_tree
+    P = synth.uniform_points(6000, 3, 5)
+    leaf, eta, m = 64, 0.7, 3
+    r = m ** 3
+    got = bench.galerkin_flops(P, leaf, eta, m, 3)
+    tree = build_tree(P, leaf)
+    part = build_partition(tree, eta)
+    L = tree.L
+    far = sum(int(np.sum(np.asarray(part.far[d])[:, 0] < np.asarray(part.far[d])[:, 1]))
+              for d in range(L + 1) if len(part.far[d]))
+    near_l = np.asarray(part.near[L])
+    near_l = near_l[near_l[:, 0] <= near_l[:, 1]]
+    sizes = np.diff(np.asarray(tree.offsets[L])).astype(np.float64)
+    ns, nt = sizes[near_l[:, 0]], sizes[near_l[:, 1]]
+    upper = sum(int(np.sum(np.asarray(part.near[d])[:, 0] <= np.asarray(part.near[d])[:, 1]))
+                for d in range(part.d_top, L))
+    assert got["far_blocks"] == far and got["coupling"] == far * 4.0 * r ** 3
+    assert got["leaf_blocks"] == len(near_l)
+    assert got["pi_leaf"] == float(np.sum(2.0 * r * ns * nt + 2.0 * r * r * ns))
+    assert got["upper_blocks"] == upper and got["pi_upper"] == upper * 12.0 * r ** 3
