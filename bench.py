@@ -672,13 +672,13 @@ def batched(args, torch, synth, H2Matrix, n_problems=None):
         sizes = sizes[:n_problems]       # the first problems of the same sequence
     shift = args.batch_shift
     budget = args.batch_budget_gb * 1e9
-    t_build = t_batch = t_seq = t_single = t_onelaunch = 0.0
+    t_build = t_batch = t_seq = t_single = t_onelaunch = t_onelaunch_eager = 0.0
     group_equal = []
     per = []
     group = []
 
     def solve_group():
-        nonlocal t_batch, t_seq, t_single, t_onelaunch
+        nonlocal t_batch, t_seq, t_single, t_onelaunch, t_onelaunch_eager
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         xs, infos = solve_batch([(g, B) for g, B, _ in group], rtol=1e-8, precision="fp32",
@@ -700,6 +700,20 @@ def batched(args, torch, synth, H2Matrix, n_problems=None):
         group_equal.append(same)
         log(f"batched: the same group with one launch per tile-product step: {dtg:.2f} s, "
             f"bitwise equal to the stream solves: {same}")
+        # and launched kernel by kernel (no cycle graphs)
+        for g, _, _ in group:
+            g.set_graphs(False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xe, _ = solve_batch([(g, B) for g, B, _ in group], rtol=1e-8, precision="fp32",
+                            smoother="bj", raise_on_error=False, mode="group")
+        torch.cuda.synchronize()
+        dte = time.perf_counter() - t0
+        t_onelaunch_eager += dte
+        for g, _, _ in group:
+            g.set_graphs(True)
+        group_equal.append(all(bool(torch.equal(a, b)) for a, b in zip(xs, xe)))
+        log(f"batched: the same, kernel by kernel: {dte:.2f} s")
         for (g, B, i), info in zip(group, infos):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -771,6 +785,7 @@ def batched(args, torch, synth, H2Matrix, n_problems=None):
         "batched_solve_s": round(t_batch, 3),
         "rhs_per_s_batched": round(nrhs_total / t_batch, 2),
         "one_launch_per_step_solve_s": round(t_onelaunch, 3),
+        "one_launch_per_step_kernel_by_kernel_s": round(t_onelaunch_eager, 3),
         "rhs_per_s_one_launch_per_step": round(nrhs_total / t_onelaunch, 2),
         "one_launch_per_step_bitwise_equal": all(group_equal),
         "sequential_block_solves_s": round(t_seq, 3),

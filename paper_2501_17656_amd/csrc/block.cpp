@@ -484,6 +484,80 @@ struct GM {
   Work16* w;
 };
 
+// Lanes for the members' own launches: a section of per-member launches is
+// bracketed by a fork (every lane stream waits for the group's stream, and
+// member i launches on lane i mod L) and a join (the group's stream waits for
+// every lane, and the members launch on the group's stream again).  Sections
+// of different members then overlap, while each group launch stays ordered
+// after every member's preceding work and before its following work.  Under
+// stream capture the event record / wait pairs become graph edges.
+struct GroupLanes {
+  std::vector<hipStream_t> lane;
+  std::vector<hipEvent_t> join_ev;
+  hipEvent_t fork_ev = nullptr;
+  hipStream_t main = nullptr;
+  bool open = false;
+
+  void create(int n) {
+    for (int l = 0; l < n; ++l) {
+      hipStream_t s = nullptr;
+      hip_check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "lane stream");
+      lane.push_back(s);
+      hipEvent_t e = nullptr;
+      hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "lane event");
+      join_ev.push_back(e);
+    }
+    hip_check(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming), "lane event");
+  }
+  void destroy() {
+    for (hipStream_t s : lane) (void)hipStreamDestroy(s);
+    for (hipEvent_t e : join_ev) (void)hipEventDestroy(e);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
+    lane.clear();
+    join_ev.clear();
+    fork_ev = nullptr;
+  }
+  void fork(const std::vector<H2*>& hs) {
+    main = hs[0]->stream;
+    hip_check(hipEventRecord(fork_ev, main), "fork");
+    for (hipStream_t s : lane) hip_check(hipStreamWaitEvent(s, fork_ev, 0), "fork");
+    for (size_t i = 0; i < hs.size(); ++i) hs[i]->stream = lane[i % lane.size()];
+    open = true;
+  }
+  void join(const std::vector<H2*>& hs) {
+    for (size_t l = 0; l < lane.size(); ++l) {
+      hip_check(hipEventRecord(join_ev[l], lane[l]), "join");
+      hip_check(hipStreamWaitEvent(main, join_ev[l], 0), "join");
+    }
+    for (H2* h : hs) h->stream = main;
+    open = false;
+  }
+};
+
+// The lanes of the group solve running on this thread (none outside it).
+thread_local GroupLanes* t_lanes = nullptr;
+constexpr int GROUP_LANES = 4;       // lane streams of a group solve
+
+// A section of per-member launches: forked on construction, joined by end().
+class MemberSection {
+ public:
+  template <typename V, typename F>
+  MemberSection(const V& members, F h_of) {
+    for (const auto& m : members) hs_.push_back(h_of(m));
+    on_ = t_lanes && hs_.size() > 1;
+    if (on_) t_lanes->fork(hs_);
+  }
+  explicit MemberSection(const std::vector<GM>& G) : MemberSection(G, [](const GM& m) { return m.h; }) {}
+  void end() {
+    if (on_) t_lanes->join(hs_);
+    on_ = false;
+  }
+
+ private:
+  std::vector<H2*> hs_;
+  bool on_ = false;
+};
+
 // Y_m = A_k X_m for every member (each at its own level k).
 void apply16_group(const std::vector<GM>& G, int p, int k, const std::vector<const void*>& X,
                    const std::vector<void*>& Y, double alpha = 1.0, const std::vector<const void*>* add = nullptr,
@@ -494,6 +568,7 @@ void apply16_group(const std::vector<GM>& G, int p, int k, const std::vector<con
   std::vector<GroupTiles> tiles;
   if (k == 1) {
     std::vector<const void*> yhat(G.size(), nullptr);
+    MemberSection up(G);
     for (size_t i = 0; i < G.size(); ++i) {
       H2& h = *G[i].h;
       BlockWork& w = h.blk16;
@@ -503,8 +578,10 @@ void apply16_group(const std::vector<GM>& G, int p, int k, const std::vector<con
         launch_transfer_up16(h, p, d, at_depth(w.xall, p, d + 1, h.r), at_depth(w.xall, p, d, h.r));
       tiles.push_back(GroupTiles{h.T, &w.fine, h.prec[p].blk, h.r, w.xall, w.partial});
     }
+    up.end();
     launch_tgemm_group(st, p, tiles);
     std::vector<const void*> xc(G.size());
+    MemberSection down(G);
     for (size_t i = 0; i < G.size(); ++i) {
       H2& h = *G[i].h;
       BlockWork& w = h.blk16;
@@ -522,6 +599,7 @@ void apply16_group(const std::vector<GM>& G, int p, int k, const std::vector<con
         xc[i] = buf;
       }
     }
+    down.end();
     tiles.clear();
     std::vector<GroupTiles> tiles32;
     std::vector<GroupEval> evals;
@@ -535,14 +613,17 @@ void apply16_group(const std::vector<GM>& G, int p, int k, const std::vector<con
     launch_tgemm_group(st, P64, tiles);
     launch_tgemm_group(st, P32, tiles32);
     launch_tgemm_eval_group(st, vp, evals);
+    MemberSection out(G);
     for (size_t i = 0; i < G.size(); ++i) {
       H2& h = *G[i].h;
       BlockWork& w = h.blk16;
       launch_reduce16(h, p, w.near, 64, w.partial, w.yc);
       launch_leaf_down16(h, p, yhat[i], w.yc, Y[i], alpha, add ? (*add)[i] : nullptr, beta);
     }
+    out.end();
     return;
   }
+  MemberSection up(G);
   for (size_t i = 0; i < G.size(); ++i) {
     H2& h = *G[i].h;
     BlockWork& w = h.blk16;
@@ -552,7 +633,9 @@ void apply16_group(const std::vector<GM>& G, int p, int k, const std::vector<con
       launch_transfer_up16(h, p, q, at_depth(w.xall, p, q + 1, r), at_depth(w.xall, p, q, r));
     tiles.push_back(GroupTiles{h.T, &w.coarse[d], h.prec[p].blk, r, w.xall, w.partial});
   }
+  up.end();
   launch_tgemm_group(st, p, tiles);
+  MemberSection down(G);
   for (size_t i = 0; i < G.size(); ++i) {
     H2& h = *G[i].h;
     BlockWork& w = h.blk16;
@@ -563,6 +646,7 @@ void apply16_group(const std::vector<GM>& G, int p, int k, const std::vector<con
                              at_depth(w.yall, p, q, r));
     if (d == h.d_top) launch_copy(h, vp, at_depth(w.yall, p, d, r), Y[i], int64_t(1 << d) * r * NR);
   }
+  down.end();
 }
 
 // cg16 for every member: e = Iter(A_k, rhs, e0) on level k.
@@ -572,8 +656,11 @@ void cg16_group(const std::vector<GM>& G, int k, bool e0_zero, int nsteps) {
   auto N = [&](const GM& m) { return m.h->level_size(k); };
   std::vector<const void*> X(G.size());
   std::vector<void*> Y(G.size());
-  for (const GM& m : G)
-    if (e0_zero) launch_zero(*m.h, vp, m.w->et[k], N(m) * NR);
+  if (e0_zero) {
+    MemberSection zero(G);
+    for (const GM& m : G) launch_zero(*m.h, vp, m.w->et[k], N(m) * NR);
+    zero.end();
+  }
   if (nsteps <= 0) return;
   if (!e0_zero) {
     for (size_t i = 0; i < G.size(); ++i) {
@@ -582,6 +669,7 @@ void cg16_group(const std::vector<GM>& G, int k, bool e0_zero, int nsteps) {
     }
     apply16_group(G, p, k, X, Y);
   }
+  MemberSection init(G);
   for (const GM& m : G) {
     H2& h = *m.h;
     Work16& w = *m.w;
@@ -597,6 +685,7 @@ void cg16_group(const std::vector<GM>& G, int k, bool e0_zero, int nsteps) {
       launch_dot16(h, vp, N(m), w.s, w.s, w.gpart(0));
     }
   }
+  init.end();
   int cur = 0;
   for (int it = 0; it < nsteps; ++it) {
     for (size_t i = 0; i < G.size(); ++i) {
@@ -604,6 +693,7 @@ void cg16_group(const std::vector<GM>& G, int k, bool e0_zero, int nsteps) {
       Y[i] = G[i].w->q;
     }
     apply16_group(G, p, k, X, Y);
+    MemberSection step(G);
     for (const GM& m : G) {
       H2& h = *m.h;
       Work16& w = *m.w;
@@ -620,16 +710,22 @@ void cg16_group(const std::vector<GM>& G, int k, bool e0_zero, int nsteps) {
         if (it + 1 < nsteps) launch_cg_pupdate16(h, vp, n, w.pv, w.s, w.gpart(cur), w.gpart(1 - cur));
       }
     }
+    step.end();
     cur = 1 - cur;
   }
 }
 
 // mg16 for every member, level k down.
 void mg16_group(const std::vector<GM>& all, int k, int kind, int n_f, int n_c) {
-  std::vector<GM> G;
+  std::vector<GM> G, C;
   for (const GM& m : all) {
-    if (k == m.h->levels) coarse_solve16(*m.h, *m.w, m.w->r[k], m.w->et[k]);
+    if (k == m.h->levels) C.push_back(m);
     else if (k < m.h->levels) G.push_back(m);
+  }
+  if (!C.empty()) {
+    MemberSection coarse(C);
+    for (const GM& m : C) coarse_solve16(*m.h, *m.w, m.w->r[k], m.w->et[k]);
+    coarse.end();
   }
   if (G.empty()) return;
   const int p = G[0].w->p, vp = vprec(p);
@@ -642,6 +738,7 @@ void mg16_group(const std::vector<GM>& all, int k, int kind, int n_f, int n_c) {
     Y[i] = G[i].w->tmp;
   }
   apply16_group(G, p, k, X, Y);
+  MemberSection restrict_(G);
   for (const GM& m : G) {
     H2& h = *m.h;
     Work16& w = *m.w;
@@ -649,6 +746,7 @@ void mg16_group(const std::vector<GM>& all, int k, int kind, int n_f, int n_c) {
     if (k == 1) launch_leaf_up16(h, p, w.tmp, w.r[k + 1]);
     else launch_transfer_up16(h, p, h.level_depth(k) - 1, w.tmp, w.r[k + 1]);
   }
+  restrict_.end();
   mg16_group(G, k + 1, kind, n_f, n_c);
   if (kind != CYCLE_V) {
     std::vector<GM> sub;
@@ -657,6 +755,7 @@ void mg16_group(const std::vector<GM>& all, int k, int kind, int n_f, int n_c) {
     if (!sub.empty()) {
       std::vector<const void*> X1(sub.size());
       std::vector<void*> Y1(sub.size());
+      MemberSection save(sub);
       for (size_t i = 0; i < sub.size(); ++i) {
         H2& h = *sub[i].h;
         Work16& w = *sub[i].w;
@@ -664,20 +763,27 @@ void mg16_group(const std::vector<GM>& all, int k, int kind, int n_f, int n_c) {
         X1[i] = w.et[k + 1];
         Y1[i] = w.tmp;
       }
+      save.end();
       apply16_group(sub, p, k + 1, X1, Y1);
+      MemberSection res(sub);
       for (const GM& m : sub)
         launch_axpby(*m.h, vp, m.h->level_size(k + 1) * NR, -1.0, m.w->tmp, 1.0, m.w->r[k + 1]);
+      res.end();
       mg16_group(sub, k + 1, kind == CYCLE_F ? CYCLE_V : CYCLE_W, n_f, n_c);
+      MemberSection add(sub);
       for (const GM& m : sub)
         launch_axpby(*m.h, vp, m.h->level_size(k + 1) * NR, 1.0, m.w->ec[k + 1], 1.0, m.w->et[k + 1]);
+      add.end();
     }
   }
+  MemberSection prolong(G);
   for (const GM& m : G) {
     H2& h = *m.h;
     Work16& w = *m.w;
     if (k == 1) launch_leaf_down16(h, p, w.et[k + 1], nullptr, w.et[k], 1.0, w.et[k], 1.0);
     else launch_transfer_down16(h, p, h.level_depth(k) - 1, w.et[k + 1], w.et[k], w.et[k]);
   }
+  prolong.end();
   cg16_group(G, k, false, nk);
 }
 
@@ -1021,6 +1127,8 @@ h2mg_status solve_group(int nprob, H2* const* hs, const int* nrhs, const double*
   hipStream_t cap = nullptr;
   CycleGraph graph;
   std::vector<int> graph_set;          // members of the captured cycle
+  std::vector<int> eager_set;          // members of the last cycle run kernel by kernel
+  GroupLanes lanes;
   auto record = [&](int i, h2mg_status st) {
     if (st != H2MG_OK && result[i] == H2MG_OK) {
       result[i] = st;
@@ -1028,10 +1136,12 @@ h2mg_status solve_group(int nprob, H2* const* hs, const int* nrhs, const double*
     }
   };
   auto cleanup = [&]() {
+    t_lanes = nullptr;
     graph.reset();
     for (auto& q : bs) q.reset();
     for (int i = 0; i < nprob; ++i) hs[i]->stream = saved[i];
     if (cap) (void)hipStreamDestroy(cap);
+    lanes.destroy();
   };
   const int p = sp.precision == 0 ? P64 : sp.precision == 1 ? P32 : P16;
   bool graphs = true;
@@ -1039,6 +1149,10 @@ h2mg_status solve_group(int nprob, H2* const* hs, const int* nrhs, const double*
   h2mg_status err = H2MG_OK;
   try {
     for (int i = 0; i < nprob; ++i) hs[i]->stream = user;
+    if (nprob > 1) {
+      lanes.create(std::min(nprob, GROUP_LANES));
+      t_lanes = &lanes;
+    }
     for (int i = 0; i < nprob; ++i) {
       bs[i].reset(new BlockSolve);
       const h2mg_status st = bs[i]->begin(*hs[i], nrhs[i], b[i], ldb[i], x[i], ldx[i], sp);
@@ -1082,10 +1196,14 @@ h2mg_status solve_group(int nprob, H2* const* hs, const int* nrhs, const double*
       auto body = [&]() {
         std::vector<GM> G;
         for (int i : next) G.push_back(GM{hs[i], p == P64 ? &bs[i]->w64 : &bs[i]->wlp});
-        if (p != P64)
+        if (p != P64) {
+          MemberSection cast(G);
           for (int i : next)
             launch_cast(*hs[i], P32, bs[i]->wlp.r[1], P64, bs[i]->w64.r[1], int64_t(hs[i]->n) * NR);
+          cast.end();
+        }
         mg16_group(G, 1, sp.method, sp.n_fine, sp.n_coarse);
+        MemberSection update(G);
         for (int i : next) {
           H2& H = *hs[i];
           const int64_t nf = int64_t(H.n) * NR;
@@ -1096,9 +1214,17 @@ h2mg_status solve_group(int nprob, H2* const* hs, const int* nrhs, const double*
             launch_axpby(H, P64, nf, 1.0, bs[i]->w64.tmp, 1.0, bs[i]->xt);
           }
         }
+        update.end();
       };
-      if (graphs) {
-        if (graph_set != next) {
+      // A new active set (a member converged or failed) runs its first cycle
+      // kernel by kernel; the cycle is captured once the set repeats, so sets
+      // that last one cycle never pay for a capture.
+      const bool capture_now = graphs && graph_set != next && next == eager_set;
+      if (graphs && graph_set != next && !capture_now) {
+        eager_set = next;
+        body();
+      } else if (graphs) {
+        if (capture_now) {
           // the active set changed: record the cycle of the new set
           graph.reset();
           if (!cap) hip_check(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "stream create");
