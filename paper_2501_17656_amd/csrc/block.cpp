@@ -51,10 +51,13 @@ T* upload_owned(H2& h, const std::vector<T>& v) {
 // every tile, column-pass tasks the off-diagonal ones; tiles keep their id
 // order within a row or column, and a row's (column's) tasks are
 // consecutive.
-// Read-once form when a tile's transposed product (rr x 16 words) is at most
-// half the stored tile (RP x RP words): writing and reducing it moves less
-// than reading the tile a second time.
-bool use_dual(int T, int rr) { return rr * NR * 2 <= (8 * T) * (8 * T); }
+// Read-once form for 64 x 64 tiles (rank 64 and the near-field tiles): a
+// tile's transposed product (rr x 16 words, a quarter of the tile at rank 64)
+// is written once and reduced once, which moves less than reading the tile a
+// second time.  For 32 x 32 and smaller tiles the two passes are faster
+// (measured at rank 27, where the transposed product is 42% of the padded
+// tile: 12.0-12.3 s against 11.3 s for 13 batched problems).
+bool use_dual(int T, int rr) { return T == 8 && rr * NR * 2 <= (8 * T) * (8 * T); }
 
 TileSet make_set(H2& h, const std::vector<int>& ids, const std::vector<int>& rows, const std::vector<int>& cols,
                  int nrows_total, int row0, int nrows, const int* brow, const int* bcol, int run,
@@ -1128,6 +1131,10 @@ h2mg_status solve_group(int nprob, H2* const* hs, const int* nrhs, const double*
   CycleGraph graph;
   std::vector<int> graph_set;          // members of the captured cycle
   std::vector<int> eager_set;          // members of the last cycle run kernel by kernel
+  hipEvent_t eager_ev[2] = {nullptr, nullptr};
+  double eager_host_ms = 0.0;          // host time to enqueue that cycle
+  bool eager_pending = false;          // its GPU time not read yet
+  bool eager_launch_bound = false;
   GroupLanes lanes;
   auto record = [&](int i, h2mg_status st) {
     if (st != H2MG_OK && result[i] == H2MG_OK) {
@@ -1137,6 +1144,11 @@ h2mg_status solve_group(int nprob, H2* const* hs, const int* nrhs, const double*
   };
   auto cleanup = [&]() {
     t_lanes = nullptr;
+    for (hipEvent_t& e : eager_ev)
+      if (e) {
+        (void)hipEventDestroy(e);
+        e = nullptr;
+      }
     graph.reset();
     for (auto& q : bs) q.reset();
     for (int i = 0; i < nprob; ++i) hs[i]->stream = saved[i];
@@ -1217,12 +1229,35 @@ h2mg_status solve_group(int nprob, H2* const* hs, const int* nrhs, const double*
         update.end();
       };
       // A new active set (a member converged or failed) runs its first cycle
-      // kernel by kernel; the cycle is captured once the set repeats, so sets
-      // that last one cycle never pay for a capture.
-      const bool capture_now = graphs && graph_set != next && next == eager_set;
+      // kernel by kernel, timed on the host (enqueue) and on the GPU.  When
+      // the set repeats, its cycle is captured only if that cycle was
+      // launch-bound (enqueueing took at least 80% of the GPU time): a graph
+      // then saves the launches, while for GPU-bound cycles capturing and
+      // instantiating a graph of every member's launches costs more than it
+      // saves.
+      if (eager_pending) {
+        float ms = 0.0f;
+        hip_check(hipEventElapsedTime(&ms, eager_ev[0], eager_ev[1]), "cycle time");
+        eager_launch_bound = eager_host_ms >= 0.8 * double(ms);
+        eager_pending = false;
+      }
+      const bool capture_now = graphs && graph_set != next && next == eager_set && eager_launch_bound;
       if (graphs && graph_set != next && !capture_now) {
-        eager_set = next;
-        body();
+        if (next != eager_set) {
+          if (!eager_ev[0]) {
+            hip_check(hipEventCreate(&eager_ev[0]), "event");
+            hip_check(hipEventCreate(&eager_ev[1]), "event");
+          }
+          eager_set = next;
+          const auto t0 = std::chrono::steady_clock::now();
+          hip_check(hipEventRecord(eager_ev[0], user), "event");
+          body();
+          hip_check(hipEventRecord(eager_ev[1], user), "event");
+          eager_host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+          eager_pending = true;
+        } else {
+          body();
+        }
       } else if (graphs) {
         if (capture_now) {
           // the active set changed: record the cycle of the new set

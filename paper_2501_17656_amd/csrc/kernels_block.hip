@@ -417,22 +417,37 @@ __global__ __launch_bounds__(256) void k_tgemm_eval_group(TevalGroup G) {
       StageEval<Tv, KIND, DERIV>{M.brow, M.bcol, M.chunk_start, M.chunk_n, M.pts, M.dim, M.kp, M.ps}, M.rslot);
 }
 
+// v += p[t * stride] for t = a .. b - 1, added in that order, with eight
+// loads in flight (a row can have hundreds of column contributions).
+template <typename Tv>
+__device__ __forceinline__ void sum_run(Tv& v, const Tv* __restrict__ p, int64_t stride, int a, int b) {
+  int t = a;
+  for (; t + 8 <= b; t += 8) {
+    Tv x[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = p[int64_t(t + k) * stride];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v += x[k];
+  }
+  for (; t < b; ++t) v += p[int64_t(t) * stride];
+}
+
 // out[row] (rr x 16) = the row-pass partials [rtp[row], rtp[row+1]) plus the
 // column-pass partials [ctp[row], ctp[row+1]) (after the nrt row-pass ones),
-// summed in that order, for rows row0 .. row0 + nrows - 1.
+// summed in that order, for rows row0 .. row0 + nrows - 1.  Workgroup
+// (row, y) sums elements y * NT .. of its row, one element per thread.
 template <typename Tv>
 __global__ __launch_bounds__(NT) void k_reduce16(int row0, const int* __restrict__ rtp,
                                                  const int* __restrict__ ctp, int nrt, int rr,
                                                  const Tv* __restrict__ partial, Tv* __restrict__ out) {
   const int row = row0 + blockIdx.x;
+  const int e = blockIdx.y * NT + threadIdx.x;
+  if (e >= rr * NR) return;
   const int64_t stride = int64_t(rr) * NR;
-  const int t0 = rtp[row], t1 = rtp[row + 1], c0 = ctp[row], c1 = ctp[row + 1];
-  for (int e = threadIdx.x; e < rr * NR; e += NT) {
-    Tv v = Tv(0);
-    for (int t = t0; t < t1; ++t) v += partial[t * stride + e];
-    for (int t = c0; t < c1; ++t) v += partial[(nrt + t) * stride + e];
-    out[row * stride + e] = v;
-  }
+  Tv v = Tv(0);
+  sum_run(v, partial + e, stride, rtp[row], rtp[row + 1]);
+  sum_run(v, partial + e, stride, nrt + ctp[row], nrt + ctp[row + 1]);
+  out[row * stride + e] = v;
 }
 
 // Tree-order FP64 block from user order (columns >= nrhs zero), and back.
@@ -861,11 +876,12 @@ void launch_tgemm_eval_group(hipStream_t st, int p, const std::vector<GroupEval>
 
 void launch_reduce16(H2& h, int p, const TileSet& ts, int rr, const void* partial, void* out) {
   if (ts.nrows == 0) return;
+  const dim3 grid(ts.nrows, (rr * NR + NT - 1) / NT);
   if (p == P64)
-    hipLaunchKernelGGL(k_reduce16<double>, dim3(ts.nrows), dim3(NT), 0, h.stream, ts.row0, ts.rtp, ts.ctp,
+    hipLaunchKernelGGL(k_reduce16<double>, grid, dim3(NT), 0, h.stream, ts.row0, ts.rtp, ts.ctp,
                        ts.nrt, rr, static_cast<const double*>(partial), static_cast<double*>(out));
   else
-    hipLaunchKernelGGL(k_reduce16<float>, dim3(ts.nrows), dim3(NT), 0, h.stream, ts.row0, ts.rtp, ts.ctp,
+    hipLaunchKernelGGL(k_reduce16<float>, grid, dim3(NT), 0, h.stream, ts.row0, ts.rtp, ts.ctp,
                        ts.nrt, rr, static_cast<const float*>(partial), static_cast<float*>(out));
   check_launch("reduce16");
 }
