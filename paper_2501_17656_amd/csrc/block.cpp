@@ -1231,14 +1231,15 @@ h2mg_status solve_group(int nprob, H2* const* hs, const int* nrhs, const double*
       // A new active set (a member converged or failed) runs its first cycle
       // kernel by kernel, timed on the host (enqueue) and on the GPU.  When
       // the set repeats, its cycle is captured only if that cycle was
-      // launch-bound (enqueueing took at least 80% of the GPU time): a graph
-      // then saves the launches, while for GPU-bound cycles capturing and
-      // instantiating a graph of every member's launches costs more than it
-      // saves.
+      // clearly launch-bound (enqueueing took at least twice the GPU time):
+      // a graph saves only the enqueue time beyond the GPU time, while
+      // capturing and instantiating a graph of every member's launches costs
+      // several cycles' worth of enqueueing (measured: with an 80% threshold
+      // four batched problems took 10.8 s against 6.6 s kernel by kernel).
       if (eager_pending) {
         float ms = 0.0f;
         hip_check(hipEventElapsedTime(&ms, eager_ev[0], eager_ev[1]), "cycle time");
-        eager_launch_bound = eager_host_ms >= 0.8 * double(ms);
+        eager_launch_bound = eager_host_ms >= 2.0 * double(ms);
         eager_pending = false;
       }
       const bool capture_now = graphs && graph_set != next && next == eager_set && eager_launch_bound;
