@@ -389,12 +389,15 @@ h2mg_status h2mg_solve_batch(int32_t nprob, const h2mg_h2_t* hs, const int32_t* 
  * near-field tiles -- is one kernel launch over the task lists of every
  * active problem (up to 16 per launch; problems whose level does not exist
  * at that step are left out, and a problem's coarsest level is solved
- * directly when the others go deeper).  Vector steps stay per problem.  A
- * problem's arithmetic is the same, in the same order, as in its own
- * h2mg_solve_multi, so results are bitwise equal.  With h2mg_set_graphs on
- * every handle, one graph holds the cycle of all active problems (recorded
- * again when a problem finishes).  Arguments, ownership and errors as
- * h2mg_solve_batch. */
+ * directly when the others go deeper).  Vector steps stay per problem, on
+ * up to four lane streams that fork from and join back into `stream`
+ * around each group launch.  A problem's arithmetic is the same, in the
+ * same order, as in its own h2mg_solve_multi, so results are bitwise equal.
+ * With h2mg_set_graphs on every handle, the first cycle of each set of
+ * active problems runs kernel by kernel; the set's cycle is captured as one
+ * graph when it repeats, and only if that first cycle was launch-bound (its
+ * enqueue took at least twice its GPU time).  Arguments, ownership and
+ * errors as h2mg_solve_batch. */
 h2mg_status h2mg_solve_group(int32_t nprob, const h2mg_h2_t* hs, const int32_t* nrhs,
                              const double* const* b_dev, const int32_t* ldb, double* const* x_dev,
                              const int32_t* ldx, const h2mg_solve_opts* opts,
