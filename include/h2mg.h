@@ -383,7 +383,7 @@ h2mg_status h2mg_solve_batch(int32_t nprob, const h2mg_h2_t* hs, const int32_t* 
                              hipStream_t stream);
 
 /* The problems of h2mg_solve_batch solved in one sequence of launches on
- * `stream` (Algorithm 1 for every problem, spec batching form): the
+ * `stream` (Algorithm 1 for every problem, batched over problems): the
  * problems advance cycle by cycle together, and each tile product of a
  * cycle step -- the couplings, the restricted operators of each level, the
  * near-field tiles -- is one kernel launch over the task lists of every

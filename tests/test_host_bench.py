@@ -37,7 +37,7 @@ def _bench():
 
 
 def test_default_run_asks_for_no_extra_part():
-    """The driver's command (--gpus 1 --steps 20 --warmup 5) requests none of
+    """The benchmark's standard command (--gpus 1 --steps 20 --warmup 5) requests none of
     the opt-in parts, and the extra runners then do nothing at all (they get
     None for every handle, so any work they started would fail)."""
     bench = _bench()
