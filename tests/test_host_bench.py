@@ -137,3 +137,29 @@ def test_galerkin_flop_count_matches_the_oracle_partition():
     assert got["leaf_blocks"] == len(near_l)
     assert got["pi_leaf"] == float(np.sum(2.0 * r * ns * nt + 2.0 * r * r * ns))
     assert got["upper_blocks"] == upper and got["pi_upper"] == upper * 12.0 * r ** 3
+
+
+def test_profiled_traffic_is_tied_to_the_profiled_kernel_source(tmp_path, monkeypatch):
+    """The roofline's traffic comes from a counter profile only while the
+    block-GEMV sources hash to the profiled ones: it scales the profile's
+    HBM / algorithmic ratio to the run's bytes, and is None for another
+    source or a kernel kind the profile does not list."""
+    import hashlib
+    import shutil
+    bench = _bench()
+    csrc = tmp_path / "paper_2501_17656_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    h = hashlib.sha256()
+    for f in ("kernels_apply.hip", "device_common.h"):
+        shutil.copy(os.path.join(ROOT, "paper_2501_17656_amd", "csrc", f), csrc / f)
+        h.update((csrc / f).read_bytes())
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "gemv_counters_test.md").write_text(
+        "    traffic gemv_fp32 src=%s per_launch_bytes=1.020000e+10 alg_per_launch_bytes=1.000000e+10\n"
+        % h.hexdigest()[:16])
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.profiled_traffic("gemv_fp32", 5.0e9) == round(5.0e9 * 1.02)
+    assert bench.profiled_traffic("gemv_fp64", 5.0e9) is None
+    with open(csrc / "kernels_apply.hip", "a") as f:
+        f.write("\n// changed\n")
+    assert bench.profiled_traffic("gemv_fp32", 5.0e9) is None
